@@ -1,0 +1,235 @@
+/*
+ * comet.h -- C ABI of the MI355X (gfx950) permuted tensor-contraction library.
+ *
+ * The library computes the binary tensor contraction of Section 2 of the COMET
+ * paper (arXiv 2102.06827): the output C over its free (external) indices is
+ * the sum, over the summation indices shared by A and B, of A * B.  As in the
+ * ta.tc operation of Section 5 the product is scaled by alpha; the "=", "+="
+ * and "-=" forms of the operation grammar (Fig. 2) map to beta = 0, beta = 1,
+ * and beta = 1 with alpha negated:
+ *
+ *     C[free] = alpha * sum_{summation} A[...] * B[...]  +  beta * C[free]
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * spec     "C=A*B" label strings, e.g. "abij=acik*cbkj".  One ASCII letter per
+ *          tensor dimension, blanks ignored, rank <= COMET_MAX_RANK per tensor
+ *          (rank 0 is allowed for C: a full contraction to a scalar).  Every
+ *          label must appear in exactly two of C, A, B (free labels in C and
+ *          one input; summation labels in A and B).  A label in all three
+ *          tensors returns COMET_ERR_UNSUPPORTED; a label in one tensor only,
+ *          or repeated inside one tensor, returns COMET_ERR_INVALID_SPEC.
+ * extents  one int64 per distinct label, in order of first appearance when
+ *          scanning C's labels, then A's, then B's.  Negative extents and
+ *          tensor sizes that overflow int64 return COMET_ERR_INVALID_SHAPE.
+ *          Zero extents are allowed (empty output: nothing happens; empty
+ *          summation: C = beta * C).
+ * strides  element strides per tensor, in the order of that tensor's labels,
+ *          or NULL for dense row-major (the storage the paper's cost model
+ *          assumes, Section 6).  Negative strides return
+ *          COMET_ERR_INVALID_STRIDE.  Stride 0 (broadcast) is allowed for A
+ *          and B.  C must not overlap itself: stride 0 on a C dimension of
+ *          extent > 1, or dimensions that interleave, return
+ *          COMET_ERR_INVALID_STRIDE.
+ * pointers A, B, C and workspaces are device pointers owned by the caller;
+ *          the library never frees them and keeps none after the call
+ *          returns (except inside a graph the caller captured).  C must not
+ *          alias A or B (the same base pointer returns COMET_ERR_UNSUPPORTED).
+ * stream   a hipStream_t passed as void*; NULL is the null stream.  All work
+ *          is enqueued on it; calls return after the enqueue.
+ * beta     beta == 0 means C is not read (NaN/Inf in C do not propagate);
+ *          alpha == 0 means A and B are not read.  For FP32 storage alpha and
+ *          beta are rounded to float.
+ * errors   every argument is validated on the host before anything is
+ *          enqueued; on error nothing is enqueued and C is untouched.
+ *          comet_last_error() gives a thread-local message for the last
+ *          failing call of the calling thread.  A HIP launch failure returns
+ *          COMET_ERR_HIP; a device fault surfaces at the caller's next sync.
+ * determinism  the same plan and inputs give bit-identical outputs: no
+ *          atomics in any reduction, no split of the summation across
+ *          workgroups.
+ */
+#ifndef COMET_H
+#define COMET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COMET_MAX_RANK 12
+#define COMET_VERSION_STRING "0.1.0"
+
+typedef enum {
+  COMET_OK = 0,
+  COMET_ERR_INVALID_SPEC = 1,
+  COMET_ERR_INVALID_SHAPE = 2,
+  COMET_ERR_INVALID_STRIDE = 3,
+  COMET_ERR_NULL_POINTER = 4,
+  COMET_ERR_UNSUPPORTED = 5,
+  COMET_ERR_WORKSPACE = 6,
+  COMET_ERR_HIP = 7,
+  COMET_ERR_INTERNAL = 8
+} comet_status_t;
+
+/* Storage type of A, B and C. */
+typedef enum { COMET_F64 = 0, COMET_F32 = 1 } comet_dtype_t;
+
+/* Arithmetic used for the products.
+ *   DEFAULT      the matrix-core type of the storage type (F64 -> F64, F32 -> F32).
+ *   F64          FP64 MFMA, FP64 accumulation (FP32 inputs are widened exactly).
+ *   F32          FP32 MFMA, FP32 accumulation (FP64 inputs are rounded to FP32).
+ *   SPLIT_BF16   each row of A and column of B is scaled by a power of two to
+ *                its largest magnitude over the summation labels and cut into
+ *                S 8-bit integer slices held exactly in bfloat16 (error-free
+ *                splitting in the manner of Ozaki et al. 2012); slice pairs
+ *                with p + q < S run on BF16 MFMA with FP32 accumulation, the
+ *                leading partial sums kept exact over short chunks and folded
+ *                into FP64.  S comes from comet_set_split_slices (default 5).
+ *   SPLIT_BF16X3 x = b0 + b1 + b2 with b_i = bf16 of the remainder (Henry,
+ *                Tang and Heinecke 2019); the six products b_p*c_q with
+ *                p + q <= 2 on BF16 MFMA, one FP32 accumulator.
+ *   SPLIT_FP16X2 x = h0 + h1 * 2^-11, h0 = fp16(x), h1 = fp16((x - h0) * 2^11),
+ *                rows scaled by a power of two into FP16 range (Ootomo and
+ *                Yokota 2022); three FP16 MFMA products, FP32 accumulation.
+ * Split modes accumulate the final result in FP64 before the alpha/beta
+ * epilogue and need a workspace for the slices. */
+typedef enum {
+  COMET_COMPUTE_DEFAULT = 0,
+  COMET_COMPUTE_F64 = 1,
+  COMET_COMPUTE_F32 = 2,
+  COMET_COMPUTE_SPLIT_BF16 = 3,
+  COMET_COMPUTE_SPLIT_BF16X3 = 4,
+  COMET_COMPUTE_SPLIT_FP16X2 = 5
+} comet_compute_t;
+
+/* Which lowering a plan uses.
+ *   AUTO  the planner's choice (the fused gather path unless the autotune
+ *         cache recorded TTGT as faster for this problem class).
+ *   GETT  operands are gathered through per-label offset tables straight into
+ *         on-chip tiles; no transposed copies are made.
+ *   TTGT  transpose-transpose-GEMM-transpose (Section 2; Section 6 "TTGT"):
+ *         A and B are permuted into matrices, multiplied, and the product is
+ *         permuted into C, with the permutation picked by the cost model of
+ *         Section 6 ("Optimal permutation for TTGT"). */
+typedef enum { COMET_PATH_AUTO = 0, COMET_PATH_GETT = 1, COMET_PATH_TTGT = 2 } comet_path_t;
+
+typedef struct comet_plan_s *comet_plan_t;
+typedef struct comet_batch_s *comet_batch_t;
+
+/* One problem of a batch: the same meaning as the comet_contract arguments. */
+typedef struct {
+  const char *spec;
+  const int64_t *extents;
+  const int64_t *strides_A;   /* NULL = dense row-major */
+  const int64_t *strides_B;
+  const int64_t *strides_C;
+  double alpha;
+  double beta;
+  const void *A;
+  const void *B;
+  void *C;
+} comet_problem_t;
+
+/*
+ * comet_contract -- one contraction, C = alpha * contract(A, B) + beta * C
+ * (Section 2 equations; ta.tc of Section 5).  Convenience call: plans on
+ * first use (cached per spec, extents, strides, dtype, compute, device) and
+ * uses a library-owned, stream-ordered workspace.  Returns
+ * COMET_ERR_UNSUPPORTED if the stream is being captured (use the plan API
+ * there).
+ */
+comet_status_t comet_contract(const char *spec, const int64_t *extents,
+                              comet_dtype_t dtype, comet_compute_t compute,
+                              double alpha, const void *A, const int64_t *strides_A,
+                              const void *B, const int64_t *strides_B,
+                              double beta, void *C, const int64_t *strides_C,
+                              void *stream);
+
+/*
+ * Plan API.  comet_plan_create parses and validates the problem, fuses labels
+ * (consecutive indices merged as in the TTGT flattening of Section 2), builds
+ * the per-label offset tables, picks the lowering and the tile shape, and
+ * uploads the tables to the current device (so it allocates and is not
+ * capturable).  comet_plan_execute enqueues the contraction with a caller
+ * workspace of at least comet_plan_workspace_size bytes (256-byte aligned;
+ * may be NULL when the size is 0) and is capturable into a HIP graph.
+ * Pointer arguments of execute must satisfy the alignment the plan was
+ * made for; misaligned pointers take the scalar gather, never an error.
+ */
+comet_status_t comet_plan_create(comet_plan_t *plan, const char *spec, const int64_t *extents,
+                                 const int64_t *strides_A, const int64_t *strides_B,
+                                 const int64_t *strides_C, comet_dtype_t dtype,
+                                 comet_compute_t compute);
+comet_status_t comet_plan_create_ex(comet_plan_t *plan, const char *spec, const int64_t *extents,
+                                    const int64_t *strides_A, const int64_t *strides_B,
+                                    const int64_t *strides_C, comet_dtype_t dtype,
+                                    comet_compute_t compute, comet_path_t path);
+comet_status_t comet_plan_workspace_size(comet_plan_t plan, size_t *bytes);
+comet_status_t comet_plan_execute(comet_plan_t plan, double alpha, const void *A, const void *B,
+                                  double beta, void *C, void *workspace, size_t ws_bytes,
+                                  void *stream);
+comet_status_t comet_plan_destroy(comet_plan_t plan);
+/* Writes a JSON description of the plan (path, label classes and fusion,
+ * layouts, tile shape, TTGT permutations and cost) into buf; host only. */
+comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len);
+
+/*
+ * comet_analyze -- host-only planning without a device: validates exactly as
+ * comet_plan_create does and writes the same JSON as comet_plan_describe.
+ * Allocates no device memory and launches nothing.
+ */
+comet_status_t comet_analyze(const char *spec, const int64_t *extents,
+                             const int64_t *strides_A, const int64_t *strides_B,
+                             const int64_t *strides_C, comet_dtype_t dtype,
+                             comet_compute_t compute, comet_path_t path,
+                             char *buf, size_t len);
+
+/*
+ * Batch API: n independent contractions in ONE persistent kernel launch.
+ * Workgroups take (problem, tile) items from a device work list ordered by
+ * decreasing cost, so many small, uneven problems fill the GPU together.
+ * All problems share dtype and compute; compute must be DEFAULT, F64 or F32.
+ * comet_batch_create plans every problem and uploads the work list and
+ * offset tables (not capturable); comet_batch_execute is capturable.
+ */
+comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_problem_t *problems,
+                                  comet_dtype_t dtype, comet_compute_t compute);
+comet_status_t comet_batch_workspace_size(comet_batch_t batch, size_t *bytes);
+comet_status_t comet_batch_execute(comet_batch_t batch, void *workspace, size_t ws_bytes,
+                                   void *stream);
+comet_status_t comet_batch_destroy(comet_batch_t batch);
+
+/*
+ * comet_permute -- the ta.copy operation of Section 5 (out = alpha * in with
+ * the labels permuted, Section 4 "labeled tensors"), plus beta * out:
+ * spec "ji=ij" (same labels on both sides).  Tiled through LDS so reads and
+ * writes are both coalesced (Section 6 "Transpose optimization").
+ */
+comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dtype_t dtype,
+                             double alpha, const void *in, const int64_t *strides_in,
+                             double beta, void *out, const int64_t *strides_out,
+                             void *stream);
+
+/*
+ * Autotuner.  mode 0: off (heuristic tiles); 1: use the cache at cache_path
+ * and time candidates for problem classes it does not hold, appending them;
+ * 2: re-time everything.  A corrupt cache file is ignored and rewritten.
+ * cache_path NULL uses $COMET_TUNE_CACHE or ~/.cache/comet_tune.json.
+ */
+comet_status_t comet_autotune(const char *cache_path, int mode);
+
+/* Number of slices S used by COMET_COMPUTE_SPLIT_BF16 for plans created
+ * afterwards; 3 <= S <= 6 (COMET_ERR_UNSUPPORTED otherwise). */
+comet_status_t comet_set_split_slices(int S);
+
+const char *comet_last_error(void);
+const char *comet_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COMET_H */

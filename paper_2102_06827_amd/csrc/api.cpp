@@ -1,0 +1,579 @@
+// api.cpp -- the C ABI (include/comet.h): validation, plans, workspaces and
+// dispatch to the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "comet.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "split.hpp"
+
+using namespace comet;
+
+namespace {
+
+thread_local std::string g_last_error;
+int g_split_slices = 5;
+std::mutex g_mu;
+
+comet_status_t fail(comet_status_t code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+comet_status_t fail(const Status &st) { return fail(st.code, st.msg); }
+
+comet_status_t hip_fail(hipError_t e, const char *what) {
+  return fail(COMET_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)              \
+  do {                                   \
+    hipError_t _e = (expr);              \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool tables_vec_ok(const std::vector<int64_t> &offR, const std::vector<int64_t> &offK, int layout, int runR,
+                   int runK, int VEC) {
+  if ((layout == 0 ? runK : runR) < VEC) return false;
+  for (size_t r = 0; r < offR.size(); ++r)
+    if ((layout == 0 || r % VEC == 0) && offR[r] % VEC) return false;
+  for (size_t k = 0; k < offK.size(); ++k)
+    if ((layout == 1 || k % VEC == 0) && offK[k] % VEC) return false;
+  return true;
+}
+
+std::vector<int64_t> dense_strides(const std::vector<int64_t> &ext) {
+  std::vector<int64_t> s(ext.size());
+  int64_t x = 1;
+  for (int p = (int)ext.size() - 1; p >= 0; --p) {
+    s[p] = x;
+    x *= ext[p];
+  }
+  return s;
+}
+
+}  // namespace
+
+struct comet_plan_s {
+  Analysis an;
+  int device = 0;
+  void *dtables = nullptr;     // the six offset tables, one device allocation
+  GettTables t{};
+  bool vecA_tables = false, vecB_tables = false;
+  size_t ws_bytes = 0;
+  // split modes
+  SplitPlan split;
+  // TTGT
+  std::unique_ptr<comet_plan_s> gemm;
+  PermuteLaunch permA{}, permB{}, permC{};
+  size_t wsA = 0, wsB = 0, wsC = 0;   // byte offsets of A_p, B_p, C_p in the workspace
+
+  ~comet_plan_s() {
+    if (dtables) (void)hipFree(dtables);
+  }
+};
+
+namespace {
+
+comet_status_t upload_tables(comet_plan_s *p) {
+  const Analysis &an = p->an;
+  const std::vector<int64_t> *tabs[6] = {&an.offAm, &an.offAk, &an.offBk, &an.offBn, &an.offCm, &an.offCn};
+  size_t off[6], total = 0;
+  for (int i = 0; i < 6; ++i) {
+    off[i] = total;
+    total += align256(std::max<size_t>(tabs[i]->size(), 1) * sizeof(int64_t));
+  }
+  HIP_TRY(hipMalloc(&p->dtables, total), "hipMalloc(offset tables)");
+  std::vector<char> host(total, 0);
+  for (int i = 0; i < 6; ++i)
+    if (!tabs[i]->empty()) std::memcpy(host.data() + off[i], tabs[i]->data(), tabs[i]->size() * sizeof(int64_t));
+  HIP_TRY(hipMemcpy(p->dtables, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(offset tables)");
+  char *b = static_cast<char *>(p->dtables);
+  p->t.offAm = reinterpret_cast<const int64_t *>(b + off[0]);
+  p->t.offAk = reinterpret_cast<const int64_t *>(b + off[1]);
+  p->t.offBk = reinterpret_cast<const int64_t *>(b + off[2]);
+  p->t.offBn = reinterpret_cast<const int64_t *>(b + off[3]);
+  p->t.offCm = reinterpret_cast<const int64_t *>(b + off[4]);
+  p->t.offCn = reinterpret_cast<const int64_t *>(b + off[5]);
+  return COMET_OK;
+}
+
+int pick_tile(const Analysis &an) {
+  // large problems: 128 x 128 tiles; otherwise 64 x 64 so more workgroups exist
+  const int64_t big_tiles = ((an.m + 127) / 128) * ((an.n + 127) / 128);
+  return big_tiles >= 256 ? 0 : 1;
+}
+
+comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
+                          const int64_t *sA, const int64_t *sB, const int64_t *sC, comet_dtype_t dtype,
+                          comet_compute_t compute, comet_path_t path);
+
+comet_status_t build_ttgt(comet_plan_s *p) {
+  Analysis &an = p->an;
+  const char *forced = std::getenv("COMET_TTGT_ORDER");
+  if (forced && *forced) {
+    std::string s(forced);
+    size_t a = s.find('|'), b = s.find('|', a == std::string::npos ? 0 : a + 1);
+    if (a == std::string::npos || b == std::string::npos)
+      return fail(COMET_ERR_INVALID_SPEC, "COMET_TTGT_ORDER must read Aorder|Border|Corder");
+    TTGTChoice c;
+    c.a_order = s.substr(0, a);
+    c.b_order = s.substr(a + 1, b - a - 1);
+    c.c_order = s.substr(b + 1);
+    auto same_set = [](std::string x, std::string y) {
+      std::sort(x.begin(), x.end());
+      std::sort(y.begin(), y.end());
+      return x == y;
+    };
+    if (!same_set(c.a_order, an.spec_a) || !same_set(c.b_order, an.spec_b) || !same_set(c.c_order, an.spec_c))
+      return fail(COMET_ERR_INVALID_SPEC, "COMET_TTGT_ORDER is not a relabeling of the spec");
+    c.a_copy = c.b_copy = c.c_copy = true;
+    an.ttgt = c;
+  }
+  const TTGTChoice &tc = an.ttgt;
+  const size_t es = elem_size(an.dtype);
+  auto ext_of = [&](char ch) {
+    return an.extents[std::find(an.labels.begin(), an.labels.end(), ch) - an.labels.begin()];
+  };
+  auto exts = [&](const std::string &s) {
+    std::vector<int64_t> e;
+    for (char ch : s) e.push_back(ext_of(ch));
+    return e;
+  };
+  auto count = [](const std::vector<int64_t> &e) {
+    int64_t n = 1;
+    for (int64_t x : e) n *= x;
+    return n;
+  };
+  std::vector<int64_t> eA = exts(tc.a_order), eB = exts(tc.b_order), eC = exts(tc.c_order);
+  std::vector<int64_t> dA = dense_strides(eA), dB = dense_strides(eB), dC = dense_strides(eC);
+  size_t off = 0;
+  auto fill_perm = [&](PermuteLaunch &pl, const PermuteDesc &d) {
+    pl = PermuteLaunch{};
+    pl.ndim = (int)d.ext.size();
+    for (int i = 0; i < pl.ndim; ++i) {
+      pl.ext[i] = d.ext[i];
+      pl.s_in[i] = d.s_in[i];
+      pl.s_out[i] = d.s_out[i];
+    }
+    pl.dtype = an.dtype == COMET_F64 ? 0 : 1;
+  };
+  if (tc.a_copy) {
+    p->wsA = off;
+    off += align256(count(eA) * es);
+    fill_perm(p->permA, make_permute(tc.a_order, dA, an.spec_a, an.strA, eA));
+  }
+  if (tc.b_copy) {
+    p->wsB = off;
+    off += align256(count(eB) * es);
+    fill_perm(p->permB, make_permute(tc.b_order, dB, an.spec_b, an.strB, eB));
+  }
+  if (tc.c_copy) {
+    p->wsC = off;
+    off += align256(count(eC) * es);
+    fill_perm(p->permC, make_permute(an.spec_c, an.strC, tc.c_order, dC, exts(an.spec_c)));
+  }
+  if (p->permA.ndim > kPermMaxDims || p->permB.ndim > kPermMaxDims || p->permC.ndim > kPermMaxDims)
+    return fail(COMET_ERR_UNSUPPORTED, "too many dims for the permute kernel");
+  // the GEMM stage: a contraction of the permuted operands, whose gather
+  // degenerates to plain row- or column-major matrix access
+  std::string gspec = tc.c_order + "=" + tc.a_order + "*" + tc.b_order;
+  std::vector<int64_t> gext;
+  std::string seen;
+  for (const std::string *s : {&tc.c_order, &tc.a_order, &tc.b_order})
+    for (char ch : *s)
+      if (seen.find(ch) == std::string::npos) {
+        seen += ch;
+        gext.push_back(ext_of(ch));
+      }
+  auto reorder = [&](const std::string &to, const std::string &from, const std::vector<int64_t> &s) {
+    std::vector<int64_t> r;
+    for (char ch : to) r.push_back(s[from.find(ch)]);
+    return r;
+  };
+  std::vector<int64_t> gsA = tc.a_copy ? dA : reorder(tc.a_order, an.spec_a, an.strA);
+  std::vector<int64_t> gsB = tc.b_copy ? dB : reorder(tc.b_order, an.spec_b, an.strB);
+  std::vector<int64_t> gsC = tc.c_copy ? dC : reorder(tc.c_order, an.spec_c, an.strC);
+  comet_status_t rc = build_plan(p->gemm, gspec.c_str(), gext.data(), gsA.data(), gsB.data(), gsC.data(), an.dtype,
+                                 an.compute, COMET_PATH_GETT);
+  if (rc != COMET_OK) return rc;
+  p->ws_bytes = off;
+  return COMET_OK;
+}
+
+comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
+                          const int64_t *sA, const int64_t *sB, const int64_t *sC, comet_dtype_t dtype,
+                          comet_compute_t compute, comet_path_t path) {
+  std::unique_ptr<comet_plan_s> p(new comet_plan_s());
+  Status st = analyze(spec, extents, sA, sB, sC, dtype, compute, path, g_split_slices, p->an);
+  if (!st.ok()) return fail(st);
+  Analysis &an = p->an;
+  HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
+  an.tile = pick_tile(an);
+  if (an.path == COMET_PATH_TTGT && !an.empty_out && !an.empty_sum) {
+    comet_status_t rc = build_ttgt(p.get());
+    if (rc != COMET_OK) return rc;
+  }
+  comet_status_t rc = upload_tables(p.get());
+  if (rc != COMET_OK) return rc;
+  const int VEC = an.dtype == COMET_F64 ? 2 : 4;
+  p->vecA_tables = tables_vec_ok(an.offAm, an.offAk, an.layoutA, an.runAm, an.runAk, VEC);
+  p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC);
+  bool split = an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
+               an.compute == COMET_COMPUTE_SPLIT_FP16X2;
+  if (split && !an.empty_out && !an.empty_sum) {
+    Status s2 = split_prepare(an, p->split);
+    if (!s2.ok()) return fail(s2);
+    p->ws_bytes = p->split.ws_bytes;
+  }
+  out = std::move(p);
+  return COMET_OK;
+}
+
+comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
+                        hipStream_t s) {
+  const Analysis &an = p->an;
+  GettLaunch g{};
+  g.A = an.swapped ? B : A;
+  g.B = an.swapped ? A : B;
+  g.C = C;
+  g.t = p->t;
+  g.M = an.m;
+  g.N = an.n;
+  g.K = an.k;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.dtype = an.dtype == COMET_F64 ? 0 : 1;
+  g.compute = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  g.layoutA = an.layoutA;
+  g.layoutB = an.layoutB;
+  g.vecA = p->vecA_tables && (reinterpret_cast<uintptr_t>(g.A) % 16 == 0);
+  g.vecB = p->vecB_tables && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0);
+  g.tile = an.tile;
+  HIP_TRY(launch_gett(g, s), "gett launch");
+  return COMET_OK;
+}
+
+comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
+                       void *ws, size_t ws_bytes, hipStream_t s) {
+  const Analysis &an = p->an;
+  if (an.empty_out) return COMET_OK;
+  if (!C) return fail(COMET_ERR_NULL_POINTER, "C is NULL");
+  if (alpha != 0.0 && !an.empty_sum && (!A || !B)) return fail(COMET_ERR_NULL_POINTER, "A or B is NULL");
+  if (alpha != 0.0 && !an.empty_sum && (C == A || C == B))
+    return fail(COMET_ERR_UNSUPPORTED, "C aliases an input");
+  if (an.dtype == COMET_F32) {
+    alpha = double(float(alpha));
+    beta = double(float(beta));
+  }
+  if (alpha == 0.0 || an.empty_sum) {
+    HIP_TRY(launch_scale(C, an.dtype == COMET_F64 ? 0 : 1, p->t.offCm, p->t.offCn, an.m, an.n, beta, s), "scale");
+    return COMET_OK;
+  }
+  if (p->ws_bytes > 0 && (!ws || ws_bytes < p->ws_bytes))
+    return fail(COMET_ERR_WORKSPACE, "workspace smaller than comet_plan_workspace_size");
+  if (an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
+      an.compute == COMET_COMPUTE_SPLIT_FP16X2) {
+    const void *Ak = an.swapped ? B : A, *Bk = an.swapped ? A : B;
+    HIP_TRY(split_execute(an, p->split, p->t, alpha, Ak, Bk, beta, C, ws, s), "split launch");
+    return COMET_OK;
+  }
+  if (an.path == COMET_PATH_TTGT) {
+    const TTGTChoice &tc = an.ttgt;
+    char *w = static_cast<char *>(ws);
+    const void *Ap = A, *Bp = B;
+    if (tc.a_copy) {
+      PermuteLaunch pl = p->permA;
+      pl.in = A;
+      pl.out = w + p->wsA;
+      pl.alpha = 1.0;
+      pl.beta = 0.0;
+      HIP_TRY(launch_permute(pl, s), "permute A");
+      Ap = pl.out;
+    }
+    if (tc.b_copy) {
+      PermuteLaunch pl = p->permB;
+      pl.in = B;
+      pl.out = w + p->wsB;
+      pl.alpha = 1.0;
+      pl.beta = 0.0;
+      HIP_TRY(launch_permute(pl, s), "permute B");
+      Bp = pl.out;
+    }
+    if (tc.c_copy) {
+      comet_status_t rc = run_gett(p->gemm.get(), alpha, Ap, Bp, 0.0, w + p->wsC, s);
+      if (rc != COMET_OK) return rc;
+      PermuteLaunch pl = p->permC;
+      pl.in = w + p->wsC;
+      pl.out = C;
+      pl.alpha = 1.0;
+      pl.beta = beta;
+      HIP_TRY(launch_permute(pl, s), "permute C");
+      return COMET_OK;
+    }
+    return run_gett(p->gemm.get(), alpha, Ap, Bp, beta, C, s);
+  }
+  return run_gett(p, alpha, A, B, beta, C, s);
+}
+
+// ---- convenience-call state: plan cache and per-device workspace ----------
+
+struct DeviceWorkspace {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+std::map<std::string, std::unique_ptr<comet_plan_s>> g_cache;
+std::map<int, DeviceWorkspace> g_ws;
+
+std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const int64_t *sA, size_t ra,
+                      const int64_t *sB, size_t rb, const int64_t *sC, size_t rc, int dtype, int compute, int dev) {
+  std::string k(spec);
+  auto add = [&](const int64_t *v, size_t n) {
+    k += "|";
+    if (!v) {
+      k += "-";
+      return;
+    }
+    for (size_t i = 0; i < n; ++i) k += std::to_string(v[i]) + ",";
+  };
+  add(ext, nlab);
+  add(sA, ra);
+  add(sB, rb);
+  add(sC, rc);
+  k += "|" + std::to_string(dtype) + "|" + std::to_string(compute) + "|" + std::to_string(dev) + "|" +
+       std::to_string(g_split_slices);
+  const char *env = std::getenv("COMET_FORCE_PATH");
+  k += "|";
+  if (env) k += env;
+  const char *ord = std::getenv("COMET_TTGT_ORDER");
+  k += "|";
+  if (ord) k += ord;
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *comet_version(void) { return COMET_VERSION_STRING; }
+
+const char *comet_last_error(void) { return g_last_error.c_str(); }
+
+comet_status_t comet_set_split_slices(int S) {
+  if (S < 3 || S > 6) return fail(COMET_ERR_UNSUPPORTED, "split slices must be within 3..6");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_split_slices = S;
+  return COMET_OK;
+}
+
+comet_status_t comet_analyze(const char *spec, const int64_t *extents, const int64_t *strides_A,
+                             const int64_t *strides_B, const int64_t *strides_C, comet_dtype_t dtype,
+                             comet_compute_t compute, comet_path_t path, char *buf, size_t len) {
+  Analysis an;
+  Status st = analyze(spec, extents, strides_A, strides_B, strides_C, dtype, compute, path, g_split_slices, an);
+  if (!st.ok()) return fail(st);
+  std::string js = describe_json(an);
+  if (buf && len) {
+    std::strncpy(buf, js.c_str(), len - 1);
+    buf[len - 1] = 0;
+    if (js.size() + 1 > len) return fail(COMET_ERR_WORKSPACE, "describe buffer too small");
+  }
+  return COMET_OK;
+}
+
+comet_status_t comet_plan_create_ex(comet_plan_t *plan, const char *spec, const int64_t *extents,
+                                    const int64_t *strides_A, const int64_t *strides_B, const int64_t *strides_C,
+                                    comet_dtype_t dtype, comet_compute_t compute, comet_path_t path) {
+  if (!plan) return fail(COMET_ERR_NULL_POINTER, "plan is NULL");
+  std::unique_ptr<comet_plan_s> p;
+  comet_status_t rc = build_plan(p, spec, extents, strides_A, strides_B, strides_C, dtype, compute, path);
+  if (rc != COMET_OK) return rc;
+  *plan = p.release();
+  return COMET_OK;
+}
+
+comet_status_t comet_plan_create(comet_plan_t *plan, const char *spec, const int64_t *extents,
+                                 const int64_t *strides_A, const int64_t *strides_B, const int64_t *strides_C,
+                                 comet_dtype_t dtype, comet_compute_t compute) {
+  return comet_plan_create_ex(plan, spec, extents, strides_A, strides_B, strides_C, dtype, compute,
+                              COMET_PATH_AUTO);
+}
+
+comet_status_t comet_plan_workspace_size(comet_plan_t plan, size_t *bytes) {
+  if (!plan || !bytes) return fail(COMET_ERR_NULL_POINTER, "NULL argument");
+  *bytes = plan->ws_bytes;
+  return COMET_OK;
+}
+
+comet_status_t comet_plan_execute(comet_plan_t plan, double alpha, const void *A, const void *B, double beta,
+                                  void *C, void *workspace, size_t ws_bytes, void *stream) {
+  if (!plan) return fail(COMET_ERR_NULL_POINTER, "plan is NULL");
+  return execute(plan, alpha, A, B, beta, C, workspace, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+comet_status_t comet_plan_destroy(comet_plan_t plan) {
+  delete plan;
+  return COMET_OK;
+}
+
+comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len) {
+  if (!plan || !buf || !len) return fail(COMET_ERR_NULL_POINTER, "NULL argument");
+  std::string js = describe_json(plan->an);
+  std::strncpy(buf, js.c_str(), len - 1);
+  buf[len - 1] = 0;
+  if (js.size() + 1 > len) return fail(COMET_ERR_WORKSPACE, "describe buffer too small");
+  return COMET_OK;
+}
+
+comet_status_t comet_contract(const char *spec, const int64_t *extents, comet_dtype_t dtype, comet_compute_t compute,
+                              double alpha, const void *A, const int64_t *strides_A, const void *B,
+                              const int64_t *strides_B, double beta, void *C, const int64_t *strides_C,
+                              void *stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // validate first (host only), so errors come back before any HIP call
+  Analysis pre;
+  Status st = parse_spec(spec, pre);
+  if (!st.ok()) return fail(st);
+  if (!pre.labels.empty() && !extents) return fail(COMET_ERR_NULL_POINTER, "extents is NULL");
+  int dev = 0;
+  hipError_t de = hipGetDevice(&dev);
+  if (de != hipSuccess) {
+    // no usable device: still report argument errors first
+    Analysis an;
+    Status vs = analyze(spec, extents, strides_A, strides_B, strides_C, dtype, compute, COMET_PATH_AUTO,
+                        g_split_slices, an);
+    if (!vs.ok()) return fail(vs);
+    return hip_fail(de, "hipGetDevice");
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(COMET_ERR_UNSUPPORTED, "comet_contract cannot run under stream capture; use the plan API");
+  std::string key = cache_key(spec, extents, pre.labels.size(), strides_A, pre.spec_a.size(), strides_B,
+                              pre.spec_b.size(), strides_C, pre.spec_c.size(), dtype, compute, dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cache.find(key);
+  comet_plan_s *p;
+  if (it == g_cache.end()) {
+    std::unique_ptr<comet_plan_s> np;
+    comet_status_t rc = build_plan(np, spec, extents, strides_A, strides_B, strides_C, dtype, compute,
+                                   COMET_PATH_AUTO);
+    if (rc != COMET_OK) return rc;
+    p = np.get();
+    g_cache[key] = std::move(np);
+  } else {
+    p = it->second.get();
+  }
+  DeviceWorkspace &w = g_ws[dev];
+  if (p->ws_bytes > w.bytes) {
+    // grow: wait for every stream that may still use the old buffer
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (w.ptr) (void)hipFree(w.ptr);
+    w.ptr = nullptr;
+    w.bytes = 0;
+    HIP_TRY(hipMalloc(&w.ptr, p->ws_bytes), "hipMalloc(workspace)");
+    w.bytes = p->ws_bytes;
+  }
+  return execute(p, alpha, A, B, beta, C, w.ptr, w.bytes, s);
+}
+
+comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dtype_t dtype, double alpha,
+                             const void *in, const int64_t *strides_in, double beta, void *out,
+                             const int64_t *strides_out, void *stream) {
+  if (!spec) return fail(COMET_ERR_NULL_POINTER, "spec is NULL");
+  std::string s(spec), lo, li;
+  s.erase(std::remove_if(s.begin(), s.end(), [](char c) { return c == ' ' || c == '\t'; }), s.end());
+  size_t eq = s.find('=');
+  if (eq == std::string::npos || s.find('=', eq + 1) != std::string::npos)
+    return fail(COMET_ERR_INVALID_SPEC, "permute spec must read OUT=IN");
+  lo = s.substr(0, eq);
+  li = s.substr(eq + 1);
+  std::string a = lo, b = li;
+  std::sort(a.begin(), a.end());
+  std::sort(b.begin(), b.end());
+  if (a != b || std::adjacent_find(a.begin(), a.end()) != a.end() || (int)lo.size() > COMET_MAX_RANK)
+    return fail(COMET_ERR_INVALID_SPEC, "permute spec needs the same distinct labels on both sides");
+  for (char ch : lo)
+    if (!((ch >= 'a' && ch <= 'z') || (ch >= 'A' && ch <= 'Z'))) return fail(COMET_ERR_INVALID_SPEC, "bad label");
+  if (dtype != COMET_F64 && dtype != COMET_F32) return fail(COMET_ERR_UNSUPPORTED, "unknown dtype");
+  if (!lo.empty() && !extents) return fail(COMET_ERR_NULL_POINTER, "extents is NULL");
+  std::vector<int64_t> eo(lo.size());
+  int64_t total = 1;
+  for (size_t p = 0; p < lo.size(); ++p) {
+    eo[p] = extents[p];
+    if (eo[p] < 0) return fail(COMET_ERR_INVALID_SHAPE, "negative extent");
+    if (__builtin_mul_overflow(total, eo[p], &total)) return fail(COMET_ERR_INVALID_SHAPE, "size overflows int64");
+  }
+  std::vector<int64_t> so = strides_out ? std::vector<int64_t>(strides_out, strides_out + lo.size())
+                                        : dense_strides(eo);
+  std::vector<int64_t> ei(li.size());
+  for (size_t q = 0; q < li.size(); ++q) ei[q] = eo[lo.find(li[q])];
+  std::vector<int64_t> si = strides_in ? std::vector<int64_t>(strides_in, strides_in + li.size()) : dense_strides(ei);
+  for (int64_t x : so)
+    if (x < 0) return fail(COMET_ERR_INVALID_STRIDE, "negative stride");
+  for (int64_t x : si)
+    if (x < 0) return fail(COMET_ERR_INVALID_STRIDE, "negative stride");
+  {
+    std::vector<std::pair<int64_t, int64_t>> sd;
+    for (size_t p = 0; p < lo.size(); ++p) {
+      if (eo[p] <= 1) continue;
+      if (so[p] == 0) return fail(COMET_ERR_INVALID_STRIDE, "output stride 0 on a dimension of extent > 1");
+      sd.push_back({so[p], eo[p]});
+    }
+    std::sort(sd.begin(), sd.end());
+    for (size_t i = 0; i + 1 < sd.size(); ++i)
+      if (sd[i + 1].first < sd[i].first * sd[i].second)
+        return fail(COMET_ERR_INVALID_STRIDE, "output dimensions overlap in memory");
+  }
+  if (total == 0) return COMET_OK;
+  if (!out || (alpha != 0.0 && !in)) return fail(COMET_ERR_NULL_POINTER, "NULL tensor pointer");
+  PermuteDesc d = make_permute(lo, so, li, si, eo);
+  PermuteLaunch pl{};
+  pl.ndim = (int)d.ext.size();
+  for (int i = 0; i < pl.ndim; ++i) {
+    pl.ext[i] = d.ext[i];
+    pl.s_in[i] = alpha == 0.0 ? 0 : d.s_in[i];
+    pl.s_out[i] = d.s_out[i];
+  }
+  pl.in = alpha == 0.0 ? out : in;
+  pl.out = out;
+  pl.alpha = alpha;
+  pl.beta = beta;
+  pl.dtype = dtype == COMET_F64 ? 0 : 1;
+  if (dtype == COMET_F32) {
+    pl.alpha = double(float(alpha));
+    pl.beta = double(float(beta));
+  }
+  if (alpha == 0.0) {
+    // out = beta * out: a permutation of out onto itself is the identity
+    for (int i = 0; i < pl.ndim; ++i) pl.s_in[i] = pl.s_out[i];
+    pl.alpha = 0.0;
+  }
+  HIP_TRY(launch_permute(pl, static_cast<hipStream_t>(stream)), "permute launch");
+  return COMET_OK;
+}
+
+comet_status_t comet_batch_create(comet_batch_t *, int, const comet_problem_t *, comet_dtype_t, comet_compute_t) {
+  return fail(COMET_ERR_UNSUPPORTED, "batch API not built yet");
+}
+comet_status_t comet_batch_workspace_size(comet_batch_t, size_t *) {
+  return fail(COMET_ERR_UNSUPPORTED, "batch API not built yet");
+}
+comet_status_t comet_batch_execute(comet_batch_t, void *, size_t, void *) {
+  return fail(COMET_ERR_UNSUPPORTED, "batch API not built yet");
+}
+comet_status_t comet_batch_destroy(comet_batch_t) { return COMET_OK; }
+comet_status_t comet_autotune(const char *, int) { return fail(COMET_ERR_UNSUPPORTED, "autotuner not built yet"); }
+
+}  // extern "C"

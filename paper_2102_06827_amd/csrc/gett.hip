@@ -1,0 +1,369 @@
+// gett.hip -- fused gather contraction on the CDNA4 matrix cores (gfx950).
+//
+// The contraction C = alpha * A * B + beta * C over arbitrary label
+// permutations is computed as one tiled matrix product whose operand tiles
+// are gathered straight from the permuted tensors through per-label offset
+// tables (addr_A(m,k) = offAm[m] + offAk[k], and likewise for B and C).  This
+// replaces the three explicit transposes of TTGT (Section 2) by address
+// arithmetic in the loader; the tiling follows the blocking scheme of
+// Section 6 ("GEMM optimizations": an Mc x Kc panel of A and a Kc x Nc panel
+// of B staged in fast memory, an Mr x Nr register block as the micro-kernel),
+// mapped to the MI355X hierarchy:
+//
+//   workgroup tile BM x BN (LDS, double-buffered along K in steps of BK)
+//   wave tile (BM/2) x (BN/2) (registers), made of 16 x 16 MFMA blocks
+//   micro-kernel: v_mfma_f64_16x16x4f64 or v_mfma_f32_16x16x4f32
+//
+// Lane layout of the 16x16x4 MFMAs (64 lanes): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16].  It receives D[4*(l/16) + r][l%16] (r = 0..3) from the
+// FP32 instruction but D[l/16 + 4*r][l%16] from the FP64 one (checked on the
+// device with a Kronecker-delta operand).
+//
+// The epilogue writes alpha*acc + beta*C through the C offset tables; the
+// planner orders A and B so that C's unit-stride label lies along N, which
+// the MFMA output spreads over consecutive lanes.
+#include <algorithm>
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace comet {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
+template <typename T> struct AccT;
+template <> struct AccT<double> { typedef d4_t type; };
+template <> struct AccT<float> { typedef f4_t type; };
+
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// row of the 16 x 16 output block held in accumulator element r of a lane
+template <typename Tc> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+constexpr int NT = 256;   // 4 waves of 64
+
+// 16-byte vector of Tin
+template <typename T> struct V16;
+template <> struct V16<double> {
+  static constexpr int N = 2;
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <> struct V16<float> {
+  static constexpr int N = 4;
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
+// Map a linear workgroup id to a tile id such that the workgroups the
+// hardware places on one XCD (ids congruent mod 8) get consecutive tile ids,
+// then walk tiles in groups of G tile-rows so that an XCD's tiles share A
+// rows and B columns in its L2.
+__device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int *tm, int *tn) {
+  const int total = tilesM * tilesN;
+  const int X = 8;
+  int xcd = bid % X, local = bid / X;
+  int q = total / X, rem = total % X;
+  int id = xcd * q + (xcd < rem ? xcd : rem) + local;
+  const int G = 8;
+  int per_group = G * tilesN;
+  int group = id / per_group;
+  int first = group * G;
+  int gsize = tilesM - first < G ? tilesM - first : G;
+  int in = id - group * per_group;
+  *tm = first + in % gsize;
+  *tn = in / gsize;
+}
+
+// One operand tile: R rows (m for A, n for B) by BK summation indices, held in
+// LDS as s[k][r] (r contiguous, row pitch R + PAD).  LAYOUT 0: the operand is
+// contiguous along k in memory, threads walk k; LAYOUT 1: contiguous along r.
+template <typename Tin, typename Tc, int R, int BK, int LAYOUT>
+struct Loader {
+  static constexpr int VEC = V16<Tin>::N;
+  static constexpr int P = R * BK / (VEC * NT);
+  static_assert(P >= 1 && P * VEC * NT == R * BK, "tile does not split evenly over the workgroup");
+  static constexpr int PAD = 4;
+  static constexpr int LDR = R + PAD;
+
+  Tin v[P][VEC];
+  int64_t roff[P][VEC];     // hoisted row offsets (-1: row out of range)
+  int rr[P], kk[P];
+
+  __device__ __forceinline__ void init(int tid, int64_t r0, int64_t Rtot, const int64_t *offR, bool vec) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      int id = tid + p * NT;
+      if (LAYOUT == 0) {
+        rr[p] = id / (BK / VEC);
+        kk[p] = (id % (BK / VEC)) * VEC;
+        int64_t gr = r0 + rr[p];
+        int64_t o = gr < Rtot ? offR[gr] : -1;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) roff[p][i] = o;
+      } else {
+        kk[p] = id / (R / VEC);
+        rr[p] = (id % (R / VEC)) * VEC;
+        int64_t gr = r0 + rr[p];
+        if (vec) {
+          int64_t o = gr < Rtot ? offR[gr] : -1;
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) roff[p][i] = o;
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) roff[p][i] = gr + i < Rtot ? offR[gr + i] : -1;
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void load(const Tin *__restrict__ base, const int64_t *__restrict__ offK, int64_t k0,
+                                       int64_t K, bool vec) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      int64_t k = k0 + kk[p];
+      if (LAYOUT == 0) {
+        if (vec) {
+          bool ok = roff[p][0] >= 0 && k < K;
+          if (ok) {
+            typename V16<Tin>::type x =
+                *reinterpret_cast<const typename V16<Tin>::type *>(base + roff[p][0] + offK[k]);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) v[p][i] = Tin(0);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) {
+            bool ok = roff[p][0] >= 0 && k + i < K;
+            v[p][i] = ok ? base[roff[p][0] + offK[k + i]] : Tin(0);
+          }
+        }
+      } else {
+        bool kok = k < K;
+        int64_t ko = kok ? offK[k] : 0;
+        if (vec) {
+          if (kok && roff[p][0] >= 0) {
+            typename V16<Tin>::type x =
+                *reinterpret_cast<const typename V16<Tin>::type *>(base + roff[p][0] + ko);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) v[p][i] = Tin(0);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) v[p][i] = (kok && roff[p][i] >= 0) ? base[roff[p][i] + ko] : Tin(0);
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(Tc *s) const {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (LAYOUT == 0) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) s[(kk[p] + i) * LDR + rr[p]] = Tc(v[p][i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) s[kk[p] * LDR + rr[p] + i] = Tc(v[p][i]);
+      }
+    }
+  }
+};
+
+template <typename Tin, typename Tc, int BM, int BN, int BK, int LA, int LB>
+__global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, const Tin *__restrict__ B,
+                                                  Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+                                                  int64_t K, double alpha, double beta, int vecA, int vecB,
+                                                  int tilesM, int tilesN) {
+  typedef Loader<Tin, Tc, BM, BK, LA> LoadA;
+  typedef Loader<Tin, Tc, BN, BK, LB> LoadB;
+  typedef typename AccT<Tc>::type acc_t;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int FM = WM / 16, FN = WN / 16;
+  __shared__ Tc sA[2][BK * LoadA::LDR];
+  __shared__ Tc sB[2][BK * LoadB::LDR];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  int tm, tn;
+  tile_coords(blockIdx.x, tilesM, tilesN, &tm, &tn);
+  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+
+  acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  LoadA la;
+  LoadB lb;
+  la.init(tid, m0, M, t.offAm, vecA);
+  lb.init(tid, n0, N, t.offBn, vecB);
+
+  const int64_t nsteps = (K + BK - 1) / BK;
+  if (nsteps > 0) {
+    la.load(A, t.offAk, 0, K, vecA);
+    lb.load(B, t.offBk, 0, K, vecB);
+    la.store(sA[0]);
+    lb.store(sB[0]);
+  }
+  __syncthreads();
+  for (int64_t step = 0; step < nsteps; ++step) {
+    const int cur = int(step & 1);
+    const bool more = step + 1 < nsteps;
+    if (more) {
+      la.load(A, t.offAk, (step + 1) * BK, K, vecA);
+      lb.load(B, t.offBk, (step + 1) * BK, K, vecB);
+    }
+    const Tc *a_s = sA[cur];
+    const Tc *b_s = sB[cur];
+#pragma unroll
+    for (int k4 = 0; k4 < BK; k4 += 4) {
+      const int kr = k4 + (lane >> 4);
+      Tc af[FM], bf[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) af[i] = a_s[kr * LoadA::LDR + wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bf[j] = b_s[kr * LoadB::LDR + wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+    }
+    if (more) {
+      la.store(sA[cur ^ 1]);
+      lb.store(sB[cur ^ 1]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: alpha * acc + beta * C, in double for double storage or
+  // double accumulation, in float otherwise
+  typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
+  const Te al = Te(alpha), be = Te(beta);
+  const bool read_c = beta != 0.0;
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
+    if (n >= N) continue;
+    const int64_t cn = t.offCn[n];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm0 + i * 16 + acc_row<Tc>(lane, r);
+        if (m >= M) continue;
+        const int64_t addr = t.offCm[m] + cn;
+        Te v = al * Te(acc[i][j][r]);
+        if (read_c) v = v + be * Te(C[addr]);
+        C[addr] = Tin(v);
+      }
+    }
+  }
+}
+
+struct TileShape {
+  int bm, bn, bk;
+};
+constexpr TileShape kTiles[] = {{128, 128, 16}, {64, 64, 16}};
+
+template <typename Tin, typename Tc, int TILE>
+hipError_t launch_t(const GettLaunch &g, hipStream_t s) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
+  dim3 grid(tilesM * tilesN), block(NT);
+  const Tin *A = static_cast<const Tin *>(g.A);
+  const Tin *B = static_cast<const Tin *>(g.B);
+  Tin *C = static_cast<Tin *>(g.C);
+  const int sel = g.layoutA * 2 + g.layoutB;
+  switch (sel) {
+    case 0:
+      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 0, 0>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
+                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
+      break;
+    case 1:
+      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 0, 1>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
+                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 1, 0>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
+                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
+      break;
+    default:
+      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 1, 1>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
+                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename Tin, typename Tc>
+hipError_t launch_tc(const GettLaunch &g, hipStream_t s) {
+  switch (g.tile) {
+    case 1: return launch_t<Tin, Tc, 1>(g, s);
+    default: return launch_t<Tin, Tc, 0>(g, s);
+  }
+}
+
+// beta * C over the (m, n) index space of C
+template <typename T>
+__global__ __launch_bounds__(256) void scale_kernel(T *__restrict__ C, const int64_t *__restrict__ offCm,
+                                                    const int64_t *__restrict__ offCn, int64_t M, int64_t N,
+                                                    double beta) {
+  const int64_t total = M * N;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t m = i / N, n = i - m * N;
+    const int64_t a = offCm[m] + offCn[n];
+    C[a] = beta == 0.0 ? T(0) : T(double(C[a]) * beta);
+  }
+}
+
+}  // namespace
+
+int gett_tile_count() { return int(sizeof(kTiles) / sizeof(kTiles[0])); }
+
+void gett_tile_shape(int tile, int *bm, int *bn, int *bk) {
+  *bm = kTiles[tile].bm;
+  *bn = kTiles[tile].bn;
+  *bk = kTiles[tile].bk;
+}
+
+hipError_t launch_gett(const GettLaunch &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (g.dtype == 0) {
+    return g.compute == 0 ? launch_tc<double, double>(g, s) : launch_tc<double, float>(g, s);
+  }
+  return g.compute == 0 ? launch_tc<float, double>(g, s) : launch_tc<float, float>(g, s);
+}
+
+hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,
+                        double beta, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  int64_t total = M * N;
+  int blocks = int(std::min<int64_t>((total + 255) / 256, 4096));
+  if (dtype == 0)
+    hipLaunchKernelGGL(scale_kernel<double>, dim3(blocks), dim3(256), 0, s, static_cast<double *>(C), offCm, offCn, M,
+                       N, beta);
+  else
+    hipLaunchKernelGGL(scale_kernel<float>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(C), offCm, offCn, M,
+                       N, beta);
+  return hipGetLastError();
+}
+
+}  // namespace comet

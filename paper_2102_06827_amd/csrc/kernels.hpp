@@ -1,0 +1,56 @@
+// kernels.hpp -- launch interfaces of the HIP kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace comet {
+
+// Offset tables of one gather product C[m,n] = sum_k A[m,k] * B[k,n]:
+// addr_A(m,k) = offAm[m] + offAk[k], addr_B(k,n) = offBk[k] + offBn[n],
+// addr_C(m,n) = offCm[m] + offCn[n]  (elements).
+struct GettTables {
+  const int64_t *offAm, *offAk, *offBk, *offBn, *offCm, *offCn;
+};
+
+// dtype_in/out: 0 = double, 1 = float.  compute: 0 = FP64 MFMA, 1 = FP32 MFMA.
+struct GettLaunch {
+  const void *A;
+  const void *B;
+  void *C;
+  GettTables t;
+  int64_t M, N, K;
+  double alpha, beta;
+  int dtype;           // storage type of A, B, C
+  int compute;         // 0: FP64 MFMA, 1: FP32 MFMA
+  int layoutA;         // 0: A contiguous along K, 1: along M
+  int layoutB;         // 0: B contiguous along K, 1: along N
+  int vecA, vecB;      // 16-byte vector loads allowed
+  int tile;            // tile variant
+};
+
+hipError_t launch_gett(const GettLaunch &g, hipStream_t s);
+int gett_tile_count();
+void gett_tile_shape(int tile, int *bm, int *bn, int *bk);
+
+// C[offCm[m] + offCn[n]] = beta * C (beta == 0 writes zeros without reading).
+hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,
+                        double beta, hipStream_t s);
+
+// N-dimensional permutation out = alpha * in (+ beta * out), dims given in
+// output order with both strides.
+constexpr int kPermMaxDims = 12;
+struct PermuteLaunch {
+  const void *in;
+  void *out;
+  int ndim;
+  int64_t ext[kPermMaxDims];
+  int64_t s_in[kPermMaxDims];
+  int64_t s_out[kPermMaxDims];
+  double alpha, beta;
+  int dtype;
+};
+hipError_t launch_permute(const PermuteLaunch &p, hipStream_t s);
+
+}  // namespace comet

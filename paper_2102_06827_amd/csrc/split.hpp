@@ -1,0 +1,25 @@
+// split.hpp -- compensated low-precision products for FP64-grade results:
+// operand slicing (HBM-bound preparation) and the slice-pair matrix product.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace comet {
+
+struct SplitPlan {
+  int mode = 0;             // 0: aligned BF16 slices, 1: BF16x3, 2: FP16x2
+  int S = 5;                // slices per operand
+  int64_t Mp = 0, Np = 0, Kp = 0;   // padded matrix sizes of the packed operands
+  size_t offA = 0, offB = 0, offEA = 0, offEB = 0;   // workspace byte offsets
+  size_t ws_bytes = 0;
+  int tile = 0;
+};
+
+Status split_prepare(const Analysis &an, SplitPlan &sp);
+hipError_t split_execute(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
+                         const void *B, double beta, void *C, void *ws, hipStream_t s);
+
+}  // namespace comet

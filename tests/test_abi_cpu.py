@@ -1,0 +1,238 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every symbol include/comet.h declares, validates arguments before touching
+the device, and plans as documented."""
+import ctypes
+import itertools
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "comet.h")
+
+comet = pytest.importorskip("paper_2102_06827_amd")
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(comet_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_header_symbol():
+    L = comet.lib()
+    syms = header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+    out = subprocess.run(["nm", "-D", "--defined-only", comet.library_path()], capture_output=True, text=True).stdout
+    for s in syms:
+        assert re.search(r"\bT %s\b" % s, out), s
+    assert sorted(comet.SYMBOLS) == syms
+
+
+def test_version():
+    assert comet.lib().comet_version().decode() == "0.1.0"
+
+
+OK, SPEC, SHAPE, STRIDE, NULLP, UNSUP = 0, 1, 2, 3, 4, 5
+
+
+@pytest.mark.parametrize("spec,ext,code", [
+    ("abij=acik*cbkj", [2] * 6, OK),
+    ("abij=acik*cbk", [2] * 6, SPEC),         # j in C only
+    ("abij=acik*cbkjj", [2] * 6, SPEC),       # repeated label
+    ("aij=acik*ackj", [2] * 5, UNSUP),        # a in all three tensors
+    ("abij-acik*cbkj", [2] * 6, SPEC),
+    ("abij=acik", [2] * 6, SPEC),
+    ("ab1j=acik*cbkj", [2] * 6, SPEC),
+    ("abij=acik*cbkj", [2, 2, -1, 2, 2, 2], SHAPE),
+    ("abcdefghijklm=abcdefghijklmz*z", [1] * 14, SPEC),   # rank 14 > 12
+    ("=ab*ab", [3, 4], OK),                    # full contraction
+    ("iaj=ij*a", [2, 3, 4], OK),               # outer product
+])
+def test_validation_codes(spec, ext, code):
+    assert comet.analyze_status(spec, ext) == code
+
+
+def test_null_spec_and_extents():
+    assert comet.analyze_status(None, [2]) == NULLP
+    buf = ctypes.create_string_buffer(4096)
+    rc = comet.lib().comet_analyze(b"ij=ik*kj", None, None, None, None, 0, 0, 0, buf, len(buf))
+    assert rc == NULLP
+
+
+def test_stride_validation():
+    ext = [4, 5, 6]          # i, j, k for "ij=ik*kj"
+    assert comet.analyze_status("ij=ik*kj", ext, strides_A=[6, -1]) == STRIDE
+    assert comet.analyze_status("ij=ik*kj", ext, strides_A=[0, 1]) == OK          # broadcast input
+    assert comet.analyze_status("ij=ik*kj", ext, strides_C=[0, 1]) == STRIDE      # C stride 0
+    assert comet.analyze_status("ij=ik*kj", ext, strides_C=[3, 1]) == STRIDE      # rows overlap
+    assert comet.analyze_status("ij=ik*kj", ext, strides_C=[1, 4]) == OK          # column-major C
+    assert comet.analyze_status("ij=ik*kj", ext, strides_C=[10, 2]) == OK         # padded C
+
+
+def test_size_overflow():
+    big = 1 << 40
+    assert comet.analyze_status("ij=ik*kj", [big, big, 2]) == SHAPE
+
+
+def test_contract_validates_before_device():
+    """comet_contract reports argument errors before any device call."""
+    L = comet.lib()
+    ext = (ctypes.c_int64 * 6)(*([2] * 6))
+    rc = L.comet_contract(b"abij=acik*cbk", ext, 0, 0, 1.0, None, None, None, None, 0.0, None, None, None)
+    assert rc == SPEC
+    rc = L.comet_contract(b"abij=acik*cbkj", None, 0, 0, 1.0, None, None, None, None, 0.0, None, None, None)
+    assert rc == NULLP
+
+
+def test_set_split_slices_range():
+    L = comet.lib()
+    assert L.comet_set_split_slices(2) == UNSUP
+    assert L.comet_set_split_slices(7) == UNSUP
+    assert L.comet_set_split_slices(5) == OK
+
+
+# --------------------------------------------------------------------------
+# planner decisions
+# --------------------------------------------------------------------------
+
+def ext_list(spec, ext):
+    c, a, b = comet.split_spec(spec)
+    order = []
+    for ch in c + a + b:
+        if ch not in order:
+            order.append(ch)
+    return [ext[ch] for ch in order]
+
+
+def test_config2_classes_and_layouts():
+    spec = "abij=acik*bkcj"
+    ext = dict(a=96, b=96, c=96, i=32, j=32, k=32)
+    d = comet.analyze(spec, ext_list(spec, ext))
+    assert d["swapped"] is False                      # C's unit label j comes from B
+    assert [x["labels"] for x in d["M"]] == ["a", "i"]
+    assert [x["labels"] for x in d["N"]] == ["b", "j"]
+    assert sorted(x["labels"] for x in d["K"]) == ["c", "k"]
+    assert d["m"] == d["n"] == d["k"] == 3072
+    assert d["layoutA"] == "k" and d["layoutB"] == "n"   # A unit along k (K), B along j (N)
+    assert d["runs"]["Ak"] == 8 and d["runs"]["Bn"] == 8
+
+
+def test_config3_fuses_i_and_j():
+    spec = "abcijk=daij*bcdk"
+    ext = dict(a=32, b=32, c=32, d=32, i=16, j=16, k=16)
+    d = comet.analyze(spec, ext_list(spec, ext))
+    labs = [x["labels"] for x in d["M"]]
+    assert "ij" in labs                                # i, j consecutive in A and in C
+    nl = [x["labels"] for x in d["N"]]
+    assert "bck" in nl or "ck" in nl or "bc" in nl     # b, c, k consecutive in B and C
+    assert d["m"] == 8192 and d["n"] == 16384 and d["k"] == 32
+
+
+def test_swap_when_C_unit_label_comes_from_A():
+    spec = "ajbi=kcia*cjkb"      # C unit i is a free label of A
+    ext = dict(a=8, b=8, c=8, i=8, j=8, k=8)
+    d = comet.analyze(spec, ext_list(spec, ext))
+    assert d["swapped"] is True
+    assert "i" in "".join(x["labels"] for x in d["N"])
+
+
+def direct_addr(labels, strides, val):
+    return sum(val[ch] * s for ch, s in zip(labels, strides))
+
+
+@pytest.mark.parametrize("spec", ["abij=acik*cbkj", "abij=acik*bkcj", "abcijk=daij*bcdk", "ajbi=kcia*cjkb",
+                                  "abij=abcd*cdij", "abij=ijcd*cdab", "abij=ciak*bkjc", "abcd=aebf*dfce"])
+def test_offset_decomposition_matches_direct_addressing(spec):
+    """Rebuild the separable offset tables from the planner's dims and check
+    that offA[m] + offA[k] (etc.) equals the tensor's own address of every
+    label tuple."""
+    rng = np.random.default_rng(abs(hash(spec)) % 1000)
+    c, a, b = comet.split_spec(spec)
+    labels = []
+    for ch in c + a + b:
+        if ch not in labels:
+            labels.append(ch)
+    ext = {ch: int(rng.integers(2, 5)) for ch in labels}
+    # random non-dense but non-overlapping strides: pad each tensor
+    def strides(labs):
+        s, out = 1, []
+        for ch in reversed(labs):
+            out.append(s)
+            s *= ext[ch] + int(rng.integers(0, 2))
+        return out[::-1]
+    sA, sB, sC = strides(a), strides(b), strides(c)
+    d = comet.analyze(spec, [ext[ch] for ch in labels], sA, sB, sC)
+    swapped = d["swapped"]
+    la, lb = (b, a) if swapped else (a, b)
+    sa, sb = (sB, sA) if swapped else (sA, sB)
+
+    def table(dims, key):
+        shape = [x["ext"] for x in dims]
+        out = []
+        for idx in itertools.product(*[range(n) for n in shape]):
+            out.append(sum(i * x[key] for i, x in zip(idx, dims)))
+        return out, shape
+
+    def decode(dims, t):
+        val = {}
+        for x in reversed(dims):
+            n = x["ext"]
+            r, t = t % n, t // n
+            # a fused dim stands for several labels, outermost first
+            for ch in reversed(x["labels"]):
+                val[ch] = r % ext[ch]
+                r //= ext[ch]
+        return val
+
+    offAm, _ = table(d["M"], "sA")
+    offCm, _ = table(d["M"], "sC")
+    offBn, _ = table(d["N"], "sB")
+    offCn, _ = table(d["N"], "sC")
+    offAk, _ = table(d["K"], "sA")
+    offBk, _ = table(d["K"], "sB")
+    assert len(offAm) == d["m"] and len(offBn) == d["n"] and len(offAk) == d["k"]
+    for m in range(d["m"]):
+        vm = decode(d["M"], m)
+        for kk in range(d["k"]):
+            vk = decode(d["K"], kk)
+            v = dict(vm, **vk)
+            assert offAm[m] + offAk[kk] == direct_addr(la, sa, {ch: v.get(ch, 0) for ch in la})
+        for n in range(d["n"]):
+            vn = decode(d["N"], n)
+            v = dict(vm, **vn)
+            assert offCm[m] + offCn[n] == direct_addr(c, sC, v)
+    for n in range(d["n"]):
+        vn = decode(d["N"], n)
+        for kk in range(d["k"]):
+            vk = decode(d["K"], kk)
+            v = dict(vn, **vk)
+            assert offBk[kk] + offBn[n] == direct_addr(lb, sb, v)
+
+
+def test_ttgt_cost_model_on_the_worked_example():
+    """The paper's TTGT grouping of its worked example is one of the
+    candidates; the cost model picks one that moves no more (Section 6)."""
+    spec = "abcd=aebf*dfce"
+    ext = dict(a=4, b=5, c=6, d=3, e=4, f=5)
+    d = comet.analyze(spec, ext_list(spec, ext), path="ttgt")
+    t = d["ttgt"]
+    # cost of the paper's choice under the same weights: A aebf->abef, B dfce->efdc, C abcd->abdc
+    def cost(orig, perm, w):
+        return sum(w * (len(orig) - p) for p in range(len(orig)) if orig[p] != perm[p])
+    paper = cost("aebf", "abef", 1) + cost("dfce", "efdc", 1) + cost("abcd", "abdc", 2)
+    assert t["cost"] <= paper
+    # every candidate keeps each group contiguous
+    assert set(t["A"]) == set("aebf") and set(t["B"]) == set("dfce") and set(t["C"]) == set("abcd")
+
+
+def test_ttgt_identity_for_plain_gemm():
+    spec = "abij=abcd*cdij"
+    ext = dict(a=4, b=5, c=6, d=3, i=4, j=5)
+    d = comet.analyze(spec, ext_list(spec, ext), path="ttgt")
+    t = d["ttgt"]
+    assert t["cost"] == 0 and not t["copyA"] and not t["copyB"] and not t["copyC"]

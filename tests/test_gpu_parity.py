@@ -1,0 +1,340 @@
+"""Parity of the HIP contraction path against the CPU FP64 oracle.
+
+Bars: relative Frobenius error <= 1e-12 for FP64 arithmetic and <= 1e-5 for
+FP32 arithmetic; bit-exact results for integer-valued inputs (every partial
+sum is an exact integer in both precisions) and for the pure data-movement
+permute kernel.
+"""
+import os
+import random
+
+import numpy as np
+import pytest
+
+from gpu_common import TOL, inputs, oracle, print_case, shape_of, synth, to_np, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+comet = pytest.importorskip("paper_2102_06827_amd")
+
+DT = {"f64": None, "f32": None}
+
+
+def tdt(name):
+    return torch.float64 if name == "f64" else torch.float32
+
+
+def run(spec, A, B, C0=None, alpha=1.0, beta=0.0, dtype="f64", compute="default", path=None):
+    Ad, Bd = torch_dev(A, tdt(dtype)), torch_dev(B, tdt(dtype))
+    Cd = torch_dev(C0, tdt(dtype)) if C0 is not None else None
+    if path is None:
+        out = comet.contract(spec, Ad, Bd, Cd, alpha=alpha, beta=beta, compute=compute)
+    else:
+        plan = comet.Plan(spec, Ad, Bd, Cd, compute=compute, path=path)
+        out = plan(Ad, Bd, Cd, alpha=alpha, beta=beta)
+    torch.cuda.synchronize()
+    return to_np(out)
+
+
+def ref_of(spec, A, B, C0, alpha, beta, dtype):
+    """Oracle on exactly the values the GPU received (rounded to storage)."""
+    cast = np.float32 if dtype == "f32" else np.float64
+    Ar, Br = A.astype(cast), B.astype(cast)
+    Cr = C0.astype(cast) if C0 is not None else None
+    return oracle.contract(spec, Ar, Br, Cr, alpha=alpha, beta=beta)
+
+
+def check(spec, ext, dtype, seed, kind="uniform", alpha=1.0, beta=0.0, compute="default", path=None):
+    print_case(spec, ext, dtype, kind, "alpha", alpha, "beta", beta, compute, path)
+    A, B, C0 = inputs(spec, ext, seed, kind=kind, beta=True)
+    got = run(spec, A, B, C0, alpha, beta, dtype, compute, path)
+    ref = ref_of(spec, A, B, C0, alpha, beta, dtype)
+    assert got.shape == ref.shape
+    if kind == "integer":
+        assert np.array_equal(got, ref), "integer inputs must match bit for bit"
+    else:
+        mode = dtype if compute == "default" else compute
+        err = oracle.relerr(got, ref)
+        assert err <= TOL[mode], "relerr %.3e > %.0e" % (err, TOL[mode])
+    return got
+
+
+CONFIG_SMALL = [
+    # config 1 at full size (all extents 16)
+    ("abij=acik*cbkj", dict(a=16, b=16, c=16, i=16, j=16, k=16)),
+    # config 2 shape family, several tiles plus a ragged tail (M = N = K = 480)
+    ("abij=acik*bkcj", dict(a=40, b=40, c=40, i=12, j=12, k=12)),
+    # config 3 shape family, ragged
+    ("abcijk=daij*bcdk", dict(a=10, b=9, c=7, d=12, i=6, j=5, k=6)),
+    # config 5 patterns
+    ("abij=abcd*cdij", dict(a=9, b=13, c=7, d=11, i=10, j=14)),
+    ("abij=ijcd*cdab", dict(a=9, b=13, c=7, d=11, i=10, j=14)),
+    ("abij=ciak*bkjc", dict(a=17, b=9, c=12, i=8, j=24, k=6)),
+    ("ajbi=kcia*cjkb", dict(a=17, b=9, c=12, i=8, j=24, k=6)),
+    # the paper's worked example
+    ("abcd=aebf*dfce", dict(a=13, b=11, c=12, d=9, e=10, f=7)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", CONFIG_SMALL)
+def test_configs_random(spec, ext, dtype):
+    check(spec, ext, dtype, seed=100, beta=1.0, alpha=0.75)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", CONFIG_SMALL)
+def test_configs_integer_bitwise(spec, ext, dtype):
+    check(spec, ext, dtype, seed=200, kind="integer", beta=1.0, alpha=1.0)
+
+
+@pytest.mark.parametrize("compute", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_cross_precision(dtype, compute):
+    spec, ext = CONFIG_SMALL[1]
+    A, B, C0 = inputs(spec, ext, 300, beta=True)
+    print_case("cross", dtype, compute)
+    got = run(spec, A, B, C0, 1.0, 1.0, dtype, compute)
+    ref = ref_of(spec, A, B, C0, 1.0, 1.0, dtype)
+    tol = 1e-5 if (compute == "f32" or dtype == "f32") else 1e-12
+    assert oracle.relerr(got, ref) <= tol
+
+
+def random_spec(rng, max_per_class=3):
+    letters = list("abcdefghijklmnopqrstuvwxyz")
+    rng.shuffle(letters)
+    nm, nn, nk = rng.randint(0, max_per_class), rng.randint(0, max_per_class), rng.randint(0, max_per_class)
+    m, n, k = letters[:nm], letters[nm:nm + nn], letters[nm + nn:nm + nn + nk]
+    a, b, c = m + k, k + n, m + n
+    rng.shuffle(a)
+    rng.shuffle(b)
+    rng.shuffle(c)
+    return "%s=%s*%s" % ("".join(c), "".join(a), "".join(b))
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_random_specs(case):
+    rng = random.Random(5000 + case)
+    spec = random_spec(rng)
+    ext = {ch: rng.randint(1, 9) for ch in set(spec) if ch.isalpha()}
+    dtype = "f64" if case % 2 == 0 else "f32"
+    kind = "integer" if case % 3 == 0 else "uniform"
+    check(spec, ext, dtype, seed=6000 + case, kind=kind, alpha=rng.choice([1.0, -0.5, 2.0]),
+          beta=rng.choice([0.0, 1.0, -1.5]))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_strided_views(dtype):
+    spec = "abij=acik*bkcj"
+    ext = dict(a=20, b=18, c=22, i=9, j=7, k=10)
+    base_A = synth.uniform(11, (26, 30, 12, 14))
+    base_B = synth.uniform(12, (20, 12, 25, 9))
+    base_C = synth.uniform(13, (22, 21, 11, 9))
+    Ad = torch_dev(base_A, tdt(dtype))[1:21, 2:24, 1:10, 3:13]
+    Bd = torch_dev(base_B, tdt(dtype))[0:18, 1:11, 2:24, 1:8]
+    Cfull = torch_dev(base_C, tdt(dtype))
+    Cd = Cfull[1:21, 2:20, 1:10, 1:8]
+    print_case("strided", dtype)
+    A, B, C0 = to_np(Ad), to_np(Bd), to_np(Cd)
+    comet.contract(spec, Ad, Bd, Cd, alpha=1.0, beta=1.0)
+    torch.cuda.synchronize()
+    ref = oracle.contract(spec, A, B, C0, alpha=1.0, beta=1.0)
+    assert oracle.relerr(to_np(Cd), ref) <= TOL[dtype]
+    # the rest of the big C buffer is untouched
+    Cf = to_np(Cfull)
+    mask = np.ones(Cf.shape, bool)
+    mask[1:21, 2:20, 1:10, 1:8] = False
+    assert np.array_equal(Cf[mask], base_C.astype(np.float32 if dtype == "f32" else np.float64)[mask])
+
+
+def test_beta_zero_ignores_nan_in_C():
+    spec, ext = CONFIG_SMALL[0]
+    A, B, _ = inputs(spec, ext, 21)
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    Cd = torch.full(shape_of("abij", ext), float("nan"), dtype=torch.float64, device="cuda")
+    print_case("beta0 nan")
+    comet.contract(spec, Ad, Bd, Cd, beta=0.0)
+    torch.cuda.synchronize()
+    assert torch.isfinite(Cd).all()
+    assert oracle.relerr(to_np(Cd), oracle.contract(spec, A, B)) <= 1e-12
+
+
+def test_alpha_zero_scales_C_only():
+    spec, ext = CONFIG_SMALL[0]
+    C0 = synth.uniform(22, shape_of("abij", ext))
+    Ad = torch.full(shape_of("acik", ext), float("nan"), dtype=torch.float64, device="cuda")
+    Bd = torch.full(shape_of("cbkj", ext), float("nan"), dtype=torch.float64, device="cuda")
+    Cd = torch_dev(C0, torch.float64)
+    print_case("alpha0")
+    comet.contract(spec, Ad, Bd, Cd, alpha=0.0, beta=2.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(Cd), 2.0 * C0)
+
+
+def test_empty_and_degenerate():
+    print_case("degenerate")
+    # zero contracted extent: C = beta * C
+    A = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
+    B = torch.zeros((0, 7), dtype=torch.float64, device="cuda")
+    C0 = synth.uniform(31, (5, 7))
+    C = torch_dev(C0, torch.float64)
+    comet.contract("ij=ik*kj", A, B, C, beta=3.0)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), 3.0 * C0)
+    # zero free extent: nothing happens, no error
+    A = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+    B = torch.ones((4, 3), dtype=torch.float64, device="cuda")
+    C = comet.contract("ij=ik*kj", A, B)
+    assert C.shape == (0, 3)
+    # full contraction to a scalar
+    Ai = synth.integers(32, (37, 41))
+    Bi = synth.integers(33, (41, 37))
+    C = comet.contract("=ab*ba", torch_dev(Ai, torch.float64), torch_dev(Bi, torch.float64))
+    torch.cuda.synchronize()
+    assert float(C.item()) == float(np.sum(Ai * Bi.T))
+    # outer product
+    A = synth.uniform(34, (13, 6))
+    B = synth.uniform(35, (9,))
+    C = comet.contract("iaj=ij*a", torch_dev(A, torch.float64), torch_dev(B, torch.float64))
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), A[:, None, :] * B[None, :, None])
+    # extent-1 labels everywhere
+    check("abij=acik*cbkj", dict(a=1, b=1, c=1, i=1, j=1, k=1), "f64", 36)
+    check("abij=acik*cbkj", dict(a=1, b=7, c=1, i=5, j=1, k=3), "f64", 37)
+
+
+@pytest.mark.parametrize("spec,ext", [CONFIG_SMALL[1], CONFIG_SMALL[2], CONFIG_SMALL[7], CONFIG_SMALL[6]])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ttgt_equals_gett_and_oracle(spec, ext, dtype):
+    A, B, C0 = inputs(spec, ext, 400, beta=True)
+    print_case("ttgt", spec, dtype)
+    g = run(spec, A, B, C0, 1.25, -1.0, dtype, path="gett")
+    t = run(spec, A, B, C0, 1.25, -1.0, dtype, path="ttgt")
+    ref = ref_of(spec, A, B, C0, 1.25, -1.0, dtype)
+    assert oracle.relerr(g, ref) <= TOL[dtype]
+    assert oracle.relerr(t, ref) <= TOL[dtype]
+    Ai, Bi, Ci = inputs(spec, ext, 401, kind="integer", beta=True)
+    gi = run(spec, Ai, Bi, Ci, 1.0, 1.0, dtype, path="gett")
+    ti = run(spec, Ai, Bi, Ci, 1.0, 1.0, dtype, path="ttgt")
+    assert np.array_equal(gi, ti)
+    assert np.array_equal(gi, ref_of(spec, Ai, Bi, Ci, 1.0, 1.0, dtype))
+
+
+def test_ttgt_with_the_papers_worked_example_permutation(monkeypatch):
+    """TTGT forced to the decomposition printed for the worked example
+    (TA[a,b,e,f], TB[e,f,d,c], TC[a,b,d,c]) equals the oracle."""
+    spec = "abcd=aebf*dfce"
+    ext = dict(a=13, b=11, c=12, d=9, e=10, f=7)
+    monkeypatch.setenv("COMET_TTGT_ORDER", "abef|efdc|abdc")
+    A, B, C0 = inputs(spec, ext, 410, kind="integer", beta=True)
+    print_case("ttgt paper order")
+    got = run(spec, A, B, C0, 1.0, 1.0, "f64", path="ttgt")
+    assert np.array_equal(got, ref_of(spec, A, B, C0, 1.0, 1.0, "f64"))
+
+
+def test_determinism_bitwise():
+    spec, ext = CONFIG_SMALL[1]
+    A, B, C0 = inputs(spec, ext, 500, beta=True)
+    print_case("determinism")
+    r1 = run(spec, A, B, C0, 1.0, 1.0, "f64")
+    r2 = run(spec, A, B, C0, 1.0, 1.0, "f64")
+    assert np.array_equal(r1, r2)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,shape", [
+    ("ji=ij", (67, 45)),
+    ("kji=ijk", (33, 17, 29)),
+    ("acbd=abcd", (5, 34, 40, 3)),
+    ("dcba=abcd", (7, 9, 11, 35)),
+    ("bcda=abcd", (40, 3, 5, 7)),
+    ("abcd=abcd", (3, 4, 5, 6)),
+])
+def test_permute_bitwise(spec, shape, dtype):
+    lo, li = spec.split("=")
+    x = synth.uniform(600, shape)
+    xd = torch_dev(x, tdt(dtype))
+    print_case("permute", spec, dtype)
+    out = comet.permute(spec, xd)
+    torch.cuda.synchronize()
+    ref = np.transpose(x.astype(np.float32 if dtype == "f32" else np.float64), [li.index(ch) for ch in lo])
+    assert np.array_equal(to_np(out), ref)
+    # alpha, beta
+    o0 = synth.uniform(601, ref.shape)
+    od = torch_dev(o0, tdt(dtype))
+    comet.permute(spec, xd, od, alpha=2.0, beta=-1.0)
+    torch.cuda.synchronize()
+    cast = np.float32 if dtype == "f32" else np.float64
+    exp = (2.0 * ref.astype(np.float64) - o0.astype(cast).astype(np.float64)).astype(cast)
+    assert np.array_equal(to_np(od).astype(cast), exp)
+
+
+# --------------------------------------------------------------------------
+# full-size configurations, sampled against the oracle
+# --------------------------------------------------------------------------
+
+def sample_points(shape, n, seed):
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.integers(0, s, n) for s in shape], axis=1)
+    # always include the corners of the index space
+    pts[0] = 0
+    pts[1] = np.array(shape) - 1
+    return pts
+
+
+def config2_inputs():
+    V, O = 96, 32
+    ext = dict(a=V, b=V, c=V, i=O, j=O, k=O)
+    A = synth.decayed_normal(synth.config_seed(2, "A"), "acik", shape_of("acik", ext), "abc", "ijk")
+    B = synth.decayed_normal(synth.config_seed(2, "B"), "bkcj", shape_of("bkcj", ext), "abc", "ijk")
+    C0 = synth.decayed_normal(synth.config_seed(2, "C0"), "abij", shape_of("abij", ext), "abc", "ijk")
+    return ext, A, B, C0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_config2_full_size_sampled(dtype):
+    spec = "abij=acik*bkcj"
+    ext, A, B, C0 = config2_inputs()
+    print_case("config2 full", dtype)
+    got = run(spec, A, B, C0, 1.0, 1.0, dtype)
+    cast = np.float32 if dtype == "f32" else np.float64
+    pts = sample_points(got.shape, 3000, 7)
+    ref = oracle.contract_points(spec, A.astype(cast), B.astype(cast), pts, C0.astype(cast), 1.0, 1.0)
+    g = got[tuple(pts.T)]
+    assert oracle.relerr(g, ref) <= TOL[dtype]
+    # the beta = 0 product alone, so C0 cannot hide product errors
+    got0 = run(spec, A, B, None, 1.0, 0.0, dtype)
+    ref0 = oracle.contract_points(spec, A.astype(cast), B.astype(cast), pts)
+    assert oracle.relerr(got0[tuple(pts.T)], ref0) <= TOL[dtype]
+
+
+def test_config3_full_size_sampled():
+    spec = "abcijk=daij*bcdk"
+    ext = dict(a=32, b=32, c=32, d=32, i=16, j=16, k=16)
+    A = synth.uniform(synth.config_seed(3, "A"), shape_of("daij", ext))
+    B = synth.uniform(synth.config_seed(3, "B"), shape_of("bcdk", ext))
+    print_case("config3 full")
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    C = comet.contract(spec, Ad, Bd)
+    torch.cuda.synchronize()
+    pts = sample_points(tuple(C.shape), 4000, 8)
+    idx = torch.from_numpy(pts).cuda()
+    g = C[tuple(idx.T)].cpu().numpy()
+    ref = oracle.contract_points(spec, A, B, pts)
+    assert oracle.relerr(g, ref) <= 1e-12
+    # all-ones closed form over the whole output: every element is d = 32
+    C1 = comet.contract(spec, torch.ones_like(Ad), torch.ones_like(Bd))
+    torch.cuda.synchronize()
+    assert bool((C1 == 32.0).all())
+    del C, C1
+
+
+def test_config1_oracle_and_delta():
+    spec = "abij=acik*cbkj"
+    n = 16
+    A = synth.uniform(1001, (n,) * 4)
+    B = np.einsum("cb,kj->cbkj", np.eye(n), np.eye(n))
+    print_case("config1 delta")
+    got = run(spec, A, B)
+    assert np.array_equal(got, A)
