@@ -86,111 +86,123 @@ __device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int
 // One operand tile: R rows (m for A, n for B) by BK summation indices, held in
 // LDS as s[k][r] (r contiguous, row pitch R + PAD).  LAYOUT 0: the operand is
 // contiguous along k in memory, threads walk k; LAYOUT 1: contiguous along r.
-template <typename Tin, typename Tc, int R, int BK, int LAYOUT>
+//
+// Loads are branch-free: an out-of-range element is fetched from a clamped,
+// valid address and replaced by zero afterwards, so no load sits under a
+// divergent branch (which would force a full wait at the join).  The K-offset
+// table entries a step needs are fetched one step ahead, so a data load never
+// waits on the table load that addresses it.
+template <typename Tin, typename Tc, int R, int BK, int LAYOUT, bool VECLD>
 struct Loader {
   static constexpr int VEC = V16<Tin>::N;
   static constexpr int P = R * BK / (VEC * NT);
   static_assert(P >= 1 && P * VEC * NT == R * BK, "tile does not split evenly over the workgroup");
   static constexpr int PAD = 4;
   static constexpr int LDR = R + PAD;
+  // K-table entries held per pass: one per vector, or one per element when
+  // a K-contiguous operand is read element by element
+  static constexpr int NKO = (LAYOUT == 0) ? VEC : 1;
 
   Tin v[P][VEC];
-  int64_t roff[P][VEC];     // hoisted row offsets (-1: row out of range)
+  int64_t roff[P][VEC];     // hoisted row offsets (clamped to a valid row)
+  uint32_t rmask[P];        // bit i: row of element i in range
+  uint32_t vmask[P];        // bit i: element i of the last load in range
+  int64_t kofs[P][NKO];     // K-table entries of the step being fetched next
   int rr[P], kk[P];
 
-  __device__ __forceinline__ void init(int tid, int64_t r0, int64_t Rtot, const int64_t *offR, bool vec) {
+  static constexpr bool vec = VECLD;
+
+  __device__ __forceinline__ void init(int tid, int64_t r0, int64_t Rtot, const int64_t *__restrict__ offR) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       int id = tid + p * NT;
       if (LAYOUT == 0) {
         rr[p] = id / (BK / VEC);
         kk[p] = (id % (BK / VEC)) * VEC;
-        int64_t gr = r0 + rr[p];
-        int64_t o = gr < Rtot ? offR[gr] : -1;
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) roff[p][i] = o;
       } else {
         kk[p] = id / (R / VEC);
         rr[p] = (id % (R / VEC)) * VEC;
-        int64_t gr = r0 + rr[p];
-        if (vec) {
-          int64_t o = gr < Rtot ? offR[gr] : -1;
+      }
+      const int64_t gr = r0 + rr[p];
+      rmask[p] = 0;
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) roff[p][i] = o;
-        } else {
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) roff[p][i] = gr + i < Rtot ? offR[gr + i] : -1;
-        }
+      for (int i = 0; i < VEC; ++i) {
+        // K-contiguous and vector reads share the vector's first row offset
+        const int64_t g = (LAYOUT == 0 || vec) ? gr : gr + i;
+        const bool ok = g < Rtot;
+        roff[p][i] = offR[ok ? g : 0];
+        rmask[p] |= (ok ? 1u : 0u) << i;
       }
     }
   }
 
-  __device__ __forceinline__ void load(const Tin *__restrict__ base, const int64_t *__restrict__ offK, int64_t k0,
-                                       int64_t K, bool vec) {
+  // fetch the K-table entries for the step starting at k0.  Indices past the
+  // end are clamped to the last valid start: K - 1 for single elements, and
+  // K - VEC for a K-contiguous vector (K is a multiple of VEC in that mode),
+  // so the clamped vector still lies inside the tensor.
+  __device__ __forceinline__ void fetch_k(const int64_t *__restrict__ offK, int64_t k0, int64_t K) {
+    constexpr bool kvec = LAYOUT == 0 && VECLD;
+    const int64_t last = kvec ? K - VEC : K - 1;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      int64_t k = k0 + kk[p];
-      if (LAYOUT == 0) {
-        if (vec) {
-          bool ok = roff[p][0] >= 0 && k < K;
-          if (ok) {
-            typename V16<Tin>::type x =
-                *reinterpret_cast<const typename V16<Tin>::type *>(base + roff[p][0] + offK[k]);
+      const int64_t k = k0 + kk[p];
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
-          } else {
+      for (int i = 0; i < NKO; ++i) {
+        int64_t ki = k + ((LAYOUT == 0 && !vec) ? i : 0);
+        kofs[p][i] = offK[ki <= last ? ki : last];
+      }
+    }
+  }
+
+  // load the step starting at k0, addressed by the K-table entries fetched
+  // for it; the raw values are kept and masked only when stored to LDS, so
+  // no instruction between here and the store waits for the loads
+  __device__ __forceinline__ void load(const Tin *__restrict__ base, int64_t k0, int64_t K) {
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) v[p][i] = Tin(0);
-          }
-        } else {
+    for (int p = 0; p < P; ++p) {
+      const int64_t k = k0 + kk[p];
+      uint32_t m = 0;
+      if constexpr (VECLD) {
+        const typename V16<Tin>::type x =
+            *reinterpret_cast<const typename V16<Tin>::type *>(base + roff[p][0] + kofs[p][0]);
+        const bool ok = (rmask[p] & 1u) && k < K;
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) {
-            bool ok = roff[p][0] >= 0 && k + i < K;
-            v[p][i] = ok ? base[roff[p][0] + offK[k + i]] : Tin(0);
-          }
-        }
+        for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
+        m = ok ? ((1u << VEC) - 1u) : 0u;
       } else {
-        bool kok = k < K;
-        int64_t ko = kok ? offK[k] : 0;
-        if (vec) {
-          if (kok && roff[p][0] >= 0) {
-            typename V16<Tin>::type x =
-                *reinterpret_cast<const typename V16<Tin>::type *>(base + roff[p][0] + ko);
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
-          } else {
-#pragma unroll
-            for (int i = 0; i < VEC; ++i) v[p][i] = Tin(0);
-          }
-        } else {
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) v[p][i] = (kok && roff[p][i] >= 0) ? base[roff[p][i] + ko] : Tin(0);
+        for (int i = 0; i < VEC; ++i) {
+          const int64_t ko = kofs[p][LAYOUT == 0 ? i : 0];
+          v[p][i] = base[roff[p][LAYOUT == 0 ? 0 : i] + ko];
+          const bool ok = LAYOUT == 0 ? ((rmask[p] & 1u) && k + i < K) : (((rmask[p] >> i) & 1u) && k < K);
+          m |= (ok ? 1u : 0u) << i;
         }
       }
+      vmask[p] = m;
     }
   }
 
   __device__ __forceinline__ void store(Tc *s) const {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      if (LAYOUT == 0) {
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) s[(kk[p] + i) * LDR + rr[p]] = Tc(v[p][i]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) s[kk[p] * LDR + rr[p] + i] = Tc(v[p][i]);
+      for (int i = 0; i < VEC; ++i) {
+        const Tc x = ((vmask[p] >> i) & 1u) ? Tc(v[p][i]) : Tc(0);
+        if (LAYOUT == 0)
+          s[(kk[p] + i) * LDR + rr[p]] = x;
+        else
+          s[kk[p] * LDR + rr[p] + i] = x;
       }
     }
   }
 };
 
-template <typename Tin, typename Tc, int BM, int BN, int BK, int LA, int LB>
+template <typename Tin, typename Tc, int BM, int BN, int BK, int LA, int LB, bool VA, bool VB>
 __global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, const Tin *__restrict__ B,
                                                   Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
-                                                  int64_t K, double alpha, double beta, int vecA, int vecB,
-                                                  int tilesM, int tilesN) {
-  typedef Loader<Tin, Tc, BM, BK, LA> LoadA;
-  typedef Loader<Tin, Tc, BN, BK, LB> LoadB;
+                                                  int64_t K, double alpha, double beta, int tilesM, int tilesN) {
+  typedef Loader<Tin, Tc, BM, BK, LA, VA> LoadA;
+  typedef Loader<Tin, Tc, BN, BK, LB, VB> LoadB;
   typedef typename AccT<Tc>::type acc_t;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -212,25 +224,29 @@ __global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, con
 
   LoadA la;
   LoadB lb;
-  la.init(tid, m0, M, t.offAm, vecA);
-  lb.init(tid, n0, N, t.offBn, vecB);
+  la.init(tid, m0, M, t.offAm);
+  lb.init(tid, n0, N, t.offBn);
 
+  // Software pipeline, uniform across steps: the last step also issues a
+  // (masked, clamped-address) load of the step past the end, so the loop body
+  // has no branches.
   const int64_t nsteps = (K + BK - 1) / BK;
-  if (nsteps > 0) {
-    la.load(A, t.offAk, 0, K, vecA);
-    lb.load(B, t.offBk, 0, K, vecB);
-    la.store(sA[0]);
-    lb.store(sB[0]);
-  }
+  la.fetch_k(t.offAk, 0, K);
+  lb.fetch_k(t.offBk, 0, K);
+  la.load(A, 0, K);
+  lb.load(B, 0, K);
+  la.fetch_k(t.offAk, BK, K);
+  lb.fetch_k(t.offBk, BK, K);
+  la.store(sA[0]);
+  lb.store(sB[0]);
   __syncthreads();
   for (int64_t step = 0; step < nsteps; ++step) {
     const int cur = int(step & 1);
-    const bool more = step + 1 < nsteps;
-    if (more) {
-      la.load(A, t.offAk, (step + 1) * BK, K, vecA);
-      lb.load(B, t.offBk, (step + 1) * BK, K, vecB);
-    }
-    const Tc *a_s = sA[cur];
+    la.load(A, (step + 1) * BK, K);
+    lb.load(B, (step + 1) * BK, K);
+    la.fetch_k(t.offAk, (step + 2) * BK, K);
+    lb.fetch_k(t.offBk, (step + 2) * BK, K);
+  const Tc *a_s = sA[cur];
     const Tc *b_s = sB[cur];
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
@@ -245,10 +261,8 @@ __global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, con
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
     }
-    if (more) {
-      la.store(sA[cur ^ 1]);
-      lb.store(sB[cur ^ 1]);
-    }
+    la.store(sA[cur ^ 1]);
+    lb.store(sB[cur ^ 1]);
     __syncthreads();
   }
 
@@ -282,34 +296,34 @@ struct TileShape {
 };
 constexpr TileShape kTiles[] = {{128, 128, 16}, {64, 64, 16}};
 
-template <typename Tin, typename Tc, int TILE>
-hipError_t launch_t(const GettLaunch &g, hipStream_t s) {
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
   const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
-  dim3 grid(tilesM * tilesN), block(NT);
-  const Tin *A = static_cast<const Tin *>(g.A);
-  const Tin *B = static_cast<const Tin *>(g.B);
-  Tin *C = static_cast<Tin *>(g.C);
-  const int sel = g.layoutA * 2 + g.layoutB;
-  switch (sel) {
-    case 0:
-      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 0, 0>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
-                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
-      break;
-    case 1:
-      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 0, 1>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
-                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
-      break;
-    case 2:
-      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 1, 0>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
-                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
-      break;
-    default:
-      hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, 1, 1>), grid, block, 0, s, A, B, C, g.t, g.M, g.N, g.K,
-                         g.alpha, g.beta, g.vecA, g.vecB, tilesM, tilesN);
-      break;
-  }
+  hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, LA, LB, VA, VB>), dim3(tilesM * tilesN), dim3(NT), 0, s,
+                     static_cast<const Tin *>(g.A), static_cast<const Tin *>(g.B), static_cast<Tin *>(g.C), g.t,
+                     g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
   return hipGetLastError();
+}
+
+template <typename Tin, typename Tc, int TILE, int LA, int LB>
+hipError_t launch_l(const GettLaunch &g, hipStream_t s) {
+  switch ((g.vecA ? 2 : 0) + (g.vecB ? 1 : 0)) {
+    case 3: return launch_v<Tin, Tc, TILE, LA, LB, true, true>(g, s);
+    case 2: return launch_v<Tin, Tc, TILE, LA, LB, true, false>(g, s);
+    case 1: return launch_v<Tin, Tc, TILE, LA, LB, false, true>(g, s);
+    default: return launch_v<Tin, Tc, TILE, LA, LB, false, false>(g, s);
+  }
+}
+
+template <typename Tin, typename Tc, int TILE>
+hipError_t launch_t(const GettLaunch &g, hipStream_t s) {
+  switch (g.layoutA * 2 + g.layoutB) {
+    case 0: return launch_l<Tin, Tc, TILE, 0, 0>(g, s);
+    case 1: return launch_l<Tin, Tc, TILE, 0, 1>(g, s);
+    case 2: return launch_l<Tin, Tc, TILE, 1, 0>(g, s);
+    default: return launch_l<Tin, Tc, TILE, 1, 1>(g, s);
+  }
 }
 
 template <typename Tin, typename Tc>

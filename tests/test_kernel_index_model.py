@@ -1,0 +1,104 @@
+"""Host model of the GETT loader's index arithmetic (gett.hip, struct Loader).
+
+The kernel gathers operand tiles through offset tables and, to keep its loop
+free of branches, also loads past the last summation step from clamped
+indices and masks the values afterwards.  This test re-derives, for every
+loader variant (K- or row-contiguous, vector or element loads) and for
+ragged and full-size extents, every (row, k) index pair the kernel touches
+and every table entry it reads, and checks that all of them lie inside the
+tensor -- and that every 16-byte vector stays inside one contiguous run.
+The mirror must be kept in step with the device code.
+"""
+import numpy as np
+import pytest
+
+NT = 256
+
+
+def loader_indices(R, BK, VEC, layout, vec, Rtot, K):
+    """Sets of accessed rows, k indices and vector starts of one operand."""
+    P = R * BK // (VEC * NT)
+    assert P >= 1 and P * VEC * NT == R * BK
+    ids = np.arange(NT)[:, None] + NT * np.arange(P)[None, :]
+    if layout == 0:
+        rr = ids // (BK // VEC)
+        kk = (ids % (BK // VEC)) * VEC
+    else:
+        kk = ids // (R // VEC)
+        rr = (ids % (R // VEC)) * VEC
+    rows, ks, vec_rows, vec_ks, tab_r, tab_k = [], [], [], [], [], []
+    ntiles = (Rtot + R - 1) // R
+    for t in range(ntiles):
+        gr = t * R + rr
+        for i in range(VEC):
+            g = gr if (layout == 0 or vec) else gr + i
+            used = np.where(g < Rtot, g, 0)            # roff[p][i] = offR[ok ? g : 0]
+            tab_r.append(used.ravel())
+            if layout == 0:
+                if i == 0:
+                    rows.append(used.ravel())            # K-contiguous: one row per vector
+            else:
+                if vec:
+                    if i == 0:
+                        vec_rows.append(used.ravel())   # the vector covers used .. used+VEC-1
+                else:
+                    rows.append(used.ravel())
+    nsteps = (K + BK - 1) // BK
+    last = K - VEC if (layout == 0 and vec) else K - 1
+    # fetch_k is called for steps 0 .. nsteps + 1, load for 0 .. nsteps
+    for s in range(nsteps + 2):
+        k = s * BK + kk
+        nko = VEC if layout == 0 else 1
+        for i in range(nko):
+            ki = k + (i if (layout == 0 and not vec) else 0)
+            kc = np.where(ki <= last, ki, last)
+            tab_k.append(kc.ravel())
+            if s <= nsteps:
+                if layout == 0 and vec:
+                    if i == 0:
+                        vec_ks.append(kc.ravel())
+                else:
+                    ks.append(kc.ravel())
+    cat = lambda xs: np.concatenate(xs) if xs else np.zeros(0, dtype=np.int64)
+    return cat(rows), cat(ks), cat(vec_rows), cat(vec_ks), cat(tab_r), cat(tab_k)
+
+
+TILES = [(128, 128, 16), (64, 64, 16)]
+
+
+@pytest.mark.parametrize("VEC", [2, 4])
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("vec", [True, False])
+@pytest.mark.parametrize("R,BK", [(128, 16), (64, 16)])
+@pytest.mark.parametrize("Rtot,K", [(3072, 3072), (8192, 32), (16384, 32), (480, 480), (13, 7), (1, 1),
+                                    (96, 30), (250, 12), (4, 4), (17, 8)])
+def test_every_access_in_range(VEC, layout, vec, R, BK, Rtot, K):
+    # vector loads are only planned when the contiguous dimension is a multiple of VEC
+    if vec and ((layout == 0 and K % VEC) or (layout == 1 and Rtot % VEC)):
+        pytest.skip("vector mode not planned for this extent")
+    if R * BK % (VEC * NT):
+        pytest.skip("tile does not split for this vector width")
+    rows, ks, vrows, vks, tr, tk = loader_indices(R, BK, VEC, layout, vec, Rtot, K)
+    assert tr.min() >= 0 and tr.max() < Rtot, "row-table index out of range"
+    assert tk.min() >= 0 and tk.max() < K, "k-table index out of range"
+    if rows.size:
+        assert rows.max() < Rtot and rows.min() >= 0
+    if ks.size:
+        assert ks.max() < K and ks.min() >= 0
+    if vrows.size:
+        assert np.all(vrows % VEC == 0) and (vrows + VEC - 1).max() < Rtot
+    if vks.size:
+        assert np.all(vks % VEC == 0) and (vks + VEC - 1).max() < K
+
+
+def test_model_catches_the_unaligned_clamp():
+    """The clamp to K-1 (instead of K-VEC) for K-contiguous vectors reads
+    past the tensor; the model must flag it."""
+    R, BK, VEC, Rtot, K = 128, 16, 2, 3072, 3072
+    P = R * BK // (VEC * NT)
+    ids = np.arange(NT)[:, None] + NT * np.arange(P)[None, :]
+    kk = (ids % (BK // VEC)) * VEC
+    nsteps = (K + BK - 1) // BK
+    k = nsteps * BK + kk
+    bad = np.where(k <= K - 1, k, K - 1)
+    assert (bad + VEC - 1).max() >= K
