@@ -110,9 +110,19 @@ comet_status_t upload_tables(comet_plan_s *p) {
 }
 
 int pick_tile(const Analysis &an) {
-  // large problems: 128 x 128 tiles; otherwise 64 x 64 so more workgroups exist
+  const char *env = std::getenv("COMET_GETT_TILE");
+  if (env && *env) {
+    int t = std::atoi(env);
+    if (t >= 0 && t < gett_tile_count()) return t;
+  }
+  // Large problems: 128 x 128 tiles over 8 waves (two per SIMD) for FP64 and
+  // 64 x 128 tiles for FP32, the fastest shapes measured on a 3072^3
+  // contraction; small problems take 64 x 64 tiles so more workgroups exist.
   const int64_t big_tiles = ((an.m + 127) / 128) * ((an.n + 127) / 128);
-  return big_tiles >= 256 ? 0 : 1;
+  if (big_tiles < 256) return 1;
+  const bool same = (an.dtype == COMET_F64) == (an.compute == COMET_COMPUTE_F64);
+  if (!same) return 0;
+  return an.compute == COMET_COMPUTE_F64 ? 3 : 6;
 }
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
@@ -261,6 +271,9 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
   g.vecA = p->vecA_tables && (reinterpret_cast<uintptr_t>(g.A) % 16 == 0);
   g.vecB = p->vecB_tables && (reinterpret_cast<uintptr_t>(g.B) % 16 == 0);
   g.tile = an.tile;
+  // misaligned pointers or a tile not built for this dtype pair: the 64 x 64
+  // tile has every variant
+  if (!gett_tile_valid(g.tile, g.dtype, g.compute, g.vecA, g.vecB)) g.tile = 1;
   HIP_TRY(launch_gett(g, s), "gett launch");
   return COMET_OK;
 }
@@ -359,6 +372,9 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
   const char *ord = std::getenv("COMET_TTGT_ORDER");
   k += "|";
   if (ord) k += ord;
+  const char *tl = std::getenv("COMET_GETT_TILE");
+  k += "|";
+  if (tl) k += tl;
   return k;
 }
 

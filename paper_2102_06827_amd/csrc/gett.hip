@@ -50,7 +50,6 @@ template <typename Tc> __device__ __forceinline__ int acc_row(int lane, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
 
-constexpr int NT = 256;   // 4 waves of 64
 
 // 16-byte vector of Tin
 template <typename T> struct V16;
@@ -92,7 +91,7 @@ __device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int
 // divergent branch (which would force a full wait at the join).  The K-offset
 // table entries a step needs are fetched one step ahead, so a data load never
 // waits on the table load that addresses it.
-template <typename Tin, typename Tc, int R, int BK, int LAYOUT, bool VECLD>
+template <typename Tin, typename Tc, int R, int BK, int LAYOUT, bool VECLD, int NT>
 struct Loader {
   static constexpr int VEC = V16<Tin>::N;
   static constexpr int P = R * BK / (VEC * NT);
@@ -197,15 +196,35 @@ struct Loader {
   }
 };
 
-template <typename Tin, typename Tc, int BM, int BN, int BK, int LA, int LB, bool VA, bool VB>
-__global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, const Tin *__restrict__ B,
-                                                  Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
-                                                  int64_t K, double alpha, double beta, int tilesM, int tilesN) {
-  typedef Loader<Tin, Tc, BM, BK, LA, VA> LoadA;
-  typedef Loader<Tin, Tc, BN, BK, LB, VB> LoadB;
+// Tile variants: workgroup tile BM x BN, K step BK, and a WGM x WGN grid of
+// waves, each owning a (BM/WGM) x (BN/WGN) block of 16 x 16 MFMA tiles.
+struct TileShape {
+  int bm, bn, bk, wgm, wgn;
+};
+constexpr TileShape kTiles[] = {
+    {128, 128, 16, 2, 2},   // 0: large problems
+    {64, 64, 16, 2, 2},     // 1: small problems; also every element-load variant
+    {128, 128, 32, 2, 2},   // 2: longer K step (fewer barriers per flop)
+    {128, 128, 16, 4, 2},   // 3: 8 waves, two per SIMD
+    {256, 128, 16, 4, 2},   // 4: 8 waves, 64 x 64 per wave
+    {128, 64, 16, 2, 2},    // 5
+    {64, 128, 16, 2, 2},    // 6
+};
+constexpr int kNumTiles = int(sizeof(kTiles) / sizeof(kTiles[0]));
+
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett_kernel(
+    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+    int64_t K, double alpha, double beta, int tilesM, int tilesN) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  typedef Loader<Tin, Tc, BM, BK, LA, VA, NT> LoadA;
+  typedef Loader<Tin, Tc, BN, BK, LB, VB, NT> LoadB;
   typedef typename AccT<Tc>::type acc_t;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert(FM * 16 == WM && FN * 16 == WN, "wave tile must be a multiple of 16");
   __shared__ Tc sA[2][BK * LoadA::LDR];
   __shared__ Tc sB[2][BK * LoadB::LDR];
 
@@ -214,7 +233,7 @@ __global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, con
   int tm, tn;
   tile_coords(blockIdx.x, tilesM, tilesN, &tm, &tn);
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
   acc_t acc[FM][FN];
 #pragma unroll
@@ -246,7 +265,7 @@ __global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, con
     lb.load(B, (step + 1) * BK, K);
     la.fetch_k(t.offAk, (step + 2) * BK, K);
     lb.fetch_k(t.offBk, (step + 2) * BK, K);
-  const Tc *a_s = sA[cur];
+    const Tc *a_s = sA[cur];
     const Tc *b_s = sB[cur];
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
@@ -291,28 +310,41 @@ __global__ __launch_bounds__(NT) void gett_kernel(const Tin *__restrict__ A, con
   }
 }
 
-struct TileShape {
-  int bm, bn, bk;
-};
-constexpr TileShape kTiles[] = {{128, 128, 16}, {64, 64, 16}};
+template <typename Tin, typename Tc, int TILE>
+constexpr bool tile_fits() {
+  constexpr int V = 16 / int(sizeof(Tin));
+  constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
+  return (kTiles[TILE].bm * kTiles[TILE].bk) % (V * NT) == 0 && (kTiles[TILE].bn * kTiles[TILE].bk) % (V * NT) == 0;
+}
 
 template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
 hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
-  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
-  const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
-  hipLaunchKernelGGL((gett_kernel<Tin, Tc, BM, BN, BK, LA, LB, VA, VB>), dim3(tilesM * tilesN), dim3(NT), 0, s,
-                     static_cast<const Tin *>(g.A), static_cast<const Tin *>(g.B), static_cast<Tin *>(g.C), g.t,
-                     g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
-  return hipGetLastError();
+  if constexpr (!tile_fits<Tin, Tc, TILE>()) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn;
+    constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
+    const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(tilesM * tilesN), dim3(NT), 0, s,
+                       static_cast<const Tin *>(g.A), static_cast<const Tin *>(g.B), static_cast<Tin *>(g.C), g.t,
+                       g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+    return hipGetLastError();
+  }
 }
 
+// element-load (non-vector) variants exist for tile 1 only
 template <typename Tin, typename Tc, int TILE, int LA, int LB>
 hipError_t launch_l(const GettLaunch &g, hipStream_t s) {
-  switch ((g.vecA ? 2 : 0) + (g.vecB ? 1 : 0)) {
-    case 3: return launch_v<Tin, Tc, TILE, LA, LB, true, true>(g, s);
-    case 2: return launch_v<Tin, Tc, TILE, LA, LB, true, false>(g, s);
-    case 1: return launch_v<Tin, Tc, TILE, LA, LB, false, true>(g, s);
-    default: return launch_v<Tin, Tc, TILE, LA, LB, false, false>(g, s);
+  if constexpr (TILE == 1) {
+    switch ((g.vecA ? 2 : 0) + (g.vecB ? 1 : 0)) {
+      case 3: return launch_v<Tin, Tc, TILE, LA, LB, true, true>(g, s);
+      case 2: return launch_v<Tin, Tc, TILE, LA, LB, true, false>(g, s);
+      case 1: return launch_v<Tin, Tc, TILE, LA, LB, false, true>(g, s);
+      default: return launch_v<Tin, Tc, TILE, LA, LB, false, false>(g, s);
+    }
+  } else {
+    if (!g.vecA || !g.vecB) return hipErrorInvalidValue;
+    return launch_v<Tin, Tc, TILE, LA, LB, true, true>(g, s);
   }
 }
 
@@ -326,11 +358,19 @@ hipError_t launch_t(const GettLaunch &g, hipStream_t s) {
   }
 }
 
+// mixed storage/arithmetic pairs have the two basic tiles only
 template <typename Tin, typename Tc>
 hipError_t launch_tc(const GettLaunch &g, hipStream_t s) {
+  constexpr bool same = sizeof(Tin) == sizeof(Tc);
   switch (g.tile) {
+    case 0: return launch_t<Tin, Tc, 0>(g, s);
     case 1: return launch_t<Tin, Tc, 1>(g, s);
-    default: return launch_t<Tin, Tc, 0>(g, s);
+    case 2: if constexpr (same) return launch_t<Tin, Tc, 2>(g, s); else return hipErrorInvalidValue;
+    case 3: if constexpr (same) return launch_t<Tin, Tc, 3>(g, s); else return hipErrorInvalidValue;
+    case 4: if constexpr (same) return launch_t<Tin, Tc, 4>(g, s); else return hipErrorInvalidValue;
+    case 5: if constexpr (same) return launch_t<Tin, Tc, 5>(g, s); else return hipErrorInvalidValue;
+    case 6: if constexpr (same) return launch_t<Tin, Tc, 6>(g, s); else return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -350,12 +390,22 @@ __global__ __launch_bounds__(256) void scale_kernel(T *__restrict__ C, const int
 
 }  // namespace
 
-int gett_tile_count() { return int(sizeof(kTiles) / sizeof(kTiles[0])); }
+int gett_tile_count() { return kNumTiles; }
 
 void gett_tile_shape(int tile, int *bm, int *bn, int *bk) {
   *bm = kTiles[tile].bm;
   *bn = kTiles[tile].bn;
   *bk = kTiles[tile].bk;
+}
+
+bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB) {
+  if (tile < 0 || tile >= kNumTiles) return false;
+  if (tile != 1 && (!vecA || !vecB)) return false;
+  const bool same = (dtype == 0) == (compute == 0);
+  if (!same && tile > 1) return false;
+  const int V = dtype == 0 ? 2 : 4;
+  const int NT = 64 * kTiles[tile].wgm * kTiles[tile].wgn;
+  return (kTiles[tile].bm * kTiles[tile].bk) % (V * NT) == 0 && (kTiles[tile].bn * kTiles[tile].bk) % (V * NT) == 0;
 }
 
 hipError_t launch_gett(const GettLaunch &g, hipStream_t s) {

@@ -33,6 +33,8 @@ struct GettLaunch {
 hipError_t launch_gett(const GettLaunch &g, hipStream_t s);
 int gett_tile_count();
 void gett_tile_shape(int tile, int *bm, int *bn, int *bk);
+// whether a tile variant is compiled for this dtype/compute/vector combination
+bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB);
 
 // C[offCm[m] + offCn[n]] = beta * C (beta == 0 writes zeros without reading).
 hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,

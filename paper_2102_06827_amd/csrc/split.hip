@@ -1,15 +1,446 @@
-// split.hip -- placeholder until the slice kernels land.
+// split.hip -- FP64-grade contraction from low-precision matrix-core products.
+//
+// Each operand is viewed as a matrix (rows = its free labels, columns = the
+// summation labels; the offset tables of the gather path address it), and
+// every row is cut into S slices of 16-bit floats so that the sum of the
+// slice products reproduces the FP64 product:
+//
+//   mode 0, aligned (Ozaki et al., error-free splitting): the row is scaled by
+//     2^-e, e the exponent of its largest magnitude, so |x'| < 1; slice p is
+//     s_p * 2^-8(p+1) with s_p = trunc(256 * remainder), |s_p| <= 255, which a
+//     bfloat16 holds exactly.  Pair products with p + q < S are summed.  The
+//     (0,0) and (0,1)+(1,0) pair sums are integers times a power of two below
+//     2^24 over any 128 summation indices, so their FP32 accumulators are exact
+//     over such chunks; the remaining pairs are 2^-16 smaller and share one
+//     FP32 accumulator.  Every 128 indices the three accumulators are folded
+//     into FP64.
+//   mode 1, BF16x3 (Henry, Tang and Heinecke): b0 = bf16(x'), b1 = bf16(x' - b0),
+//     b2 = bf16(x' - b0 - b1); the six products with p + q <= 2 in one FP32
+//     accumulator.
+//   mode 2, FP16x2 (Ootomo and Yokota): h0 = fp16(x'), h1 = fp16((x' - h0) 2^11);
+//     h0 g0 in one FP32 accumulator, h0 g1 + h1 g0 in another scaled by 2^-11.
+//
+// Rows are scaled by powers of two in every mode (exact), which keeps the
+// 16-bit slices in range; the epilogue multiplies by 2^(eA[m] + eB[n]).
+//
+// Kernels: an exponent pass (row maxima, HBM-bound), a pack pass (gather
+// through the offset tables into an LDS tile, so reads are coalesced along
+// the operand's unit-stride label, then write K-contiguous slices -- this is
+// also the transpose of TTGT), and the slice-pair matrix product on
+// v_mfma_f32_16x16x32_{bf16,f16}.
+#include <climits>
+#include <type_traits>
+
 #include "split.hpp"
 
 namespace comet {
+namespace {
 
-Status split_prepare(const Analysis &, SplitPlan &) {
-  return Status::error(COMET_ERR_UNSUPPORTED, "split compute modes are not built yet");
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kExpNone = -(1 << 20);   // exponent of an all-zero row
+
+template <typename ST> struct Vec8;
+template <> struct Vec8<__bf16> { typedef bf16x8 type; };
+template <> struct Vec8<_Float16> { typedef f16x8 type; };
+
+__device__ __forceinline__ f4_t mfma_slice(bf16x8 a, bf16x8 b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma_slice(f16x8 a, f16x8 b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-hipError_t split_execute(const Analysis &, const SplitPlan &, const GettTables &, double, const void *, const void *,
-                         double, void *, void *, hipStream_t) {
-  return hipErrorNotSupported;
+// ---------------------------------------------------------------- slicing --
+
+constexpr int PR = 64;    // slicer tile rows
+constexpr int PK = 32;    // slicer tile summation indices
+constexpr int PT = 256;   // slicer threads
+
+// Gather a PR x PK tile into LDS (zeros outside the operand).  Threads walk
+// the operand's unit-stride dimension: k for LAYOUT 0, rows for LAYOUT 1.
+template <typename Tin, int LAYOUT>
+__device__ __forceinline__ void gather_tile(double (*t)[PK + 1], const Tin *__restrict__ base,
+                                            const int64_t *__restrict__ offR, const int64_t *__restrict__ offK,
+                                            int64_t r0, int64_t k0, int64_t R, int64_t K) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    int rl, kl;
+    if (LAYOUT == 0) {
+      kl = tid % PK;
+      rl = tid / PK + 8 * i;
+    } else {
+      rl = tid % PR;
+      kl = tid / PR + 4 * i;
+    }
+    const int64_t r = r0 + rl, k = k0 + kl;
+    double x = 0.0;
+    if (r < R && k < K) x = double(base[offR[r] + offK[k]]);
+    t[rl][kl] = x;
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_int_kernel(int *__restrict__ p, int64_t n, int v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// e[r] = max over k of the binary exponent of the operand row r
+template <typename Tin, int LAYOUT>
+__global__ __launch_bounds__(PT) void split_exp_kernel(const Tin *__restrict__ base, const int64_t *__restrict__ offR,
+                                                       const int64_t *__restrict__ offK, int64_t R, int64_t K,
+                                                       int64_t tilesR, int *__restrict__ e) {
+  __shared__ int emax[PR];
+  const int tid = threadIdx.x;
+  if (tid < PR) emax[tid] = kExpNone;
+  __syncthreads();
+  const int64_t r0 = (int64_t(blockIdx.x) % tilesR) * PR, k0 = (int64_t(blockIdx.x) / tilesR) * PK;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    int rl, kl;
+    if (LAYOUT == 0) {
+      kl = tid % PK;
+      rl = tid / PK + 8 * i;
+    } else {
+      rl = tid % PR;
+      kl = tid / PR + 4 * i;
+    }
+    const int64_t r = r0 + rl, k = k0 + kl;
+    if (r < R && k < K) {
+      const double x = double(base[offR[r] + offK[k]]);
+      if (x != 0.0) {
+        int ex;
+        (void)frexp(x, &ex);
+        atomicMax(&emax[rl], ex);
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < PR && r0 + tid < R && emax[tid] != kExpNone) atomicMax(&e[r0 + tid], emax[tid]);
+}
+
+// Cut a PR x PK tile into S slices, written K-contiguous: out[p][r][k]
+// (pitch Kp, Rp rows per slice).  Thread t writes 8 consecutive k of row t/4.
+template <typename Tin, typename ST, int LAYOUT, int MODE, int S>
+__global__ __launch_bounds__(PT) void split_pack_kernel(const Tin *__restrict__ base,
+                                                        const int64_t *__restrict__ offR,
+                                                        const int64_t *__restrict__ offK, int64_t R, int64_t K,
+                                                        int64_t tilesR, const int *__restrict__ e,
+                                                        ST *__restrict__ out, int64_t Rp, int64_t Kp) {
+  __shared__ double t[PR][PK + 1];
+  const int64_t r0 = (int64_t(blockIdx.x) % tilesR) * PR, k0 = (int64_t(blockIdx.x) / tilesR) * PK;
+  gather_tile<Tin, LAYOUT>(t, base, offR, offK, r0, k0, R, K);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const int rl = tid / 4, kc = (tid % 4) * 8;
+  const int64_t r = r0 + rl;
+  const int ex = r < R ? e[r] : kExpNone;
+  typename Vec8<ST>::type sl[S];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    double xs = ex == kExpNone ? 0.0 : ldexp(t[rl][kc + j], -ex);   // |xs| < 1, exact
+    if (MODE == 0) {
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+        const double tt = xs * 256.0;
+        const double s = trunc(tt);                                   // |s| <= 255
+        sl[p][j] = ST(float(ldexp(s, -8 * (p + 1))));                 // exact in 16 bits
+        xs = tt - s;                                                  // exact remainder
+      }
+    } else if (MODE == 1) {
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+        const ST b = ST(float(xs));
+        sl[p][j] = b;
+        xs = xs - double(float(b));
+      }
+    } else {
+      const ST h0 = ST(float(xs));
+      sl[0][j] = h0;
+      sl[1][j] = ST(float((xs - double(float(h0))) * 2048.0));
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < S; ++p)
+    *reinterpret_cast<typename Vec8<ST>::type *>(out + (int64_t(p) * Rp + r) * Kp + k0 + kc) = sl[p];
+}
+
+// ------------------------------------------------------- slice-pair GEMM --
+
+template <int MODE, int S> struct Pairs {
+  // which slice pairs are multiplied, into which accumulator, with what scale
+  static constexpr __host__ __device__ bool use(int p, int q) { return MODE == 2 ? p + q <= 1 : p + q <= S - 1; }
+  static constexpr __host__ __device__ int acc(int p, int q) {
+    return MODE == 1 ? 0 : (p + q < 2 ? p + q : 2);
+  }
+  static constexpr int NACC = MODE == 1 ? 1 : (MODE == 2 ? 2 : 3);
+  static constexpr __host__ __device__ double scale(int a) { return (MODE == 2 && a == 1) ? 1.0 / 2048.0 : 1.0; }
+  // stages between folds into FP64 (0: only at the end)
+  static constexpr int FOLD = MODE == 0 ? 4 : 0;
+};
+
+constexpr int GBM = 128, GBN = 64, GBK = 32;   // block tile
+constexpr int GWM = 4, GWN = 2;                // wave grid
+constexpr int GNT = 64 * GWM * GWN;
+constexpr int GLDK = GBK + 8;                  // LDS pitch (80 bytes: conflict-free 16-byte reads)
+
+template <typename ST, typename Tout, int MODE, int S>
+__global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ As, const ST *__restrict__ Bs,
+                                                          const int *__restrict__ eA, const int *__restrict__ eB,
+                                                          Tout *__restrict__ C, const int64_t *__restrict__ offCm,
+                                                          const int64_t *__restrict__ offCn, int64_t M, int64_t N,
+                                                          int64_t Mp, int64_t Np, int64_t Kp, double alpha,
+                                                          double beta, int tilesM, int tilesN) {
+  typedef Pairs<MODE, S> PP;
+  typedef typename Vec8<ST>::type v8;
+  constexpr int WM = GBM / GWM, WN = GBN / GWN;      // 32 x 32
+  constexpr int FM = WM / 16, FN = WN / 16;          // 2 x 2
+  constexpr int NVA = S * GBM * (GBK / 8);           // 16-byte vectors per stage
+  constexpr int NVB = S * GBN * (GBK / 8);
+  constexpr int NV = (NVA + NVB + GNT - 1) / GNT;    // per thread
+  __shared__ ST sA[S][GBM][GLDK];
+  __shared__ ST sB[S][GBN][GLDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // XCD-aware tile order, as in the gather kernel
+  int tm, tn;
+  {
+    const int total = tilesM * tilesN, X = 8, bid = blockIdx.x;
+    const int xcd = bid % X, local = bid / X, q = total / X, rem = total % X;
+    const int id = xcd * q + (xcd < rem ? xcd : rem) + local;
+    const int G = 8, per = G * tilesN, group = id / per, first = group * G;
+    const int gsize = tilesM - first < G ? tilesM - first : G;
+    const int in = id - group * per;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int64_t m0 = int64_t(tm) * GBM, n0 = int64_t(tn) * GBN;
+  const int wm0 = (wave / GWN) * WM, wn0 = (wave % GWN) * WN;
+
+  f4_t acc[PP::NACC][FM][FN];
+  d4_t acc64[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acc64[i][j] = d4_t{0, 0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < PP::NACC; ++a) acc[a][i][j] = f4_t{0, 0, 0, 0};
+    }
+
+  v8 pre[NV];
+  const int64_t nst = Kp / GBK;
+  auto gload = [&](int64_t st) {
+    const int64_t k0 = (st < nst ? st : nst - 1) * GBK;
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int v = tid + u * GNT;
+      if (v < NVA) {
+        const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, kc = (rem % 4) * 8;
+        pre[u] = *reinterpret_cast<const v8 *>(As + (int64_t(p) * Mp + m0 + row) * Kp + k0 + kc);
+      } else if (v < NVA + NVB) {
+        const int w = v - NVA;
+        const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, kc = (rem % 4) * 8;
+        pre[u] = *reinterpret_cast<const v8 *>(Bs + (int64_t(p) * Np + n0 + row) * Kp + k0 + kc);
+      }
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int v = tid + u * GNT;
+      if (v < NVA) {
+        const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, kc = (rem % 4) * 8;
+        *reinterpret_cast<v8 *>(&sA[p][row][kc]) = pre[u];
+      } else if (v < NVA + NVB) {
+        const int w = v - NVA;
+        const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, kc = (rem % 4) * 8;
+        *reinterpret_cast<v8 *>(&sB[p][row][kc]) = pre[u];
+      }
+    }
+  };
+  auto fold = [&]() {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int a = 0; a < PP::NACC; ++a) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[a][i][j][r]) * PP::scale(a);
+          acc[a][i][j] = f4_t{0, 0, 0, 0};
+        }
+  };
+
+  gload(0);
+  lstore();
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    gload(st + 1);
+    v8 bF[S][FN];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bF[q][j] = *reinterpret_cast<const v8 *>(&sB[q][wn0 + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      v8 aF[FM];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) aF[i] = *reinterpret_cast<const v8 *>(&sA[p][wm0 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        if (PP::use(p, q)) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[PP::acc(p, q)][i][j] = mfma_slice(aF[i], bF[q][j], acc[PP::acc(p, q)][i][j]);
+        }
+      }
+    }
+    if (PP::FOLD > 0 && ((st + 1) % (PP::FOLD > 0 ? PP::FOLD : 1)) == 0) fold();
+    __syncthreads();
+    lstore();
+    __syncthreads();
+  }
+  fold();
+
+  // epilogue: C = alpha * 2^(eA + eB) * acc + beta * C
+  typedef typename std::conditional<sizeof(Tout) == 8, double, float>::type Te;
+  const bool read_c = beta != 0.0;
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
+    if (n >= N) continue;
+    const int64_t cn = offCn[n];
+    const int en = eB[n];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= M) continue;
+        const int em = eA[m];
+        const int64_t addr = offCm[m] + cn;
+        const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(acc64[i][j][r], em + en);
+        Te v = Te(alpha * prod);
+        if (read_c) v = v + Te(beta) * Te(C[addr]);
+        C[addr] = Tout(v);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- launch --
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+template <typename Tin, typename ST, int MODE, int S>
+hipError_t pack_operand(const void *base, const int64_t *offR, const int64_t *offK, int64_t R, int64_t K, int layout,
+                        const int *e, ST *out, int64_t Rp, int64_t Kp, hipStream_t s) {
+  const int64_t tilesR = Rp / PR, tilesK = Kp / PK;
+  const dim3 grid(unsigned(tilesR * tilesK));
+  const Tin *b = static_cast<const Tin *>(base);
+  if (layout == 0)
+    hipLaunchKernelGGL((split_pack_kernel<Tin, ST, 0, MODE, S>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e,
+                       out, Rp, Kp);
+  else
+    hipLaunchKernelGGL((split_pack_kernel<Tin, ST, 1, MODE, S>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e,
+                       out, Rp, Kp);
+  return hipGetLastError();
+}
+
+template <typename Tin>
+hipError_t exp_operand(const void *base, const int64_t *offR, const int64_t *offK, int64_t R, int64_t K, int layout,
+                       int *e, hipStream_t s) {
+  const int64_t tilesR = (R + PR - 1) / PR, tilesK = (K + PK - 1) / PK;
+  const dim3 grid(unsigned(tilesR * tilesK));
+  const Tin *b = static_cast<const Tin *>(base);
+  if (layout == 0)
+    hipLaunchKernelGGL((split_exp_kernel<Tin, 0>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e);
+  else
+    hipLaunchKernelGGL((split_exp_kernel<Tin, 1>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e);
+  return hipGetLastError();
+}
+
+template <typename Tin, typename ST, int MODE, int S>
+hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
+                     const void *B, double beta, void *C, void *ws, hipStream_t s) {
+  char *w = static_cast<char *>(ws);
+  ST *As = reinterpret_cast<ST *>(w + sp.offA);
+  ST *Bs = reinterpret_cast<ST *>(w + sp.offB);
+  int *eA = reinterpret_cast<int *>(w + sp.offEA);
+  int *eB = reinterpret_cast<int *>(w + sp.offEB);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(64), dim3(256), 0, s, eA, sp.Mp, kExpNone);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(64), dim3(256), 0, s, eB, sp.Np, kExpNone);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if ((err = exp_operand<Tin>(A, t.offAm, t.offAk, an.m, an.k, an.layoutA, eA, s)) != hipSuccess) return err;
+  if ((err = exp_operand<Tin>(B, t.offBn, t.offBk, an.n, an.k, an.layoutB, eB, s)) != hipSuccess) return err;
+  if ((err = pack_operand<Tin, ST, MODE, S>(A, t.offAm, t.offAk, an.m, an.k, an.layoutA, eA, As, sp.Mp, sp.Kp, s)) !=
+      hipSuccess)
+    return err;
+  if ((err = pack_operand<Tin, ST, MODE, S>(B, t.offBn, t.offBk, an.n, an.k, an.layoutB, eB, Bs, sp.Np, sp.Kp, s)) !=
+      hipSuccess)
+    return err;
+  const int tilesM = int(sp.Mp / GBM), tilesN = int(sp.Np / GBN);
+  hipLaunchKernelGGL((split_gemm_kernel<ST, Tin, MODE, S>), dim3(tilesM * tilesN), dim3(GNT), 0, s, As, Bs, eA, eB,
+                     static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp, sp.Np, sp.Kp, alpha, beta, tilesM,
+                     tilesN);
+  return hipGetLastError();
+}
+
+template <typename Tin>
+hipError_t dispatch(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
+                    const void *B, double beta, void *C, void *ws, hipStream_t s) {
+  if (sp.mode == 1) return run_split<Tin, __bf16, 1, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
+  if (sp.mode == 2) return run_split<Tin, _Float16, 2, 2>(an, sp, t, alpha, A, B, beta, C, ws, s);
+  switch (sp.S) {
+    case 3: return run_split<Tin, __bf16, 0, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
+    case 4: return run_split<Tin, __bf16, 0, 4>(an, sp, t, alpha, A, B, beta, C, ws, s);
+    case 5: return run_split<Tin, __bf16, 0, 5>(an, sp, t, alpha, A, B, beta, C, ws, s);
+    case 6: return run_split<Tin, __bf16, 0, 6>(an, sp, t, alpha, A, B, beta, C, ws, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+Status split_prepare(const Analysis &an, SplitPlan &sp) {
+  sp = SplitPlan();
+  sp.mode = an.compute == COMET_COMPUTE_SPLIT_BF16 ? 0 : an.compute == COMET_COMPUTE_SPLIT_BF16X3 ? 1 : 2;
+  sp.S = sp.mode == 0 ? an.split_slices : sp.mode == 1 ? 3 : 2;
+  if (sp.S < 3 && sp.mode == 0) return Status::error(COMET_ERR_UNSUPPORTED, "split slices must be within 3..6");
+  sp.Mp = round_up(an.m, GBM);
+  sp.Np = round_up(an.n, GBN);
+  sp.Kp = round_up(an.k, GBK);
+  const int64_t tiles = (sp.Mp / GBM) * (sp.Np / GBN);
+  if (tiles > INT_MAX || (sp.Mp / PR) * (sp.Kp / PK) > INT_MAX || (sp.Np / PR) * (sp.Kp / PK) > INT_MAX)
+    return Status::error(COMET_ERR_UNSUPPORTED, "problem too large for the split path");
+  const size_t es = 2;
+  size_t off = 0;
+  sp.offA = off;
+  off = align256(off + size_t(sp.S) * sp.Mp * sp.Kp * es);
+  sp.offB = off;
+  off = align256(off + size_t(sp.S) * sp.Np * sp.Kp * es);
+  sp.offEA = off;
+  off = align256(off + size_t(sp.Mp) * 4);
+  sp.offEB = off;
+  off = align256(off + size_t(sp.Np) * 4);
+  sp.ws_bytes = off;
+  return Status{};
+}
+
+hipError_t split_execute(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
+                         const void *B, double beta, void *C, void *ws, hipStream_t s) {
+  if (an.dtype == COMET_F64) return dispatch<double>(an, sp, t, alpha, A, B, beta, C, ws, s);
+  return dispatch<float>(an, sp, t, alpha, A, B, beta, C, ws, s);
 }
 
 }  // namespace comet

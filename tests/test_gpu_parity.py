@@ -338,3 +338,17 @@ def test_config1_oracle_and_delta():
     print_case("config1 delta")
     got = run(spec, A, B)
     assert np.array_equal(got, A)
+
+
+@pytest.mark.parametrize("tile", range(7))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", [
+    ("abij=acik*bkcj", dict(a=21, b=19, c=23, i=13, j=11, k=9)),      # A k-contiguous, B n-contiguous
+    ("ajbi=kcia*cjkb", dict(a=18, b=9, c=12, i=16, j=24, k=6)),       # A m-contiguous (after the swap)
+    ("abij=ijcd*cdab", dict(a=9, b=13, c=7, d=11, i=10, j=14)),       # B k-contiguous
+])
+def test_tile_variants(tile, dtype, spec, ext, monkeypatch):
+    """Every GETT tile variant, on all operand layouts, with ragged edges."""
+    monkeypatch.setenv("COMET_GETT_TILE", str(tile))
+    check(spec, ext, dtype, seed=700 + tile, kind="integer", alpha=1.0, beta=1.0)
+    check(spec, ext, dtype, seed=720 + tile, alpha=-0.5, beta=0.25)

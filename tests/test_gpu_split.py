@@ -1,0 +1,150 @@
+"""Parity of the compensated split-precision modes against the FP64 oracle.
+
+Bars (relative Frobenius error): aligned BF16 slices <= 1e-9 on FP64
+storage; classic BF16x3 and FP16x2 <= 1e-5 (FP32-class accumulation); any
+split mode on FP32 storage <= 1e-5 (rounding the output to FP32 alone costs
+~3e-8).  Integer-valued inputs are reproduced bit for bit in every mode:
+their slices and partial sums are exact.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import inputs, oracle, print_case, shape_of, synth, to_np, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+comet = pytest.importorskip("paper_2102_06827_amd")
+
+MODES = ["split_bf16", "split_bf16x3", "split_fp16x2"]
+TOL64 = {"split_bf16": 1e-9, "split_bf16x3": 1e-5, "split_fp16x2": 1e-5}
+
+CASES = [
+    ("abij=acik*cbkj", dict(a=16, b=16, c=16, i=16, j=16, k=16)),
+    ("abij=acik*bkcj", dict(a=40, b=40, c=40, i=12, j=12, k=12)),
+    ("abcijk=daij*bcdk", dict(a=10, b=9, c=7, d=12, i=6, j=5, k=6)),
+    ("abij=ijcd*cdab", dict(a=9, b=13, c=7, d=11, i=10, j=14)),
+    ("ajbi=kcia*cjkb", dict(a=17, b=9, c=12, i=8, j=24, k=6)),
+    ("abcd=aebf*dfce", dict(a=13, b=11, c=12, d=9, e=10, f=7)),
+]
+
+
+def run(spec, A, B, C0, alpha, beta, tdt, compute):
+    Ad, Bd = torch_dev(A, tdt), torch_dev(B, tdt)
+    Cd = torch_dev(C0, tdt) if C0 is not None else None
+    out = comet.contract(spec, Ad, Bd, Cd, alpha=alpha, beta=beta, compute=compute)
+    torch.cuda.synchronize()
+    return to_np(out)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("spec,ext", CASES)
+def test_split_fp64_storage(spec, ext, mode):
+    print_case("split f64", spec, mode)
+    A, B, C0 = inputs(spec, ext, 800, kind="normal", beta=True)
+    got = run(spec, A, B, C0, 1.25, -0.5, torch.float64, mode)
+    ref = oracle.contract(spec, A, B, C0, alpha=1.25, beta=-0.5)
+    err = oracle.relerr(got, ref)
+    assert err <= TOL64[mode], "relerr %.3e" % err
+    # the product alone (beta = 0), so C0 cannot hide product errors
+    got0 = run(spec, A, B, None, 1.0, 0.0, torch.float64, mode)
+    err0 = oracle.relerr(got0, oracle.contract(spec, A, B))
+    assert err0 <= TOL64[mode], "relerr (beta=0) %.3e" % err0
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("spec,ext", CASES[:3])
+def test_split_fp32_storage(spec, ext, mode):
+    print_case("split f32", spec, mode)
+    A, B, C0 = inputs(spec, ext, 810, beta=True)
+    A32, B32, C32 = A.astype(np.float32), B.astype(np.float32), C0.astype(np.float32)
+    got = run(spec, A32, B32, C32, 1.0, 1.0, torch.float32, mode)
+    ref = oracle.contract(spec, A32, B32, C32, alpha=1.0, beta=1.0)
+    assert oracle.relerr(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("spec,ext", CASES)
+def test_split_integer_inputs_bitwise(spec, ext, mode):
+    print_case("split int", spec, mode)
+    A, B, C0 = inputs(spec, ext, 820, kind="integer", beta=True)
+    got = run(spec, A, B, C0, 1.0, 1.0, torch.float64, mode)
+    assert np.array_equal(got, oracle.contract(spec, A, B, C0, alpha=1.0, beta=1.0))
+
+
+def test_split_slices_control_the_error():
+    spec, ext = CASES[1]
+    A, B, _ = inputs(spec, ext, 830, kind="normal")
+    ref = oracle.contract(spec, A, B)
+    errs = {}
+    try:
+        for S in (3, 4, 5, 6):
+            comet.set_split_slices(S)
+            print_case("slices", S)
+            errs[S] = oracle.relerr(run(spec, A, B, None, 1.0, 0.0, torch.float64, "split_bf16"), ref)
+    finally:
+        comet.set_split_slices(5)
+    # more slices, less truncation error, down to the floor set by the FP32
+    # accumulator shared by the pairs with p + q >= 2 (rounding 2^-24 on terms
+    # 2^-16 below the leading ones: ~1e-11 relative)
+    assert errs[3] > errs[4] > errs[5] >= errs[6] * 0.9
+    assert errs[5] <= 1e-9 and errs[6] <= 1e-10
+
+
+def test_split_zero_rows_and_tiny_values():
+    """All-zero rows (exponent sentinel) and widely scaled rows."""
+    spec = "ij=ik*kj"
+    A = synth.normal(840, (70, 50))
+    B = synth.normal(841, (50, 90))
+    A[3, :] = 0.0
+    B[:, 7] = 0.0
+    A[5, :] *= 1e-200
+    B[:, 9] *= 1e150
+    print_case("split zero rows")
+    for mode in MODES:
+        got = run(spec, A, B, None, 1.0, 0.0, torch.float64, mode)
+        ref = oracle.contract(spec, A, B)
+        assert np.all(got[3, :] == 0.0) and np.all(got[:, 7] == 0.0)
+        # row-wise relative error, so the scaled rows are judged on their own
+        row = np.abs(got - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), 1e-300)
+        assert row[5] <= TOL64[mode] * 100
+        assert oracle.relerr(np.delete(got, [5], 0), np.delete(ref, [5], 0)) <= TOL64[mode] * 10
+
+
+def config2_inputs():
+    V, O = 96, 32
+    ext = dict(a=V, b=V, c=V, i=O, j=O, k=O)
+    A = synth.decayed_normal(synth.config_seed(2, "A"), "acik", shape_of("acik", ext), "abc", "ijk")
+    B = synth.decayed_normal(synth.config_seed(2, "B"), "bkcj", shape_of("bkcj", ext), "abc", "ijk")
+    C0 = synth.decayed_normal(synth.config_seed(2, "C0"), "abij", shape_of("abij", ext), "abc", "ijk")
+    return ext, A, B, C0
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_split_config2_full_size_sampled(mode):
+    spec = "abij=acik*bkcj"
+    ext, A, B, C0 = config2_inputs()
+    print_case("split config2", mode)
+    rng = np.random.default_rng(5)
+    pts = np.stack([rng.integers(0, n, 3000) for n in shape_of("abij", ext)], axis=1)
+    got0 = run(spec, A, B, None, 1.0, 0.0, torch.float64, mode)
+    ref0 = oracle.contract_points(spec, A, B, pts)
+    err = oracle.relerr(got0[tuple(pts.T)], ref0)
+    assert err <= TOL64[mode], "relerr %.3e" % err
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_split_config3_full_size_sampled(mode):
+    spec = "abcijk=daij*bcdk"
+    ext = dict(a=32, b=32, c=32, d=32, i=16, j=16, k=16)
+    A = synth.uniform(synth.config_seed(3, "A"), shape_of("daij", ext))
+    B = synth.uniform(synth.config_seed(3, "B"), shape_of("bcdk", ext))
+    print_case("split config3", mode)
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    C = comet.contract(spec, Ad, Bd, compute=mode)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    pts = np.stack([rng.integers(0, n, 4000) for n in C.shape], axis=1)
+    g = C[tuple(torch.from_numpy(pts).cuda().T)].cpu().numpy()
+    assert oracle.relerr(g, oracle.contract_points(spec, A, B, pts)) <= TOL64[mode]
+    del C

@@ -15,11 +15,12 @@ import pytest
 NT = 256
 
 
-def loader_indices(R, BK, VEC, layout, vec, Rtot, K):
+def loader_indices(R, BK, VEC, layout, vec, Rtot, K, NT=256):
     """Sets of accessed rows, k indices and vector starts of one operand."""
     P = R * BK // (VEC * NT)
     assert P >= 1 and P * VEC * NT == R * BK
     ids = np.arange(NT)[:, None] + NT * np.arange(P)[None, :]
+    assert ids.max() < R * BK // VEC
     if layout == 0:
         rr = ids // (BK // VEC)
         kk = (ids % (BK // VEC)) * VEC
@@ -63,22 +64,25 @@ def loader_indices(R, BK, VEC, layout, vec, Rtot, K):
     return cat(rows), cat(ks), cat(vec_rows), cat(vec_ks), cat(tab_r), cat(tab_k)
 
 
-TILES = [(128, 128, 16), (64, 64, 16)]
+# (BM, BN, BK, waves) of the kernel's tile table
+TILES = [(128, 128, 16, 4), (64, 64, 16, 4), (128, 128, 32, 4), (128, 128, 16, 8), (256, 128, 16, 8),
+         (128, 64, 16, 4), (64, 128, 16, 4)]
 
 
 @pytest.mark.parametrize("VEC", [2, 4])
 @pytest.mark.parametrize("layout", [0, 1])
 @pytest.mark.parametrize("vec", [True, False])
-@pytest.mark.parametrize("R,BK", [(128, 16), (64, 16)])
+@pytest.mark.parametrize("R,BK,NTl", sorted({(t[0], t[2], 64 * t[3]) for t in TILES} |
+                                             {(t[1], t[2], 64 * t[3]) for t in TILES}))
 @pytest.mark.parametrize("Rtot,K", [(3072, 3072), (8192, 32), (16384, 32), (480, 480), (13, 7), (1, 1),
                                     (96, 30), (250, 12), (4, 4), (17, 8)])
-def test_every_access_in_range(VEC, layout, vec, R, BK, Rtot, K):
+def test_every_access_in_range(VEC, layout, vec, R, BK, NTl, Rtot, K):
     # vector loads are only planned when the contiguous dimension is a multiple of VEC
     if vec and ((layout == 0 and K % VEC) or (layout == 1 and Rtot % VEC)):
         pytest.skip("vector mode not planned for this extent")
-    if R * BK % (VEC * NT):
+    if R * BK % (VEC * NTl):
         pytest.skip("tile does not split for this vector width")
-    rows, ks, vrows, vks, tr, tk = loader_indices(R, BK, VEC, layout, vec, Rtot, K)
+    rows, ks, vrows, vks, tr, tk = loader_indices(R, BK, VEC, layout, vec, Rtot, K, NTl)
     assert tr.min() >= 0 and tr.max() < Rtot, "row-table index out of range"
     assert tk.min() >= 0 and tk.max() < K, "k-table index out of range"
     if rows.size:
