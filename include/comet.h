@@ -191,7 +191,11 @@ comet_status_t comet_analyze(const char *spec, const int64_t *extents,
  * Batch API: n independent contractions in ONE persistent kernel launch.
  * Workgroups take (problem, tile) items from a device work list ordered by
  * decreasing cost, so many small, uneven problems fill the GPU together.
- * All problems share dtype and compute; compute must be DEFAULT, F64 or F32.
+ * All problems share dtype and compute; compute must be the storage type's
+ * native MFMA (DEFAULT, or F64 / F32 matching the dtype), or SPLIT_BF16X3
+ * with FP32 storage (operands split into three bfloat16 slices inside the
+ * loader).  Problems with an empty summation or alpha == 0 are scaled by
+ * beta before the launch.  The workspace holds the work counter (256 bytes).
  * comet_batch_create plans every problem and uploads the work list and
  * offset tables (not capturable); comet_batch_execute is capturable.
  */

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -71,6 +72,7 @@ struct comet_plan_s {
   void *dtables = nullptr;     // the six offset tables, one device allocation
   GettTables t{};
   bool vecA_tables = false, vecB_tables = false;
+  bool fused3 = false;         // FP32 operands split into BF16x3 inside the gather kernel
   size_t ws_bytes = 0;
   // split modes
   SplitPlan split;
@@ -81,6 +83,28 @@ struct comet_plan_s {
 
   ~comet_plan_s() {
     if (dtables) (void)hipFree(dtables);
+  }
+};
+
+struct comet_batch_s {
+  struct ScaleJob {
+    void *C;
+    const int64_t *offCm, *offCn;
+    int64_t m, n;
+    double beta;
+  };
+  int device = 0;
+  comet_dtype_t dtype = COMET_F64;
+  int mode = 0;                    // 0: native MFMA, 1: fused BF16x3
+  void *dbuf = nullptr;            // descriptors, work items, offset tables
+  const BatchDesc *descs = nullptr;
+  const BatchItem *items = nullptr;
+  int64_t total = 0;
+  int grid = 1;
+  std::vector<ScaleJob> scales;    // empty summation or alpha == 0: C = beta * C
+
+  ~comet_batch_s() {
+    if (dbuf) (void)hipFree(dbuf);
   }
 };
 
@@ -242,7 +266,9 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC);
   bool split = an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
                an.compute == COMET_COMPUTE_SPLIT_FP16X2;
-  if (split && !an.empty_out && !an.empty_sum) {
+  // FP32 storage in BF16x3: split on the fly inside the gather kernel
+  p->fused3 = an.compute == COMET_COMPUTE_SPLIT_BF16X3 && an.dtype == COMET_F32;
+  if (split && !p->fused3 && !an.empty_out && !an.empty_sum) {
     Status s2 = split_prepare(an, p->split);
     if (!s2.ok()) return fail(s2);
     p->ws_bytes = p->split.ws_bytes;
@@ -296,6 +322,25 @@ comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const
   }
   if (p->ws_bytes > 0 && (!ws || ws_bytes < p->ws_bytes))
     return fail(COMET_ERR_WORKSPACE, "workspace smaller than comet_plan_workspace_size");
+  if (p->fused3) {
+    GettLaunch g{};
+    g.A = an.swapped ? B : A;
+    g.B = an.swapped ? A : B;
+    g.C = C;
+    g.t = p->t;
+    g.M = an.m;
+    g.N = an.n;
+    g.K = an.k;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.dtype = 1;
+    g.layoutA = an.layoutA;
+    g.layoutB = an.layoutB;
+    g.vecA = g.vecB = p->vecA_tables && p->vecB_tables && reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
+                      reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+    HIP_TRY(launch_fused_bf16x3(g, s), "fused BF16x3 launch");
+    return COMET_OK;
+  }
   if (an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
       an.compute == COMET_COMPUTE_SPLIT_FP16X2) {
     const void *Ak = an.swapped ? B : A, *Bk = an.swapped ? A : B;
@@ -580,16 +625,135 @@ comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dty
   return COMET_OK;
 }
 
-comet_status_t comet_batch_create(comet_batch_t *, int, const comet_problem_t *, comet_dtype_t, comet_compute_t) {
-  return fail(COMET_ERR_UNSUPPORTED, "batch API not built yet");
+comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_problem_t *problems, comet_dtype_t dtype,
+                                  comet_compute_t compute) {
+  if (!batch) return fail(COMET_ERR_NULL_POINTER, "batch is NULL");
+  if (n < 0) return fail(COMET_ERR_INVALID_SHAPE, "negative problem count");
+  if (n > 0 && !problems) return fail(COMET_ERR_NULL_POINTER, "problems is NULL");
+  std::unique_ptr<comet_batch_s> b(new comet_batch_s());
+  b->dtype = dtype;
+  const int VEC = dtype == COMET_F64 ? 2 : 4;
+  std::vector<Analysis> an(n);
+  for (int i = 0; i < n; ++i) {
+    const comet_problem_t &pr = problems[i];
+    Status st = analyze(pr.spec, pr.extents, pr.strides_A, pr.strides_B, pr.strides_C, dtype, compute,
+                        COMET_PATH_GETT, g_split_slices, an[i]);
+    if (!st.ok()) return fail(st.code, "problem " + std::to_string(i) + ": " + st.msg);
+    const Analysis &a = an[i];
+    int mode;
+    if (a.compute == COMET_COMPUTE_SPLIT_BF16X3 && dtype == COMET_F32)
+      mode = 1;
+    else if ((a.compute == COMET_COMPUTE_F64 && dtype == COMET_F64) || (a.compute == COMET_COMPUTE_F32 && dtype == COMET_F32))
+      mode = 0;
+    else
+      return fail(COMET_ERR_UNSUPPORTED, "batch: compute must be the storage type's native MFMA, or BF16x3 on FP32");
+    if (i == 0) b->mode = mode;
+    if (a.empty_out) continue;
+    if (!pr.C) return fail(COMET_ERR_NULL_POINTER, "problem " + std::to_string(i) + ": C is NULL");
+    const bool reads = pr.alpha != 0.0 && !a.empty_sum;
+    if (reads && (!pr.A || !pr.B)) return fail(COMET_ERR_NULL_POINTER, "problem " + std::to_string(i) + ": A or B is NULL");
+    if (reads && (pr.C == pr.A || pr.C == pr.B))
+      return fail(COMET_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": C aliases an input");
+  }
+  // device buffer: descriptors, work items, then every problem's six tables
+  std::vector<BatchDesc> descs(n);
+  std::vector<size_t> tab_off(n, 0);
+  size_t bytes = align256(sizeof(BatchDesc) * std::max(n, 1));
+  const size_t items_off = bytes;
+  int64_t total = 0;
+  std::vector<int> order;
+  for (int i = 0; i < n; ++i) {
+    const Analysis &a = an[i];
+    if (a.empty_out || a.empty_sum || problems[i].alpha == 0.0) continue;
+    order.push_back(i);
+    total += ((a.m + kBatchTile - 1) / kBatchTile) * ((a.n + kBatchTile - 1) / kBatchTile);
+  }
+  if (total > INT32_MAX) return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 tiles");
+  bytes += align256(sizeof(BatchItem) * std::max<int64_t>(total, 1));
+  for (int i = 0; i < n; ++i) {
+    tab_off[i] = bytes;
+    const Analysis &a = an[i];
+    for (const std::vector<int64_t> *v : {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn})
+      bytes += align256(std::max<size_t>(v->size(), 1) * sizeof(int64_t));
+  }
+  HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
+  HIP_TRY(hipMalloc(&b->dbuf, bytes), "hipMalloc(batch)");
+  std::vector<char> host(bytes, 0);
+  char *dev = static_cast<char *>(b->dbuf);
+  for (int i = 0; i < n; ++i) {
+    const Analysis &a = an[i];
+    const comet_problem_t &pr = problems[i];
+    size_t off = tab_off[i];
+    const int64_t *ptr[6];
+    int k = 0;
+    for (const std::vector<int64_t> *v : {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn}) {
+      if (!v->empty()) std::memcpy(host.data() + off, v->data(), v->size() * sizeof(int64_t));
+      ptr[k++] = reinterpret_cast<const int64_t *>(dev + off);
+      off += align256(std::max<size_t>(v->size(), 1) * sizeof(int64_t));
+    }
+    BatchDesc &d = descs[i];
+    d.A = a.swapped ? pr.B : pr.A;
+    d.B = a.swapped ? pr.A : pr.B;
+    d.C = pr.C;
+    d.t = GettTables{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5]};
+    d.M = a.m;
+    d.N = a.n;
+    d.K = a.k;
+    d.alpha = dtype == COMET_F32 ? double(float(pr.alpha)) : pr.alpha;
+    d.beta = dtype == COMET_F32 ? double(float(pr.beta)) : pr.beta;
+    const bool vec = tables_vec_ok(a.offAm, a.offAk, a.layoutA, a.runAm, a.runAk, VEC) &&
+                     tables_vec_ok(a.offBn, a.offBk, a.layoutB, a.runBn, a.runBk, VEC) &&
+                     reinterpret_cast<uintptr_t>(d.A) % 16 == 0 && reinterpret_cast<uintptr_t>(d.B) % 16 == 0;
+    d.variant = a.layoutA * 2 + a.layoutB + (vec ? 0 : 4);
+    d.tilesN = int((a.n + kBatchTile - 1) / kBatchTile);
+    if (!a.empty_out && (a.empty_sum || pr.alpha == 0.0))
+      b->scales.push_back({pr.C, ptr[4], ptr[5], a.m, a.n, d.beta});
+  }
+  // longest summation first, so the heaviest tiles start early
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return an[x].k > an[y].k; });
+  BatchItem *items = reinterpret_cast<BatchItem *>(host.data() + items_off);
+  int64_t w = 0;
+  for (int i : order) {
+    const int64_t tiles = ((an[i].m + kBatchTile - 1) / kBatchTile) * ((an[i].n + kBatchTile - 1) / kBatchTile);
+    for (int64_t t = 0; t < tiles; ++t) items[w++] = BatchItem{i, int(t)};
+  }
+  if (n > 0) std::memcpy(host.data(), descs.data(), sizeof(BatchDesc) * n);
+  HIP_TRY(hipMemcpy(b->dbuf, host.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(batch)");
+  b->descs = reinterpret_cast<const BatchDesc *>(dev);
+  b->items = reinterpret_cast<const BatchItem *>(dev + items_off);
+  b->total = total;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, b->device), "hipGetDeviceProperties");
+  const int64_t resident = int64_t(prop.multiProcessorCount) * batch_blocks_per_cu(dtype == COMET_F64 ? 0 : 1, b->mode);
+  b->grid = int(std::max<int64_t>(1, std::min<int64_t>(total, resident)));
+  *batch = b.release();
+  return COMET_OK;
 }
-comet_status_t comet_batch_workspace_size(comet_batch_t, size_t *) {
-  return fail(COMET_ERR_UNSUPPORTED, "batch API not built yet");
+
+comet_status_t comet_batch_workspace_size(comet_batch_t batch, size_t *bytes) {
+  if (!batch || !bytes) return fail(COMET_ERR_NULL_POINTER, "NULL argument");
+  *bytes = 256;   // the work counter
+  return COMET_OK;
 }
-comet_status_t comet_batch_execute(comet_batch_t, void *, size_t, void *) {
-  return fail(COMET_ERR_UNSUPPORTED, "batch API not built yet");
+
+comet_status_t comet_batch_execute(comet_batch_t batch, void *workspace, size_t ws_bytes, void *stream) {
+  if (!batch) return fail(COMET_ERR_NULL_POINTER, "batch is NULL");
+  if (!workspace || ws_bytes < 256) return fail(COMET_ERR_WORKSPACE, "batch workspace needs 256 bytes");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (const auto &sc : batch->scales)
+    HIP_TRY(launch_scale(sc.C, batch->dtype == COMET_F64 ? 0 : 1, sc.offCm, sc.offCn, sc.m, sc.n, sc.beta, s),
+            "batch scale");
+  HIP_TRY(launch_batch(batch->descs, batch->items, batch->total, static_cast<int *>(workspace),
+                       batch->dtype == COMET_F64 ? 0 : 1, batch->mode, batch->grid, s),
+          "batch launch");
+  return COMET_OK;
 }
-comet_status_t comet_batch_destroy(comet_batch_t) { return COMET_OK; }
+
+comet_status_t comet_batch_destroy(comet_batch_t batch) {
+  delete batch;
+  return COMET_OK;
+}
+
 comet_status_t comet_autotune(const char *, int) { return fail(COMET_ERR_UNSUPPORTED, "autotuner not built yet"); }
 
 }  // extern "C"

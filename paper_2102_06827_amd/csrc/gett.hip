@@ -25,176 +25,13 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "gather.hpp"
 #include "kernels.hpp"
 
 namespace comet {
 namespace {
 
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef double d2_t __attribute__((ext_vector_type(2)));
-
-template <typename T> struct AccT;
-template <> struct AccT<double> { typedef d4_t type; };
-template <> struct AccT<float> { typedef f4_t type; };
-
-__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// row of the 16 x 16 output block held in accumulator element r of a lane
-template <typename Tc> __device__ __forceinline__ int acc_row(int lane, int r);
-template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
-template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
-
-
-// 16-byte vector of Tin
-template <typename T> struct V16;
-template <> struct V16<double> {
-  static constexpr int N = 2;
-  typedef double type __attribute__((ext_vector_type(2)));
-};
-template <> struct V16<float> {
-  static constexpr int N = 4;
-  typedef float type __attribute__((ext_vector_type(4)));
-};
-
-// Map a linear workgroup id to a tile id such that the workgroups the
-// hardware places on one XCD (ids congruent mod 8) get consecutive tile ids,
-// then walk tiles in groups of G tile-rows so that an XCD's tiles share A
-// rows and B columns in its L2.
-__device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int *tm, int *tn) {
-  const int total = tilesM * tilesN;
-  const int X = 8;
-  int xcd = bid % X, local = bid / X;
-  int q = total / X, rem = total % X;
-  int id = xcd * q + (xcd < rem ? xcd : rem) + local;
-  const int G = 8;
-  int per_group = G * tilesN;
-  int group = id / per_group;
-  int first = group * G;
-  int gsize = tilesM - first < G ? tilesM - first : G;
-  int in = id - group * per_group;
-  *tm = first + in % gsize;
-  *tn = in / gsize;
-}
-
-// One operand tile: R rows (m for A, n for B) by BK summation indices, held in
-// LDS as s[k][r] (r contiguous, row pitch R + PAD).  LAYOUT 0: the operand is
-// contiguous along k in memory, threads walk k; LAYOUT 1: contiguous along r.
-//
-// Loads are branch-free: an out-of-range element is fetched from a clamped,
-// valid address and replaced by zero afterwards, so no load sits under a
-// divergent branch (which would force a full wait at the join).  The K-offset
-// table entries a step needs are fetched one step ahead, so a data load never
-// waits on the table load that addresses it.
-template <typename Tin, typename Tc, int R, int BK, int LAYOUT, bool VECLD, int NT>
-struct Loader {
-  static constexpr int VEC = V16<Tin>::N;
-  static constexpr int P = R * BK / (VEC * NT);
-  static_assert(P >= 1 && P * VEC * NT == R * BK, "tile does not split evenly over the workgroup");
-  static constexpr int PAD = 4;
-  static constexpr int LDR = R + PAD;
-  // K-table entries held per pass: one per vector, or one per element when
-  // a K-contiguous operand is read element by element
-  static constexpr int NKO = (LAYOUT == 0) ? VEC : 1;
-
-  Tin v[P][VEC];
-  int64_t roff[P][VEC];     // hoisted row offsets (clamped to a valid row)
-  uint32_t rmask[P];        // bit i: row of element i in range
-  uint32_t vmask[P];        // bit i: element i of the last load in range
-  int64_t kofs[P][NKO];     // K-table entries of the step being fetched next
-  int rr[P], kk[P];
-
-  static constexpr bool vec = VECLD;
-
-  __device__ __forceinline__ void init(int tid, int64_t r0, int64_t Rtot, const int64_t *__restrict__ offR) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      int id = tid + p * NT;
-      if (LAYOUT == 0) {
-        rr[p] = id / (BK / VEC);
-        kk[p] = (id % (BK / VEC)) * VEC;
-      } else {
-        kk[p] = id / (R / VEC);
-        rr[p] = (id % (R / VEC)) * VEC;
-      }
-      const int64_t gr = r0 + rr[p];
-      rmask[p] = 0;
-#pragma unroll
-      for (int i = 0; i < VEC; ++i) {
-        // K-contiguous and vector reads share the vector's first row offset
-        const int64_t g = (LAYOUT == 0 || vec) ? gr : gr + i;
-        const bool ok = g < Rtot;
-        roff[p][i] = offR[ok ? g : 0];
-        rmask[p] |= (ok ? 1u : 0u) << i;
-      }
-    }
-  }
-
-  // fetch the K-table entries for the step starting at k0.  Indices past the
-  // end are clamped to the last valid start: K - 1 for single elements, and
-  // K - VEC for a K-contiguous vector (K is a multiple of VEC in that mode),
-  // so the clamped vector still lies inside the tensor.
-  __device__ __forceinline__ void fetch_k(const int64_t *__restrict__ offK, int64_t k0, int64_t K) {
-    constexpr bool kvec = LAYOUT == 0 && VECLD;
-    const int64_t last = kvec ? K - VEC : K - 1;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int64_t k = k0 + kk[p];
-#pragma unroll
-      for (int i = 0; i < NKO; ++i) {
-        int64_t ki = k + ((LAYOUT == 0 && !vec) ? i : 0);
-        kofs[p][i] = offK[ki <= last ? ki : last];
-      }
-    }
-  }
-
-  // load the step starting at k0, addressed by the K-table entries fetched
-  // for it; the raw values are kept and masked only when stored to LDS, so
-  // no instruction between here and the store waits for the loads
-  __device__ __forceinline__ void load(const Tin *__restrict__ base, int64_t k0, int64_t K) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int64_t k = k0 + kk[p];
-      uint32_t m = 0;
-      if constexpr (VECLD) {
-        const typename V16<Tin>::type x =
-            *reinterpret_cast<const typename V16<Tin>::type *>(base + roff[p][0] + kofs[p][0]);
-        const bool ok = (rmask[p] & 1u) && k < K;
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
-        m = ok ? ((1u << VEC) - 1u) : 0u;
-      } else {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-          const int64_t ko = kofs[p][LAYOUT == 0 ? i : 0];
-          v[p][i] = base[roff[p][LAYOUT == 0 ? 0 : i] + ko];
-          const bool ok = LAYOUT == 0 ? ((rmask[p] & 1u) && k + i < K) : (((rmask[p] >> i) & 1u) && k < K);
-          m |= (ok ? 1u : 0u) << i;
-        }
-      }
-      vmask[p] = m;
-    }
-  }
-
-  __device__ __forceinline__ void store(Tc *s) const {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-#pragma unroll
-      for (int i = 0; i < VEC; ++i) {
-        const Tc x = ((vmask[p] >> i) & 1u) ? Tc(v[p][i]) : Tc(0);
-        if (LAYOUT == 0)
-          s[(kk[p] + i) * LDR + rr[p]] = x;
-        else
-          s[kk[p] * LDR + rr[p] + i] = x;
-      }
-    }
-  }
-};
+using namespace gather;
 
 // Tile variants: workgroup tile BM x BN, K step BK, and a WGM x WGN grid of
 // waves, each owning a (BM/WGM) x (BN/WGN) block of 16 x 16 MFMA tiles.
@@ -219,95 +56,11 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
   constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
   constexpr int NT = 64 * WGM * WGN;
-  typedef Loader<Tin, Tc, BM, BK, LA, VA, NT> LoadA;
-  typedef Loader<Tin, Tc, BN, BK, LB, VB, NT> LoadB;
-  typedef typename AccT<Tc>::type acc_t;
-  constexpr int WM = BM / WGM, WN = BN / WGN;
-  constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert(FM * 16 == WM && FN * 16 == WN, "wave tile must be a multiple of 16");
-  __shared__ Tc sA[2][BK * LoadA::LDR];
-  __shared__ Tc sB[2][BK * LoadB::LDR];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  __shared__ Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
   int tm, tn;
   tile_coords(blockIdx.x, tilesM, tilesN, &tm, &tn);
-  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
-
-  acc_t acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-
-  LoadA la;
-  LoadB lb;
-  la.init(tid, m0, M, t.offAm);
-  lb.init(tid, n0, N, t.offBn);
-
-  // Software pipeline, uniform across steps: the last step also issues a
-  // (masked, clamped-address) load of the step past the end, so the loop body
-  // has no branches.
-  const int64_t nsteps = (K + BK - 1) / BK;
-  la.fetch_k(t.offAk, 0, K);
-  lb.fetch_k(t.offBk, 0, K);
-  la.load(A, 0, K);
-  lb.load(B, 0, K);
-  la.fetch_k(t.offAk, BK, K);
-  lb.fetch_k(t.offBk, BK, K);
-  la.store(sA[0]);
-  lb.store(sB[0]);
-  __syncthreads();
-  for (int64_t step = 0; step < nsteps; ++step) {
-    const int cur = int(step & 1);
-    la.load(A, (step + 1) * BK, K);
-    lb.load(B, (step + 1) * BK, K);
-    la.fetch_k(t.offAk, (step + 2) * BK, K);
-    lb.fetch_k(t.offBk, (step + 2) * BK, K);
-    const Tc *a_s = sA[cur];
-    const Tc *b_s = sB[cur];
-#pragma unroll
-    for (int k4 = 0; k4 < BK; k4 += 4) {
-      const int kr = k4 + (lane >> 4);
-      Tc af[FM], bf[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = a_s[kr * LoadA::LDR + wm0 + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = b_s[kr * LoadB::LDR + wn0 + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
-    }
-    la.store(sA[cur ^ 1]);
-    lb.store(sB[cur ^ 1]);
-    __syncthreads();
-  }
-
-  // epilogue: alpha * acc + beta * C, in double for double storage or
-  // double accumulation, in float otherwise
-  typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
-  const Te al = Te(alpha), be = Te(beta);
-  const bool read_c = beta != 0.0;
-#pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
-    if (n >= N) continue;
-    const int64_t cn = t.offCn[n];
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm0 + i * 16 + acc_row<Tc>(lane, r);
-        if (m >= M) continue;
-        const int64_t addr = t.offCm[m] + cn;
-        Te v = al * Te(acc[i][j][r]);
-        if (read_c) v = v + be * Te(C[addr]);
-        C[addr] = Tin(v);
-      }
-    }
-  }
+  gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * BM,
+                                                           int64_t(tn) * BN, smem);
 }
 
 template <typename Tin, typename Tc, int TILE>

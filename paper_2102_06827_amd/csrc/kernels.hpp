@@ -36,6 +36,33 @@ void gett_tile_shape(int tile, int *bm, int *bn, int *bk);
 // whether a tile variant is compiled for this dtype/compute/vector combination
 bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB);
 
+// GETT with FP32 operands split on the fly into three bfloat16 slices
+// (the six products b_p c_q with p + q <= 2 on BF16 MFMA, FP32 accumulation);
+// 64 x 64 tiles.  Requires g.dtype == 1 (FP32 storage).
+hipError_t launch_fused_bf16x3(const GettLaunch &g, hipStream_t s);
+
+// One problem of the persistent batched launch (device-resident).
+struct BatchDesc {
+  const void *A;
+  const void *B;
+  void *C;
+  GettTables t;
+  int64_t M, N, K;
+  double alpha, beta;
+  int variant;         // layoutA * 2 + layoutB, + 4 for element (non-vector) loads
+  int tilesN;          // 64 x 64 tiles along N
+};
+struct BatchItem {
+  int problem;
+  int tile;
+};
+// mode 0: native MFMA of the storage type; 1: fused BF16x3 (FP32 storage)
+hipError_t launch_batch(const BatchDesc *descs, const BatchItem *items, int64_t total, int *counter, int dtype,
+                        int mode, int grid, hipStream_t s);
+// persistent workgroups per CU for the batched kernel
+int batch_blocks_per_cu(int dtype, int mode);
+constexpr int kBatchTile = 64;
+
 // C[offCm[m] + offCn[n]] = beta * C (beta == 0 writes zeros without reading).
 hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,
                         double beta, hipStream_t s);

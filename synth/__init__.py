@@ -94,3 +94,61 @@ def config_seed(config: int, role: str) -> int:
 def to_dtype(x: np.ndarray, dtype) -> np.ndarray:
     """Round FP64 values to the storage dtype (numpy casts round to nearest-even)."""
     return np.ascontiguousarray(x.astype(dtype))
+
+
+# --------------------------------------------------------------------------
+# the same streams generated with torch (any device), for inputs too large to
+# draw on the host; bit-identical to the numpy functions above
+# --------------------------------------------------------------------------
+
+def _u64_const(x):
+    """A uint64 constant as the int64 with the same bits."""
+    return x - (1 << 64) if x >= (1 << 63) else x
+
+
+def splitmix64_torch(seed: int, n: int, device="cpu", start: int = 0):
+    import torch
+    i = torch.arange(start + 1, start + n + 1, dtype=torch.int64, device=device)
+    z = (i * _u64_const(0x9E3779B97F4A7C15)) + _u64_const(seed & ((1 << 64) - 1))
+    # logical right shifts of int64 bit patterns: arithmetic shift, then mask
+    z = (z ^ ((z >> 30) & ((1 << 34) - 1))) * _u64_const(0xBF58476D1CE4E5B9)
+    z = (z ^ ((z >> 27) & ((1 << 37) - 1))) * _u64_const(0x94D049BB133111EB)
+    z = z ^ ((z >> 31) & ((1 << 33) - 1))
+    return z
+
+
+def uniform_torch(seed: int, shape, dtype=None, device="cpu", lo: float = -1.0, hi: float = 1.0):
+    import torch
+    n = 1
+    for s in shape:
+        n *= int(s)
+    z = splitmix64_torch(seed, n, device)
+    u = ((z >> 11) & ((1 << 53) - 1)).to(torch.float64) * (2.0 ** -53)
+    x = (lo + (hi - lo) * u).reshape(tuple(shape))
+    return x if dtype is None else x.to(dtype)
+
+
+# the six contraction patterns of the batched workload: 4D = 4D x 4D, output
+# labels a, b, i, j split two and two between A and B, two summation labels
+BATCH_PATTERNS = [
+    "abij=acik*cbkj",   # block-interleaved
+    "abij=acik*bkcj",   # the CCSD-like pattern
+    "abij=abcd*cdij",   # a plain matrix product
+    "abij=ijcd*cdab",   # transposed-output product
+    "abij=ciak*bkjc",   # summation labels at both ends of A
+    "ajbi=kcia*cjkb",   # A's unit label is free; C's unit label comes from A
+]
+
+
+def batch_problems(n: int, seed: int, extents=(8, 16, 24, 32, 40, 48, 56, 64)):
+    """n problems: pattern drawn uniformly from BATCH_PATTERNS, every label's
+    extent drawn independently from `extents` (SplitMix64 stream `seed`)."""
+    z = splitmix64(seed, 8 * n)
+    out = []
+    for i in range(n):
+        w = z[8 * i: 8 * i + 8]
+        spec = BATCH_PATTERNS[int(w[0] % np.uint64(len(BATCH_PATTERNS)))]
+        labels = sorted(set(spec) - {"=", "*"})
+        ext = {ch: int(extents[int(w[1 + q] % np.uint64(len(extents)))]) for q, ch in enumerate(labels)}
+        out.append((spec, ext))
+    return out

@@ -1,0 +1,57 @@
+"""The seeded input generators: determinism, the published SplitMix64 values,
+and agreement of the numpy and torch streams."""
+import numpy as np
+import pytest
+
+import synth
+
+
+def test_splitmix64_reference_values():
+    # first outputs of SplitMix64 seeded with 0 and with 1234567, as published
+    # with the generator's reference implementation
+    assert [int(x) for x in synth.splitmix64(0, 3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [int(x) for x in synth.splitmix64(1234567, 2)] == [
+        6457827717110365317, 3203168211198807973]
+
+
+def test_same_seed_same_bits():
+    a = synth.uniform(5, (7, 9))
+    b = synth.uniform(5, (7, 9))
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, synth.uniform(6, (7, 9)))
+
+
+def test_ranges():
+    u = synth.uniform(1, (10000,))
+    assert u.min() >= -1.0 and u.max() < 1.0
+    k = synth.integers(2, (10000,))
+    assert set(np.unique(k)) == set(range(-3, 4))
+    g = synth.normal(3, (20000,))
+    assert abs(g.mean()) < 0.03 and abs(g.std() - 1.0) < 0.03
+
+
+def test_torch_stream_matches_numpy():
+    torch = pytest.importorskip("torch")
+    z_np = synth.splitmix64(99, 1000)
+    z_t = synth.splitmix64_torch(99, 1000).numpy().view(np.uint64)
+    assert np.array_equal(z_np, z_t)
+    u_np = synth.uniform(123, (11, 13))
+    u_t = synth.uniform_torch(123, (11, 13)).numpy()
+    assert np.array_equal(u_np, u_t)
+
+
+def test_decay_envelope():
+    env = synth.decay_envelope("acik", (3, 3, 2, 2), "abc", "ijk")
+    assert env[0, 0, 0, 0] == 1.0
+    assert env[2, 0, 1, 0] == pytest.approx(np.exp(-3 / 8))
+
+
+def test_batch_problems():
+    probs = synth.batch_problems(50, 7)
+    assert len(probs) == 50
+    for spec, ext in probs:
+        assert spec in synth.BATCH_PATTERNS
+        assert all(v in (8, 16, 24, 32, 40, 48, 56, 64) for v in ext.values())
+        assert set(ext) == set(spec) - {"=", "*"}
+    assert probs == synth.batch_problems(50, 7)
