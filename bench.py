@@ -1,15 +1,22 @@
 #!/usr/bin/env python3
-"""Benchmark: the CCSD-like 4D contraction C[a,b,i,j] += sum_{c,k} A[a,c,i,k] * B[b,k,c,j]
-(virtual extent 96 for a, b, c; occupied extent 32 for i, j, k; alpha = 1,
-beta = 1; operands normal(0,1) * exp(-index gap / 8)) on one MI355X.
+"""Benchmark of the permuted tensor-contraction library on one MI355X.
 
-A step is one full contraction through the C ABI (plan cached, the GETT
-kernel with its alpha/beta epilogue) with inputs resident in HBM.  The line
-printed reports GFLOP/s of the FP64 matrix-core path as `value`, plus every
-other compute mode that is built (GFLOP/s, MFMA-peak fraction and relative
-error against the CPU FP64 oracle on sampled outputs), the roofline of the
-dominant kernel timed with HIP events on its own stream, and the oracle
-itself timed on the host cores on a bounded sample of the same workload.
+Headline workload (the `value` of the printed line): the CCSD-like 4D
+contraction C[a,b,i,j] += sum_{c,k} A[a,c,i,k] * B[b,k,c,j], virtual extent 96
+(a, b, c), occupied extent 32 (i, j, k), alpha = 1, beta = 1, operands
+normal(0,1) * exp(-index gap / 8).  A step is one full contraction through the
+C ABI (plan cached) on the FP64 matrix cores, inputs resident in HBM.
+
+The same line also carries, each timed with HIP events on the launch stream:
+  modes      the headline contraction in every compute mode, with its relative
+             error against the CPU FP64 oracle on sampled outputs;
+  backward   forward + dA + dB of the same contraction (FP64 and aligned split);
+  triples    the 6D-output contraction C[a,b,c,i,j,k] = sum_d A[d,a,i,j] B[b,c,d,k]
+             (virtual 32, occupied 16), bound by writing C to HBM;
+  batch      1024 independent 4D contractions of six patterns with per-label
+             extents from {8,...,64}, forward + backward in one persistent
+             launch replayed from a HIP graph (FP32 and BF16x3);
+  roofline   of the headline kernel; cpu_baseline: the oracle on the host.
 """
 from __future__ import annotations
 
@@ -30,7 +37,6 @@ EXT = dict(a=V, b=V, c=V, i=O, j=O, k=O)
 FLOPS = 2.0 * V ** 3 * O ** 3            # 2 * M * N * K, M = N = K = 3072
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6}
 HBM_PEAK_GBS = 8000.0
-# matrix-core products per algorithmic product, per compute mode
 MODES = {
     "f64": dict(compute="f64", mfma="f64", products=1, tol=1e-12),
     "split_bf16": dict(compute="split_bf16", mfma="bf16", products=15, tol=1e-9),
@@ -40,8 +46,8 @@ MODES = {
 }
 
 
-def shape(labels):
-    return tuple(EXT[c] for c in labels)
+def shape(labels, ext=EXT):
+    return tuple(ext[c] for c in labels)
 
 
 def make_inputs():
@@ -52,11 +58,23 @@ def make_inputs():
     return A, B, C0
 
 
+def timed(fn, reps, stream):
+    """Mean milliseconds of fn() over reps runs, HIP events on `stream`."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def cpu_baseline(A, B, C0, seconds_target=15.0):
     """The oracle on the host cores over the first a-slabs of the output."""
     import oracle
     threads = oracle.max_threads()
-    # calibrate on one a-slab, then size the sample to about seconds_target
     t0 = time.perf_counter()
     oracle.contract(SPEC, A[:1], B, C0[:1], alpha=1.0, beta=1.0)
     t1 = time.perf_counter() - t0
@@ -66,8 +84,182 @@ def cpu_baseline(A, B, C0, seconds_target=15.0):
     dt = time.perf_counter() - t0
     flops = FLOPS * slabs / V
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": "output slabs a < %d of %d (%.1f%% of config 2, FP64, beta=1), %.1f s" %
+            "sample": "output slabs a < %d of %d (%.1f%% of the headline contraction, FP64, beta=1), %.1f s" %
                       (slabs, V, 100.0 * slabs / V, dt)}
+
+
+def bench_modes(comet, oracle, A, B, C0, steps, warmup, want):
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(11)
+    pts = np.stack([rng.integers(0, n, 256) for n in shape("abij")], axis=1)
+    ref64 = oracle.contract_points(SPEC, A, B, pts, C0, alpha=1.0, beta=1.0)
+    ref32 = oracle.contract_points(SPEC, A.astype(np.float32), B.astype(np.float32), pts,
+                                   C0.astype(np.float32), alpha=1.0, beta=1.0)
+    results = {}
+    for name in want:
+        cfg = MODES[name]
+        tdt = torch.float32 if cfg.get("dtype") == "f32" else torch.float64
+        Ad, Bd = torch.from_numpy(A).to(dev, tdt), torch.from_numpy(B).to(dev, tdt)
+        Cd = torch.from_numpy(C0).to(dev, tdt)
+        run = lambda: comet.contract(SPEC, Ad, Bd, Cd, alpha=1.0, beta=1.0, compute=cfg["compute"])
+        run()
+        torch.cuda.synchronize()
+        idx = torch.from_numpy(pts).to(dev)
+        got = Cd[tuple(idx.T)].double().cpu().numpy()
+        err = oracle.relerr(got, ref32 if cfg.get("dtype") == "f32" else ref64)
+        for _ in range(warmup):
+            run()
+        ms = timed(run, steps, stream)
+        gflops = FLOPS / (ms * 1e-3) / 1e9
+        results[name] = {
+            "ms": round(ms, 4), "gflops": round(gflops, 1), "mfma_dtype": cfg["mfma"],
+            "mfma_products": cfg["products"],
+            "frac_mfma_peak": round(cfg["products"] * gflops / 1e3 / PEAK_TFLOPS[cfg["mfma"]], 4),
+            "relerr_vs_oracle": err, "tol": cfg["tol"], "within_tol": bool(err <= cfg["tol"]),
+        }
+        del Ad, Bd, Cd
+        torch.cuda.empty_cache()
+    return results
+
+
+def bench_backward(comet, oracle, A, B, C0, reps):
+    """forward + dA + dB for loss = sum(C * W), FP64 and aligned split."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    W = synth.uniform(synth.config_seed(4, "W"), shape("abij"))
+    sa, sb = oracle.grad_specs(SPEC)
+    rng = np.random.default_rng(12)
+    ptsA = np.stack([rng.integers(0, n, 128) for n in shape("acik")], axis=1)
+    ptsB = np.stack([rng.integers(0, n, 128) for n in shape("bkcj")], axis=1)
+    refA = oracle.contract_points(sa, W, B, ptsA)
+    refB = oracle.contract_points(sb, A, W, ptsB)
+    out = {}
+    Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    Wd = torch.from_numpy(W).to(dev)
+    C = torch.empty(shape("abij"), dtype=torch.float64, device=dev)
+    dA = torch.empty_like(Ad)
+    dB = torch.empty_like(Bd)
+    for mode in ("f64", "split_bf16"):
+        def step():
+            comet.contract(SPEC, Ad, Bd, C, compute=mode)
+            comet.contract(sa, Wd, Bd, dA, compute=mode)
+            comet.contract(sb, Ad, Wd, dB, compute=mode)
+        step()
+        torch.cuda.synchronize()
+        eA = oracle.relerr(dA[tuple(torch.from_numpy(ptsA).to(dev).T)].cpu().numpy(), refA)
+        eB = oracle.relerr(dB[tuple(torch.from_numpy(ptsB).to(dev).T)].cpu().numpy(), refB)
+        ms = timed(step, reps, stream)
+        out[mode] = {"ms": round(ms, 4), "gflops": round(3 * FLOPS / (ms * 1e-3) / 1e9, 1),
+                     "relerr_dA": eA, "relerr_dB": eB}
+    return out
+
+
+def bench_triples(comet, oracle, reps):
+    """C[a,b,c,i,j,k] = sum_d A[d,a,i,j] * B[b,c,d,k]: writing C (1.07 GB) dominates."""
+    import torch
+    import synth
+    ext = dict(a=32, b=32, c=32, d=32, i=16, j=16, k=16)
+    spec = "abcijk=daij*bcdk"
+    A = synth.uniform(synth.config_seed(3, "A"), shape("daij", ext))
+    B = synth.uniform(synth.config_seed(3, "B"), shape("bcdk", ext))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    C = torch.empty(shape("abcijk", ext), dtype=torch.float64, device=dev)
+    flops = 2.0 * 32 ** 4 * 16 ** 3
+    nbytes = 8.0 * (A.size + B.size + C.numel())
+    rng = np.random.default_rng(13)
+    pts = np.stack([rng.integers(0, n, 256) for n in C.shape], axis=1)
+    ref = oracle.contract_points(spec, A, B, pts)
+    flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+    out = {}
+    for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2"):
+        run = lambda: comet.contract(spec, Ad, Bd, C, compute=mode)
+        run()
+        torch.cuda.synchronize()
+        err = oracle.relerr(C[tuple(torch.from_numpy(pts).to(dev).T)].cpu().numpy(), ref)
+        tot = 0.0
+        for _ in range(reps):
+            flush.fill_(1.0)     # evict the 256 MB last-level cache between runs
+            tot += timed(run, 1, stream)
+        ms = tot / reps
+        out[mode] = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+                     "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "relerr_vs_oracle": err}
+    del C, flush
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batch(comet, oracle, reps, n=1024):
+    """1024 contractions, forward + dA + dB, one persistent launch in a HIP graph."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    probs = synth.batch_problems(n, synth.config_seed(5, "A"))
+    f = torch.float32
+    tensors, problems = [], []
+    flops = 0.0
+    for i, (spec, ext) in enumerate(probs):
+        c, a, b = oracle.split_spec(spec)
+        A = synth.uniform_torch(5_000_000 + 10 * i + 1, shape(a, ext), f, dev)
+        B = synth.uniform_torch(5_000_000 + 10 * i + 2, shape(b, ext), f, dev)
+        W = synth.uniform_torch(5_000_000 + 10 * i + 4, shape(c, ext), f, dev)
+        C = torch.empty(shape(c, ext), dtype=f, device=dev)
+        dA = torch.empty_like(A)
+        dB = torch.empty_like(B)
+        sa, sb = oracle.grad_specs(spec)
+        problems += [dict(spec=spec, A=A, B=B, C=C), dict(spec=sa, A=W, B=B, C=dA),
+                     dict(spec=sb, A=A, B=W, C=dB)]
+        tensors.append((spec, A, B, W, C, dA, dB))
+        prod = 1
+        for v in ext.values():
+            prod *= v
+        flops += 3 * 2.0 * prod
+    out = {"problems": n, "contractions": 3 * n, "flops_per_step": flops}
+    ws = torch.empty(256, dtype=torch.uint8, device=dev)
+    # oracle check on a seeded sample of the lighter half of the problems
+    rng = np.random.default_rng(14)
+    cost = [np.prod(list(ext.values())) for _, ext in probs]
+    light = [i for i in range(n) if cost[i] <= np.median(cost)]
+    sample = rng.choice(light, 4, replace=False)
+    for mode in ("default", "split_bf16x3"):
+        batch = comet.Batch(problems, dtype=f, compute=mode)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            batch(workspace=ws)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            batch(workspace=ws)
+        g.replay()
+        torch.cuda.synchronize()
+        errs = []
+        for i in sample:
+            spec, A, B, W, C, dA, dB = tensors[i]
+            An, Bn, Wn = A.cpu().numpy(), B.cpu().numpy(), W.cpu().numpy()
+            errs.append(oracle.relerr(C.cpu().numpy(), oracle.contract(spec, An, Bn)))
+            gA, gB, _ = oracle.grad(spec, An, Bn, Wn)
+            errs.append(oracle.relerr(dA.cpu().numpy(), gA))
+            errs.append(oracle.relerr(dB.cpu().numpy(), gB))
+        ms = timed(g.replay, reps, torch.cuda.current_stream())
+        gflops = flops / (ms * 1e-3) / 1e9
+        mf = "f32" if mode == "default" else "bf16"
+        prods = 1 if mode == "default" else 6
+        out["f32" if mode == "default" else "split_bf16x3"] = {
+            "ms": round(ms, 3), "gflops": round(gflops, 1),
+            "frac_mfma_peak": round(prods * gflops / 1e3 / PEAK_TFLOPS[mf], 4),
+            "max_relerr_sampled": max(errs), "sampled_problems": len(sample)}
+        del g, batch
+    del tensors, problems
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -75,7 +267,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--modes", default="all", help="comma list of compute modes, or all")
+    ap.add_argument("--modes", default="all", help="comma list of compute modes for the headline, or all")
+    ap.add_argument("--only-headline", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -87,69 +280,17 @@ def main():
     import oracle
     import paper_2102_06827_amd as comet
 
-    dev = torch.device("cuda:0")
     A, B, C0 = make_inputs()
-    stream = torch.cuda.current_stream()
-    rng = np.random.default_rng(11)
-    pts = np.stack([rng.integers(0, n, 256) for n in shape("abij")], axis=1)
-    ref_pts = oracle.contract_points(SPEC, A, B, pts, C0, alpha=1.0, beta=1.0)
-    ref_pts32 = oracle.contract_points(SPEC, A.astype(np.float32), B.astype(np.float32), pts,
-                                       C0.astype(np.float32), alpha=1.0, beta=1.0)
-
-    results = {}
     want = list(MODES) if args.modes == "all" else args.modes.split(",")
-    for name in want:
-        cfg = MODES[name]
-        tdt = torch.float32 if cfg.get("dtype") == "f32" else torch.float64
-        Ad = torch.from_numpy(A).to(dev, tdt)
-        Bd = torch.from_numpy(B).to(dev, tdt)
-        C0d = torch.from_numpy(C0).to(dev, tdt)
-        Cd = C0d.clone()
-        try:
-            comet.contract(SPEC, Ad, Bd, Cd, alpha=1.0, beta=1.0, compute=cfg["compute"])
-        except comet.CometError as e:
-            if e.name == "UNSUPPORTED":
-                results[name] = {"status": "not built"}
-                continue
-            raise
-        torch.cuda.synchronize()
-        # accuracy of one result (beta = 1 on the original C0)
-        idx = torch.from_numpy(pts).to(dev)
-        got = Cd[tuple(idx.T)].double().cpu().numpy()
-        err = oracle.relerr(got, ref_pts32 if cfg.get("dtype") == "f32" else ref_pts)
-        for _ in range(args.warmup):
-            comet.contract(SPEC, Ad, Bd, Cd, alpha=1.0, beta=1.0, compute=cfg["compute"])
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            comet.contract(SPEC, Ad, Bd, Cd, alpha=1.0, beta=1.0, compute=cfg["compute"])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        gflops = FLOPS / (ms * 1e-3) / 1e9
-        peak = PEAK_TFLOPS[cfg["mfma"]]
-        results[name] = {
-            "ms_per_step": round(ms, 4),
-            "gflops": round(gflops, 1),
-            "mfma_dtype": cfg["mfma"],
-            "mfma_products": cfg["products"],
-            "frac_mfma_peak": round(cfg["products"] * gflops / 1e3 / peak, 4),
-            "relerr_vs_oracle": err,
-            "tol": cfg["tol"],
-            "within_tol": bool(err <= cfg["tol"]),
-        }
-        del Ad, Bd, C0d, Cd
-        torch.cuda.empty_cache()
-
-    head = results["f64"]
-    ms = head["ms_per_step"]
-    value = head["gflops"]
-    achieved_tflops = FLOPS / (ms * 1e-3) / 1e12
+    if "f64" not in want:
+        want = ["f64"] + want
+    modes = bench_modes(comet, oracle, A, B, C0, args.steps, args.warmup, want)
+    head = modes["f64"]
+    ms = head["ms"]
+    achieved = FLOPS / (ms * 1e-3) / 1e12
     line = {
         "metric": "GFLOP/s & % MFMA peak per contraction: FP64 vs split-BF16x3 at stated rel err",
-        "value": value,
+        "value": head["gflops"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -163,11 +304,15 @@ def main():
         "config": {"workload": "CCSD-like 4D contraction abij=acik*bkcj, V=96 O=32, alpha=1 beta=1, "
                                "decayed normal operands (M=N=K=3072)",
                    "spec": SPEC, "extents": EXT, "flops_per_step": FLOPS},
-        "roofline": {"bound": "mfma", "achieved": round(achieved_tflops, 3), "peak": PEAK_TFLOPS["f64"],
-                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_TFLOPS["f64"], 4),
-                     "traffic": None, "kernel": "gett_kernel<double,double,128,128,16,K,N>"},
-        "modes": results,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
+                     "traffic": None, "kernel": "gett_kernel<double,double,tile 3 (128x128x16, 8 waves),K,N>"},
+        "modes": modes,
     }
+    if not args.only_headline:
+        line["backward"] = bench_backward(comet, oracle, A, B, C0, reps=5)
+        line["triples"] = bench_triples(comet, oracle, reps=5)
+        line["batch"] = bench_batch(comet, oracle, reps=3)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, B, C0)
     print(json.dumps(line), flush=True)

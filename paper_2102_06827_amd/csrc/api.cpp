@@ -17,6 +17,7 @@
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "split.hpp"
+#include "tune.hpp"
 
 using namespace comet;
 
@@ -151,7 +152,13 @@ int pick_tile(const Analysis &an) {
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
                           const int64_t *sA, const int64_t *sB, const int64_t *sC, comet_dtype_t dtype,
-                          comet_compute_t compute, comet_path_t path);
+                          comet_compute_t compute, comet_path_t path, bool tune = true);
+comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
+                             const int64_t *sA, const int64_t *sB, const int64_t *sC);
+comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
+                        hipStream_t s);
+comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
+                       void *ws, size_t ws_bytes, hipStream_t s);
 
 comet_status_t build_ttgt(comet_plan_s *p) {
   Analysis &an = p->an;
@@ -240,7 +247,7 @@ comet_status_t build_ttgt(comet_plan_s *p) {
   std::vector<int64_t> gsB = tc.b_copy ? dB : reorder(tc.b_order, an.spec_b, an.strB);
   std::vector<int64_t> gsC = tc.c_copy ? dC : reorder(tc.c_order, an.spec_c, an.strC);
   comet_status_t rc = build_plan(p->gemm, gspec.c_str(), gext.data(), gsA.data(), gsB.data(), gsC.data(), an.dtype,
-                                 an.compute, COMET_PATH_GETT);
+                                 an.compute, COMET_PATH_GETT, false);
   if (rc != COMET_OK) return rc;
   p->ws_bytes = off;
   return COMET_OK;
@@ -248,7 +255,7 @@ comet_status_t build_ttgt(comet_plan_s *p) {
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
                           const int64_t *sA, const int64_t *sB, const int64_t *sC, comet_dtype_t dtype,
-                          comet_compute_t compute, comet_path_t path) {
+                          comet_compute_t compute, comet_path_t path, bool tune) {
   std::unique_ptr<comet_plan_s> p(new comet_plan_s());
   Status st = analyze(spec, extents, sA, sB, sC, dtype, compute, path, g_split_slices, p->an);
   if (!st.ok()) return fail(st);
@@ -272,6 +279,10 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
     Status s2 = split_prepare(an, p->split);
     if (!s2.ok()) return fail(s2);
     p->ws_bytes = p->split.ws_bytes;
+  }
+  if (tune && path == COMET_PATH_AUTO) {
+    comet_status_t rc2 = autotune_plan(p, spec, extents, sA, sB, sC);
+    if (rc2 != COMET_OK) return rc2;
   }
   out = std::move(p);
   return COMET_OK;
@@ -385,6 +396,112 @@ comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const
   return run_gett(p, alpha, A, B, beta, C, s);
 }
 
+// ---- autotuning -------------------------------------------------------------
+
+std::string arch_id(int device) {
+  hipDeviceProp_t prop;
+  int rt = 0;
+  std::string a = "dev";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) a = prop.gcnArchName;
+  if (hipRuntimeGetVersion(&rt) == hipSuccess) a += "/hip" + std::to_string(rt);
+  for (char &c : a)
+    if (c == '"' || c == '\\') c = '_';
+  return a;
+}
+
+// Time fn on stream s: one warm-up, then the best of three runs (microseconds).
+template <typename F>
+double time_us(F fn, hipStream_t s, bool *ok) {
+  hipEvent_t e0, e1;
+  *ok = false;
+  if (hipEventCreate(&e0) != hipSuccess) return 0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return 0;
+  }
+  double best = 1e30;
+  bool good = fn() == COMET_OK;
+  for (int r = 0; good && r < 3; ++r) {
+    (void)hipEventRecord(e0, s);
+    good = fn() == COMET_OK;
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) good = false;
+    float ms = 0;
+    if (good && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best = std::min(best, double(ms) * 1e3);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ok = good && best < 1e30;
+  return best;
+}
+
+comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
+                             const int64_t *sA, const int64_t *sB, const int64_t *sC) {
+  Analysis &an = p->an;
+  TuneCache &tc = tune_cache();
+  std::lock_guard<std::mutex> lk(tc.mutex());
+  const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
+  if (tc.mode() == 0 || !native || an.empty_out || an.empty_sum) return COMET_OK;
+  if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH")) return COMET_OK;
+  const std::string key = tune_key(an, arch_id(p->device));
+  TuneEntry best;
+  if (!(tc.mode() == 1 && tc.lookup(key, &best))) {
+    // time every compiled tile variant of the gather path, and the TTGT lowering
+    const size_t es = elem_size(an.dtype);
+    void *bufA = nullptr, *bufB = nullptr, *bufC = nullptr, *ws = nullptr;
+    hipStream_t s = nullptr;
+    std::unique_ptr<comet_plan_s> tt;
+    comet_status_t rc = build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false);
+    if (rc != COMET_OK) tt.reset();
+    const size_t wsb = tt ? tt->ws_bytes : 0;
+    bool ok = hipStreamCreate(&s) == hipSuccess && hipMalloc(&bufA, std::max<int64_t>(an.sizeA, 1) * es) == hipSuccess &&
+              hipMalloc(&bufB, std::max<int64_t>(an.sizeB, 1) * es) == hipSuccess &&
+              hipMalloc(&bufC, std::max<int64_t>(an.sizeC, 1) * es) == hipSuccess &&
+              (wsb == 0 || hipMalloc(&ws, wsb) == hipSuccess);
+    if (ok) {
+      (void)hipMemsetAsync(bufA, 0, std::max<int64_t>(an.sizeA, 1) * es, s);
+      (void)hipMemsetAsync(bufB, 0, std::max<int64_t>(an.sizeB, 1) * es, s);
+      best.us = 1e30;
+      const int keep = an.tile;
+      for (int tile = 0; tile < gett_tile_count(); ++tile) {
+        if (!gett_tile_valid(tile, an.dtype == COMET_F64 ? 0 : 1, an.compute == COMET_COMPUTE_F64 ? 0 : 1,
+                             p->vecA_tables, p->vecB_tables))
+          continue;
+        an.tile = tile;
+        bool good;
+        const comet_plan_s *pp = p.get();
+        double us = time_us([&]() { return run_gett(pp, 1.0, bufA, bufB, 0.0, bufC, s); }, s, &good);
+        if (good && us < best.us) best = TuneEntry{tile, COMET_PATH_GETT, us};
+      }
+      if (tt) {
+        bool good;
+        const comet_plan_s *pt = tt.get();
+        double us = time_us([&]() { return execute(pt, 1.0, bufA, bufB, 0.0, bufC, ws, wsb, s); }, s, &good);
+        if (good && us < best.us) best = TuneEntry{tt->gemm ? tt->gemm->an.tile : 0, COMET_PATH_TTGT, us};
+      }
+      an.tile = keep;
+      (void)hipStreamSynchronize(s);
+    }
+    if (bufA) (void)hipFree(bufA);
+    if (bufB) (void)hipFree(bufB);
+    if (bufC) (void)hipFree(bufC);
+    if (ws) (void)hipFree(ws);
+    if (s) (void)hipStreamDestroy(s);
+    if (!ok || best.us >= 1e30) return COMET_OK;   // tuning not possible: keep the heuristic
+    tc.store(key, best);
+  }
+  if (best.path == COMET_PATH_TTGT) {
+    std::unique_ptr<comet_plan_s> tt;
+    comet_status_t rc = build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false);
+    if (rc == COMET_OK) {
+      p = std::move(tt);
+      return COMET_OK;
+    }
+  }
+  if (best.tile >= 0 && best.tile < gett_tile_count()) an.tile = best.tile;
+  return COMET_OK;
+}
+
 // ---- convenience-call state: plan cache and per-device workspace ----------
 
 struct DeviceWorkspace {
@@ -420,6 +537,7 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
   const char *tl = std::getenv("COMET_GETT_TILE");
   k += "|";
   if (tl) k += tl;
+  k += "|t" + std::to_string(tune_cache().mode());
   return k;
 }
 
@@ -754,6 +872,15 @@ comet_status_t comet_batch_destroy(comet_batch_t batch) {
   return COMET_OK;
 }
 
-comet_status_t comet_autotune(const char *, int) { return fail(COMET_ERR_UNSUPPORTED, "autotuner not built yet"); }
+comet_status_t comet_autotune(const char *cache_path, int mode) {
+  if (mode < 0 || mode > 2) return fail(COMET_ERR_UNSUPPORTED, "autotune mode must be 0, 1 or 2");
+  TuneCache &tc = tune_cache();
+  {
+    std::lock_guard<std::mutex> lk(tc.mutex());
+    tc.configure(cache_path ? std::string(cache_path) : std::string(), mode);
+  }
+  // plans made under another tuning mode are not reused by the convenience call
+  return COMET_OK;
+}
 
 }  // extern "C"

@@ -236,3 +236,13 @@ def test_ttgt_identity_for_plain_gemm():
     d = comet.analyze(spec, ext_list(spec, ext), path="ttgt")
     t = d["ttgt"]
     assert t["cost"] == 0 and not t["copyA"] and not t["copyB"] and not t["copyC"]
+
+
+def test_autotune_configuration(tmp_path):
+    L = comet.lib()
+    bad = tmp_path / "corrupt.json"
+    bad.write_text("{not json at all")
+    assert L.comet_autotune(str(bad).encode(), 1) == OK      # a corrupt cache is ignored
+    assert L.comet_autotune(None, 0) == OK
+    assert L.comet_autotune(None, 3) == UNSUP
+    assert L.comet_autotune(None, -1) == UNSUP
