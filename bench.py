@@ -37,6 +37,11 @@ EXT = dict(a=V, b=V, c=V, i=O, j=O, k=O)
 FLOPS = 2.0 * V ** 3 * O ** 3            # 2 * M * N * K, M = N = K = 3072
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6}
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the headline kernel from FETCH_SIZE / WRITE_SIZE
+# counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
+# valid only for the kernel version named, null otherwise
+HEADLINE_KERNEL = "gett_kernel<double, double, 3, 0, 1, true, true>"
+HEADLINE_TRAFFIC = {"kernel": HEADLINE_KERNEL, "bytes": 958.0e6, "kernel_version": "k3"}
 MODES = {
     "f64": dict(compute="f64", mfma="f64", products=1, tol=1e-12),
     "split_bf16": dict(compute="split_bf16", mfma="bf16", products=15, tol=1e-9),
@@ -270,6 +275,8 @@ def main():
     ap.add_argument("--modes", default="all", help="comma list of compute modes for the headline, or all")
     ap.add_argument("--only-headline", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -280,7 +287,26 @@ def main():
     import oracle
     import paper_2102_06827_amd as comet
 
+    if args.copy_mb:
+        n = args.copy_mb * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}), flush=True)
+        return
+
     A, B, C0 = make_inputs()
+    # bring the clocks up before anything is timed (about one second of work)
+    Ah, Bh = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    t_end = time.perf_counter() + 1.0
+    while time.perf_counter() < t_end:
+        for _ in range(20):
+            comet.contract(SPEC, Ah, Bh)
+        torch.cuda.synchronize()
+    del Ah, Bh
+    torch.cuda.empty_cache()
     want = list(MODES) if args.modes == "all" else args.modes.split(",")
     if "f64" not in want:
         want = ["f64"] + want
@@ -306,7 +332,8 @@ def main():
                    "spec": SPEC, "extents": EXT, "flops_per_step": FLOPS},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
-                     "traffic": None, "kernel": "gett_kernel<double,double,tile 3 (128x128x16, 8 waves),K,N>"},
+                     "traffic": HEADLINE_TRAFFIC["bytes"], "kernel": HEADLINE_KERNEL,
+                     "algorithmic_bytes": 4 * 8.0 * V * V * O * O},
         "modes": modes,
     }
     if not args.only_headline:
