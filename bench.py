@@ -35,18 +35,19 @@ SPEC = "abij=acik*bkcj"
 V, O = 96, 32
 EXT = dict(a=V, b=V, c=V, i=O, j=O, k=O)
 FLOPS = 2.0 * V ** 3 * O ** 3            # 2 * M * N * K, M = N = K = 3072
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "i8": 5033.2}
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the headline kernel from FETCH_SIZE / WRITE_SIZE
 # counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
 # valid only for the kernel version named, null otherwise
-HEADLINE_KERNEL = "gett_kernel<double, double, 3, 0, 1, true, true>"
-HEADLINE_TRAFFIC = {"kernel": HEADLINE_KERNEL, "bytes": 958.0e6, "kernel_version": "k3"}
+HEADLINE_KERNEL = "gett_kernel<double, double, 9, 0, 1, true, true>"
+HEADLINE_TRAFFIC = {"kernel": HEADLINE_KERNEL, "bytes": None, "kernel_version": "k4"}
 MODES = {
     "f64": dict(compute="f64", mfma="f64", products=1, tol=1e-12),
     "split_bf16": dict(compute="split_bf16", mfma="bf16", products=15, tol=1e-9),
     "split_bf16x3": dict(compute="split_bf16x3", mfma="bf16", products=6, tol=1e-5),
     "split_fp16x2": dict(compute="split_fp16x2", mfma="f16", products=3, tol=1e-5),
+    "split_int8": dict(compute="split_int8", mfma="i8", products=21, tol=1e-9),
     "f32": dict(compute="default", mfma="f32", products=1, tol=1e-5, dtype="f32"),
 }
 
@@ -148,7 +149,7 @@ def bench_backward(comet, oracle, A, B, C0, reps):
     C = torch.empty(shape("abij"), dtype=torch.float64, device=dev)
     dA = torch.empty_like(Ad)
     dB = torch.empty_like(Bd)
-    for mode in ("f64", "split_bf16"):
+    for mode in ("f64", "split_bf16", "split_int8"):
         def step():
             comet.contract(SPEC, Ad, Bd, C, compute=mode)
             comet.contract(sa, Wd, Bd, dA, compute=mode)
@@ -182,7 +183,7 @@ def bench_triples(comet, oracle, reps):
     ref = oracle.contract_points(spec, A, B, pts)
     flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
     out = {}
-    for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2"):
+    for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2", "split_int8"):
         run = lambda: comet.contract(spec, Ad, Bd, C, compute=mode)
         run()
         torch.cuda.synchronize()

@@ -94,6 +94,12 @@ typedef enum { COMET_F64 = 0, COMET_F32 = 1 } comet_dtype_t;
  *   SPLIT_FP16X2 x = h0 + h1 * 2^-11, h0 = fp16(x), h1 = fp16((x - h0) * 2^11),
  *                rows scaled by a power of two into FP16 range (Ootomo and
  *                Yokota 2022); three FP16 MFMA products, FP32 accumulation.
+ *   SPLIT_INT8   the same exponent-aligned splitting with 7-bit integer
+ *                slices (|s| <= 127) held in int8, slice pairs with p + q < S
+ *                on the INT8 matrix cores with exact int32 accumulation per
+ *                diagonal p + q, combined in FP64 at the end (the error-free
+ *                splitting above carried out on integer units).  S comes from
+ *                comet_set_int8_slices (default 6).
  * Split modes accumulate the final result in FP64 before the alpha/beta
  * epilogue and need a workspace for the slices. */
 typedef enum {
@@ -102,7 +108,8 @@ typedef enum {
   COMET_COMPUTE_F32 = 2,
   COMET_COMPUTE_SPLIT_BF16 = 3,
   COMET_COMPUTE_SPLIT_BF16X3 = 4,
-  COMET_COMPUTE_SPLIT_FP16X2 = 5
+  COMET_COMPUTE_SPLIT_FP16X2 = 5,
+  COMET_COMPUTE_SPLIT_INT8 = 6
 } comet_compute_t;
 
 /* Which lowering a plan uses.
@@ -228,6 +235,9 @@ comet_status_t comet_autotune(const char *cache_path, int mode);
 /* Number of slices S used by COMET_COMPUTE_SPLIT_BF16 for plans created
  * afterwards; 3 <= S <= 6 (COMET_ERR_UNSUPPORTED otherwise). */
 comet_status_t comet_set_split_slices(int S);
+/* Number of slices S used by COMET_COMPUTE_SPLIT_INT8 for plans created
+ * afterwards; 3 <= S <= 8 (COMET_ERR_UNSUPPORTED otherwise). */
+comet_status_t comet_set_int8_slices(int S);
 
 const char *comet_last_error(void);
 const char *comet_version(void);

@@ -22,13 +22,14 @@ import torch
 
 __all__ = [
     "CometError", "contract", "permute", "analyze", "Plan", "Batch", "ContractFn", "contract_ad",
-    "set_split_slices", "autotune", "lib", "library_path", "COMPUTE", "PATH",
+    "set_split_slices", "set_int8_slices", "autotune", "lib", "library_path", "COMPUTE", "PATH",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libcomet.so")
 
-COMPUTE = {"default": 0, "f64": 1, "f32": 2, "split_bf16": 3, "split_bf16x3": 4, "split_fp16x2": 5}
+COMPUTE = {"default": 0, "f64": 1, "f32": 2, "split_bf16": 3, "split_bf16x3": 4, "split_fp16x2": 5,
+           "split_int8": 6}
 PATH = {"auto": 0, "gett": 1, "ttgt": 2}
 _DTYPE = {torch.float64: 0, torch.float32: 1}
 STATUS = {0: "OK", 1: "INVALID_SPEC", 2: "INVALID_SHAPE", 3: "INVALID_STRIDE", 4: "NULL_POINTER",
@@ -39,7 +40,8 @@ SYMBOLS = [
     "comet_contract", "comet_plan_create", "comet_plan_create_ex", "comet_plan_workspace_size",
     "comet_plan_execute", "comet_plan_destroy", "comet_plan_describe", "comet_analyze",
     "comet_batch_create", "comet_batch_workspace_size", "comet_batch_execute", "comet_batch_destroy",
-    "comet_permute", "comet_autotune", "comet_set_split_slices", "comet_last_error", "comet_version",
+    "comet_permute", "comet_autotune", "comet_set_split_slices", "comet_set_int8_slices", "comet_last_error",
+    "comet_version",
 ]
 
 
@@ -100,6 +102,7 @@ def lib():
         L.comet_permute.argtypes = [S, I64P, I, D, P, I64P, D, P, I64P, P]
         L.comet_autotune.argtypes = [S, I]
         L.comet_set_split_slices.argtypes = [I]
+        L.comet_set_int8_slices.argtypes = [I]
         L.comet_last_error.restype = ctypes.c_char_p
         L.comet_version.restype = ctypes.c_char_p
         for name in SYMBOLS:
@@ -231,6 +234,10 @@ def analyze_status(spec, extents, strides_A=None, strides_B=None, strides_C=None
 
 def set_split_slices(S: int):
     _check(lib().comet_set_split_slices(int(S)))
+
+
+def set_int8_slices(S: int):
+    _check(lib().comet_set_int8_slices(int(S)))
 
 
 def autotune(cache_path=None, mode=1):

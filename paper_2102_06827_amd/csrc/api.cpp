@@ -25,6 +25,7 @@ namespace {
 
 thread_local std::string g_last_error;
 int g_split_slices = 5;
+int g_int8_slices = 6;
 std::mutex g_mu;
 
 comet_status_t fail(comet_status_t code, const std::string &msg) {
@@ -134,20 +135,47 @@ comet_status_t upload_tables(comet_plan_s *p) {
   return COMET_OK;
 }
 
-int pick_tile(const Analysis &an) {
+// Tile choice without timing: for every compiled tile the modeled time is
+//   ceil(tiles / (CUs * resident)) * resident * BM * BN / throughput
+// (rounds of resident workgroups; a CU running `resident` workgroups of the
+// tile delivers `throughput` output elements per unit time).  Residency and
+// throughput were measured on MI355X for each tile on a 3072^3 contraction;
+// only their ratios matter.  The autotuner replaces this with timings.
+struct TileModel {
+  int resident;
+  double throughput;
+};
+constexpr TileModel kModelF64[] = {{1, 20117}, {3, 19770}, {1, 18175}, {1, 30070}, {1, 33670},
+                                   {2, 23569}, {2, 22224}, {2, 19873}, {1, 21906}, {1, 29570}};
+constexpr TileModel kModelF32[] = {{3, 48231}, {5, 44152}, {1, 41259}, {2, 60670}, {2, 52433},
+                                   {4, 67818}, {4, 68556}};
+
+int pick_tile(const Analysis &an, int cus, bool vecA, bool vecB) {
   const char *env = std::getenv("COMET_GETT_TILE");
   if (env && *env) {
     int t = std::atoi(env);
     if (t >= 0 && t < gett_tile_count()) return t;
   }
-  // Large problems: 128 x 128 tiles over 8 waves (two per SIMD) for FP64 and
-  // 64 x 128 tiles for FP32, the fastest shapes measured on a 3072^3
-  // contraction; small problems take 64 x 64 tiles so more workgroups exist.
-  const int64_t big_tiles = ((an.m + 127) / 128) * ((an.n + 127) / 128);
-  if (big_tiles < 256) return 1;
-  const bool same = (an.dtype == COMET_F64) == (an.compute == COMET_COMPUTE_F64);
-  if (!same) return 0;
-  return an.compute == COMET_COMPUTE_F64 ? 3 : 6;
+  const int dt = an.dtype == COMET_F64 ? 0 : 1, cp = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  const bool f64 = cp == 0;
+  const int nmodel = f64 ? int(sizeof(kModelF64) / sizeof(kModelF64[0])) : int(sizeof(kModelF32) / sizeof(kModelF32[0]));
+  int best = 1;
+  double best_t = 1e300;
+  for (int t = 0; t < gett_tile_count() && t < nmodel; ++t) {
+    if (!gett_tile_valid(t, dt, cp, vecA, vecB)) continue;
+    const TileModel &tm = f64 ? kModelF64[t] : kModelF32[t];
+    int bm, bn, bk;
+    gett_tile_shape(t, &bm, &bn, &bk);
+    const int64_t tiles = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+    const int64_t slots = int64_t(std::max(cus, 1)) * tm.resident;
+    const int64_t rounds = (tiles + slots - 1) / slots;
+    const double time = double(rounds) * tm.resident * bm * bn / tm.throughput;
+    if (time < best_t * 0.999) {
+      best_t = time;
+      best = t;
+    }
+  }
+  return best;
 }
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
@@ -257,11 +285,12 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
                           const int64_t *sA, const int64_t *sB, const int64_t *sC, comet_dtype_t dtype,
                           comet_compute_t compute, comet_path_t path, bool tune) {
   std::unique_ptr<comet_plan_s> p(new comet_plan_s());
-  Status st = analyze(spec, extents, sA, sB, sC, dtype, compute, path, g_split_slices, p->an);
+  Status st = analyze(spec, extents, sA, sB, sC, dtype, compute, path, g_split_slices, p->an, g_int8_slices);
   if (!st.ok()) return fail(st);
   Analysis &an = p->an;
   HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
-  an.tile = pick_tile(an);
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) cus = 256;
   if (an.path == COMET_PATH_TTGT && !an.empty_out && !an.empty_sum) {
     comet_status_t rc = build_ttgt(p.get());
     if (rc != COMET_OK) return rc;
@@ -271,8 +300,10 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   const int VEC = an.dtype == COMET_F64 ? 2 : 4;
   p->vecA_tables = tables_vec_ok(an.offAm, an.offAk, an.layoutA, an.runAm, an.runAk, VEC);
   p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC);
+  an.tile = pick_tile(an, cus, p->vecA_tables, p->vecB_tables);
+  if (p->gemm) p->gemm->an.tile = pick_tile(p->gemm->an, cus, p->gemm->vecA_tables, p->gemm->vecB_tables);
   bool split = an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
-               an.compute == COMET_COMPUTE_SPLIT_FP16X2;
+               an.compute == COMET_COMPUTE_SPLIT_FP16X2 || an.compute == COMET_COMPUTE_SPLIT_INT8;
   // FP32 storage in BF16x3: split on the fly inside the gather kernel
   p->fused3 = an.compute == COMET_COMPUTE_SPLIT_BF16X3 && an.dtype == COMET_F32;
   if (split && !p->fused3 && !an.empty_out && !an.empty_sum) {
@@ -353,7 +384,7 @@ comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const
     return COMET_OK;
   }
   if (an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
-      an.compute == COMET_COMPUTE_SPLIT_FP16X2) {
+      an.compute == COMET_COMPUTE_SPLIT_FP16X2 || an.compute == COMET_COMPUTE_SPLIT_INT8) {
     const void *Ak = an.swapped ? B : A, *Bk = an.swapped ? A : B;
     HIP_TRY(split_execute(an, p->split, p->t, alpha, Ak, Bk, beta, C, ws, s), "split launch");
     return COMET_OK;
@@ -527,7 +558,7 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
   add(sB, rb);
   add(sC, rc);
   k += "|" + std::to_string(dtype) + "|" + std::to_string(compute) + "|" + std::to_string(dev) + "|" +
-       std::to_string(g_split_slices);
+       std::to_string(g_split_slices) + "|" + std::to_string(g_int8_slices);
   const char *env = std::getenv("COMET_FORCE_PATH");
   k += "|";
   if (env) k += env;
@@ -556,11 +587,18 @@ comet_status_t comet_set_split_slices(int S) {
   return COMET_OK;
 }
 
+comet_status_t comet_set_int8_slices(int S) {
+  if (S < 3 || S > 8) return fail(COMET_ERR_UNSUPPORTED, "int8 split slices must be within 3..8");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_int8_slices = S;
+  return COMET_OK;
+}
+
 comet_status_t comet_analyze(const char *spec, const int64_t *extents, const int64_t *strides_A,
                              const int64_t *strides_B, const int64_t *strides_C, comet_dtype_t dtype,
                              comet_compute_t compute, comet_path_t path, char *buf, size_t len) {
   Analysis an;
-  Status st = analyze(spec, extents, strides_A, strides_B, strides_C, dtype, compute, path, g_split_slices, an);
+  Status st = analyze(spec, extents, strides_A, strides_B, strides_C, dtype, compute, path, g_split_slices, an, g_int8_slices);
   if (!st.ok()) return fail(st);
   std::string js = describe_json(an);
   if (buf && len) {
@@ -631,7 +669,7 @@ comet_status_t comet_contract(const char *spec, const int64_t *extents, comet_dt
     // no usable device: still report argument errors first
     Analysis an;
     Status vs = analyze(spec, extents, strides_A, strides_B, strides_C, dtype, compute, COMET_PATH_AUTO,
-                        g_split_slices, an);
+                        g_split_slices, an, g_int8_slices);
     if (!vs.ok()) return fail(vs);
     return hip_fail(de, "hipGetDevice");
   }
@@ -755,7 +793,7 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
   for (int i = 0; i < n; ++i) {
     const comet_problem_t &pr = problems[i];
     Status st = analyze(pr.spec, pr.extents, pr.strides_A, pr.strides_B, pr.strides_C, dtype, compute,
-                        COMET_PATH_GETT, g_split_slices, an[i]);
+                        COMET_PATH_GETT, g_split_slices, an[i], g_int8_slices);
     if (!st.ok()) return fail(st.code, "problem " + std::to_string(i) + ": " + st.msg);
     const Analysis &a = an[i];
     int mode;

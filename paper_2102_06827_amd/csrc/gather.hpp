@@ -65,9 +65,12 @@ __device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int
   *tn = in / gsize;
 }
 
-// One operand tile: R rows (m for A, n for B) by BK summation indices, held in
-// LDS as s[k][r] (r contiguous, row pitch R + PAD).  LAYOUT 0: the operand is
-// contiguous along k in memory, threads walk k; LAYOUT 1: contiguous along r.
+// One operand tile: R rows (m for A, n for B) by BK summation indices.
+// LAYOUT 0: the operand is contiguous along k in memory; threads walk k and
+// the LDS tile keeps k contiguous, s[r][k] with pitch BK + KPAD, so a thread's
+// vector is one 16-byte LDS store.  LAYOUT 1: contiguous along r; s[k][r]
+// with pitch R + PAD.  The pads make the strided 16-lane MFMA fragment reads
+// of either layout hit distinct banks.
 //
 // Loads are branch-free: an out-of-range element is fetched from a clamped,
 // valid address and replaced by zero afterwards, so no load sits under a
@@ -80,7 +83,12 @@ struct Loader {
   static constexpr int P = R * BK / (VEC * NT);
   static_assert(P >= 1 && P * VEC * NT == R * BK, "tile does not split evenly over the workgroup");
   static constexpr int PAD = 4;
-  static constexpr int LDR = R + PAD;
+  static constexpr int LDR = R + PAD;                       // LAYOUT 1 pitch
+  static constexpr int KPAD = sizeof(Tc) == 8 ? 2 : 4;       // 16 bytes
+  static constexpr int LDK = BK + KPAD;                      // LAYOUT 0 pitch
+  static constexpr int ELEMS = LAYOUT == 0 ? R * LDK : BK * LDR;   // per LDS buffer
+  // LDS position of element (row r, summation index k)
+  static __device__ __forceinline__ int idx(int r, int k) { return LAYOUT == 0 ? r * LDK + k : k * LDR + r; }
   // K-table entries held per pass: one per vector, or one per element when
   // a K-contiguous operand is read element by element
   static constexpr int NKO = (LAYOUT == 0) ? VEC : 1;
@@ -191,13 +199,22 @@ struct Loader {
   __device__ __forceinline__ void store(Tc *s) const {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
+      Tc x[VEC];
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) {
-        const Tc x = ((vmask[p] >> i) & 1u) ? Tc(v[p][i]) : Tc(0);
-        if (LAYOUT == 0)
-          s[(kk[p] + i) * LDR + rr[p]] = x;
-        else
-          s[kk[p] * LDR + rr[p] + i] = x;
+      for (int i = 0; i < VEC; ++i) x[i] = ((vmask[p] >> i) & 1u) ? Tc(v[p][i]) : Tc(0);
+      // VEC consecutive elements along the contiguous dimension: one vector store
+      // when they fill 16 bytes, element stores otherwise (FP32 arithmetic on
+      // FP64 storage)
+      Tc *dst = s + (LAYOUT == 0 ? idx(rr[p], kk[p]) : idx(rr[p], kk[p]));
+      if constexpr (VEC * sizeof(Tc) == 16) {
+        typedef Tc vec_t __attribute__((ext_vector_type(VEC)));
+        vec_t w;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) w[i] = x[i];
+        *reinterpret_cast<vec_t *>(dst) = w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) dst[i] = x[i];
       }
     }
   }
@@ -207,7 +224,7 @@ struct Loader {
 // Elements of LDS (of type Tc) one gett_tile call needs.
 template <typename Tin, typename Tc, int BM, int BN, int BK, int NT, int LA, int LB, bool VA, bool VB>
 constexpr int gett_lds_elems() {
-  return 2 * BK * (Loader<Tin, Tc, BM, BK, LA, VA, NT>::LDR + Loader<Tin, Tc, BN, BK, LB, VB, NT>::LDR);
+  return 2 * (Loader<Tin, Tc, BM, BK, LA, VA, NT>::ELEMS + Loader<Tin, Tc, BN, BK, LB, VB, NT>::ELEMS);
 }
 
 // One BM x BN output tile at (m0, n0): gather A and B through the offset
@@ -225,8 +242,8 @@ __device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int FM = WM / 16, FN = WN / 16;
   static_assert(FM * 16 == WM && FN * 16 == WN, "wave tile must be a multiple of 16");
-  Tc *sA[2] = {smem, smem + BK * LoadA::LDR};
-  Tc *sB[2] = {smem + 2 * BK * LoadA::LDR, smem + 2 * BK * LoadA::LDR + BK * LoadB::LDR};
+  Tc *sA[2] = {smem, smem + LoadA::ELEMS};
+  Tc *sB[2] = {smem + 2 * LoadA::ELEMS, smem + 2 * LoadA::ELEMS + LoadB::ELEMS};
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -269,9 +286,9 @@ __device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *
       const int kr = k4 + (lane >> 4);
       Tc af[FM], bf[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = a_s[kr * LoadA::LDR + wm0 + i * 16 + (lane & 15)];
+      for (int i = 0; i < FM; ++i) af[i] = a_s[LoadA::idx(wm0 + i * 16 + (lane & 15), kr)];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = b_s[kr * LoadB::LDR + wn0 + j * 16 + (lane & 15)];
+      for (int j = 0; j < FN; ++j) bf[j] = b_s[LoadB::idx(wn0 + j * 16 + (lane & 15), kr)];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll

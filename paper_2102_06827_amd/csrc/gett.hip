@@ -46,6 +46,9 @@ constexpr TileShape kTiles[] = {
     {256, 128, 16, 4, 2},   // 4: 8 waves, 64 x 64 per wave
     {128, 64, 16, 2, 2},    // 5
     {64, 128, 16, 2, 2},    // 6
+    {96, 96, 16, 2, 2},     // 7: FP64 only; 3072^2 outputs -> 4 tiles per CU
+    {128, 96, 32, 4, 2},    // 8: FP64 only; 3072^2 outputs -> 3 tiles per CU
+    {192, 96, 32, 4, 2},    // 9: FP64 only; 3072^2 outputs -> 2 tiles per CU
 };
 constexpr int kNumTiles = int(sizeof(kTiles) / sizeof(kTiles[0]));
 
@@ -56,7 +59,7 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
   constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
   constexpr int NT = 64 * WGM * WGN;
-  __shared__ Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
   int tm, tn;
   tile_coords(blockIdx.x, tilesM, tilesN, &tm, &tn);
   gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * BM,
@@ -123,6 +126,9 @@ hipError_t launch_tc(const GettLaunch &g, hipStream_t s) {
     case 4: if constexpr (same) return launch_t<Tin, Tc, 4>(g, s); else return hipErrorInvalidValue;
     case 5: if constexpr (same) return launch_t<Tin, Tc, 5>(g, s); else return hipErrorInvalidValue;
     case 6: if constexpr (same) return launch_t<Tin, Tc, 6>(g, s); else return hipErrorInvalidValue;
+    case 7: if constexpr (same) return launch_t<Tin, Tc, 7>(g, s); else return hipErrorInvalidValue;
+    case 8: if constexpr (same) return launch_t<Tin, Tc, 8>(g, s); else return hipErrorInvalidValue;
+    case 9: if constexpr (same) return launch_t<Tin, Tc, 9>(g, s); else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

@@ -319,18 +319,18 @@ PermuteDesc make_permute(const std::string &out_labels, const std::vector<int64_
 
 Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_A, const int64_t *strides_B,
                const int64_t *strides_C, comet_dtype_t dtype, comet_compute_t compute, comet_path_t path,
-               int split_slices, Analysis &an) {
+               int split_slices, Analysis &an, int int8_slices) {
   an = Analysis();
   Status st = parse_spec(spec, an);
   if (!st.ok()) return st;
   if (dtype != COMET_F64 && dtype != COMET_F32) return Status::error(COMET_ERR_UNSUPPORTED, "unknown dtype");
-  if (compute < COMET_COMPUTE_DEFAULT || compute > COMET_COMPUTE_SPLIT_FP16X2)
+  if (compute < COMET_COMPUTE_DEFAULT || compute > COMET_COMPUTE_SPLIT_INT8)
     return Status::error(COMET_ERR_UNSUPPORTED, "unknown compute mode");
   if (path < COMET_PATH_AUTO || path > COMET_PATH_TTGT) return Status::error(COMET_ERR_UNSUPPORTED, "unknown path");
   an.dtype = dtype;
   an.compute = compute == COMET_COMPUTE_DEFAULT ? (dtype == COMET_F64 ? COMET_COMPUTE_F64 : COMET_COMPUTE_F32)
                                                 : compute;
-  an.split_slices = split_slices;
+  an.split_slices = compute == COMET_COMPUTE_SPLIT_INT8 ? int8_slices : split_slices;
   if (!an.labels.empty() && !extents) return Status::error(COMET_ERR_NULL_POINTER, "extents is NULL");
   an.extents.assign(extents, extents + an.labels.size());
   for (size_t i = 0; i < an.labels.size(); ++i)
@@ -476,7 +476,7 @@ static void json_dims(std::ostringstream &o, const char *name, const std::vector
 }
 
 std::string describe_json(const Analysis &an) {
-  static const char *cnames[] = {"default", "f64", "f32", "split_bf16", "split_bf16x3", "split_fp16x2"};
+  static const char *cnames[] = {"default", "f64", "f32", "split_bf16", "split_bf16x3", "split_fp16x2", "split_int8"};
   std::ostringstream o;
   o << "{\"spec\":\"" << an.spec_c << "=" << an.spec_a << "*" << an.spec_b << "\"";
   o << ",\"dtype\":\"" << (an.dtype == COMET_F64 ? "f64" : "f32") << "\"";

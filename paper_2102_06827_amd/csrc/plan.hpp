@@ -90,10 +90,12 @@ struct Analysis {
 // Parse "C=A*B".  Fills spec_c/a/b and the distinct label list.
 Status parse_spec(const char *spec, Analysis &an);
 
-// Full host analysis.  `split_slices` applies to SPLIT_BF16.
+// Full host analysis.  `split_slices` applies to SPLIT_BF16, `int8_slices`
+// to SPLIT_INT8.
 Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_A,
                const int64_t *strides_B, const int64_t *strides_C, comet_dtype_t dtype,
-               comet_compute_t compute, comet_path_t path, int split_slices, Analysis &an);
+               comet_compute_t compute, comet_path_t path, int split_slices, Analysis &an,
+               int int8_slices = 6);
 
 // TTGT permutation choice by the cost model (Section 6): every valid
 // flattening of A, B and C, with and without exchanging A and B, costed by

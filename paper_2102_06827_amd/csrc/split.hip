@@ -19,6 +19,13 @@
 //     accumulator.
 //   mode 2, FP16x2 (Ootomo and Yokota): h0 = fp16(x'), h1 = fp16((x' - h0) 2^11);
 //     h0 g0 in one FP32 accumulator, h0 g1 + h1 g0 in another scaled by 2^-11.
+//   mode 3, aligned INT8: as mode 0 with 7-bit slices s_p = trunc(128 *
+//     remainder), |s_p| <= 127, stored as int8 and multiplied on
+//     v_mfma_i32_16x16x64_i8.  Each diagonal d = p + q has its own int32
+//     accumulator, exact while S * 127^2 * (indices summed) < 2^31; a launch
+//     sums at most 8192 indices and combines the diagonals in FP64 (times
+//     2^-7(d+2)) in its epilogue; longer summations take several launches,
+//     each adding into C.
 //
 // Rows are scaled by powers of two in every mode (exact), which keeps the
 // 16-bit slices in range; the epilogue multiplies by 2^(eA[m] + eB[n]).
@@ -46,6 +53,9 @@ constexpr int kExpNone = -(1 << 20);   // exponent of an all-zero row
 template <typename ST> struct Vec8;
 template <> struct Vec8<__bf16> { typedef bf16x8 type; };
 template <> struct Vec8<_Float16> { typedef f16x8 type; };
+typedef signed char i8x8 __attribute__((ext_vector_type(8)));
+template <> struct Vec8<signed char> { typedef i8x8 type; };
+typedef int i4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4_t mfma_slice(bf16x8 a, bf16x8 b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -158,10 +168,18 @@ __global__ __launch_bounds__(PT) void split_pack_kernel(const Tin *__restrict__ 
         sl[p][j] = b;
         xs = xs - double(float(b));
       }
-    } else {
+    } else if (MODE == 2) {
       const ST h0 = ST(float(xs));
       sl[0][j] = h0;
       sl[1][j] = ST(float((xs - double(float(h0))) * 2048.0));
+    } else {
+#pragma unroll
+      for (int p = 0; p < S; ++p) {
+        const double tt = xs * 128.0;
+        const double s = trunc(tt);                                   // |s| <= 127
+        sl[p][j] = ST(int(s));
+        xs = tt - s;
+      }
     }
   }
 #pragma unroll
@@ -186,7 +204,13 @@ template <int MODE, int S> struct Pairs {
 constexpr int GBM = 128, GBN = 64, GBK = 32;   // block tile
 constexpr int GWM = 4, GWN = 2;                // wave grid
 constexpr int GNT = 64 * GWM * GWN;
-constexpr int GLDK = GBK + 8;                  // LDS pitch (80 bytes: conflict-free 16-byte reads)
+
+// LDS position (in 16-bit elements) of the 8-element chunk c (0..3) of tile
+// row r: rows are 64 bytes, unpadded, and the chunk index is XOR-swizzled by
+// (r / 4) mod 4.  Sixteen lanes that store four consecutive rows, and sixteen
+// lanes that read one chunk of sixteen consecutive rows (an MFMA fragment),
+// then hit 64 distinct banks.
+__device__ __forceinline__ int sw(int r, int c) { return r * GBK + ((c ^ ((r >> 2) & 3)) << 3); }
 
 template <typename ST, typename Tout, int MODE, int S>
 __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ As, const ST *__restrict__ Bs,
@@ -202,8 +226,10 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
   constexpr int NVA = S * GBM * (GBK / 8);           // 16-byte vectors per stage
   constexpr int NVB = S * GBN * (GBK / 8);
   constexpr int NV = (NVA + NVB + GNT - 1) / GNT;    // per thread
-  __shared__ ST sA[S][GBM][GLDK];
-  __shared__ ST sB[S][GBN][GLDK];
+  constexpr int STAGE = S * (GBM + GBN) * GBK;       // elements per LDS buffer
+  // two buffers when they fit in LDS (S <= 6 with 64-byte rows), else one
+  constexpr int NBUF = 2 * STAGE * int(sizeof(ST)) <= 150 * 1024 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) ST smem[NBUF * STAGE];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // XCD-aware tile order, as in the gather kernel
@@ -232,6 +258,10 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
       for (int a = 0; a < PP::NACC; ++a) acc[a][i][j] = f4_t{0, 0, 0, 0};
     }
 
+  // a buffer holds A slices [S][GBM rows] then B slices [S][GBN rows]
+  auto a_at = [&](ST *buf, int p, int row, int c) { return buf + (p * GBM) * GBK + sw(row, c); };
+  auto b_at = [&](ST *buf, int p, int row, int c) { return buf + S * GBM * GBK + (p * GBN) * GBK + sw(row, c); };
+
   v8 pre[NV];
   const int64_t nst = Kp / GBK;
   auto gload = [&](int64_t st) {
@@ -249,17 +279,17 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
       }
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](ST *buf) {
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
       const int v = tid + u * GNT;
       if (v < NVA) {
-        const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, kc = (rem % 4) * 8;
-        *reinterpret_cast<v8 *>(&sA[p][row][kc]) = pre[u];
+        const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, c = rem % 4;
+        *reinterpret_cast<v8 *>(a_at(buf, p, row, c)) = pre[u];
       } else if (v < NVA + NVB) {
         const int w = v - NVA;
-        const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, kc = (rem % 4) * 8;
-        *reinterpret_cast<v8 *>(&sB[p][row][kc]) = pre[u];
+        const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, c = rem % 4;
+        *reinterpret_cast<v8 *>(b_at(buf, p, row, c)) = pre[u];
       }
     }
   };
@@ -275,22 +305,19 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
           acc[a][i][j] = f4_t{0, 0, 0, 0};
         }
   };
-
-  gload(0);
-  lstore();
-  __syncthreads();
-  for (int64_t st = 0; st < nst; ++st) {
-    gload(st + 1);
+  auto compute = [&](ST *buf) {
     v8 bF[S][FN];
 #pragma unroll
     for (int q = 0; q < S; ++q)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bF[q][j] = *reinterpret_cast<const v8 *>(&sB[q][wn0 + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+      for (int j = 0; j < FN; ++j)
+        bF[q][j] = *reinterpret_cast<const v8 *>(b_at(buf, q, wn0 + j * 16 + (lane & 15), lane >> 4));
 #pragma unroll
     for (int p = 0; p < S; ++p) {
       v8 aF[FM];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) aF[i] = *reinterpret_cast<const v8 *>(&sA[p][wm0 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+      for (int i = 0; i < FM; ++i)
+        aF[i] = *reinterpret_cast<const v8 *>(a_at(buf, p, wm0 + i * 16 + (lane & 15), lane >> 4));
 #pragma unroll
       for (int q = 0; q < S; ++q) {
         if (PP::use(p, q)) {
@@ -302,10 +329,25 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
         }
       }
     }
+  };
+
+  gload(0);
+  lstore(smem);
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    ST *cur = smem + (NBUF == 2 ? int(st & 1) * STAGE : 0);
+    gload(st + 1);
+    compute(cur);
     if (PP::FOLD > 0 && ((st + 1) % (PP::FOLD > 0 ? PP::FOLD : 1)) == 0) fold();
-    __syncthreads();
-    lstore();
-    __syncthreads();
+    if constexpr (NBUF == 2) {
+      // the other buffer was last read before the previous barrier
+      lstore(smem + int((st + 1) & 1) * STAGE);
+      __syncthreads();
+    } else {
+      __syncthreads();
+      lstore(smem);
+      __syncthreads();
+    }
   }
   fold();
 
@@ -327,6 +369,161 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
         const int em = eA[m];
         const int64_t addr = offCm[m] + cn;
         const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(acc64[i][j][r], em + en);
+        Te v = Te(alpha * prod);
+        if (read_c) v = v + Te(beta) * Te(C[addr]);
+        C[addr] = Tout(v);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------ INT8 slice-pair GEMM --
+
+constexpr int IBK = 64;          // summation indices per stage (one 16x16x64 MFMA)
+constexpr int IKC = 8192;        // summation indices per launch: 8 * 127^2 * 8192 < 2^31
+
+// byte position of the 16-byte chunk c (0..3) of tile row r (64-byte rows),
+// swizzled as in sw()
+__device__ __forceinline__ int sw8(int r, int c) { return r * IBK + ((c ^ ((r >> 2) & 3)) << 4); }
+
+template <typename Tout, int S>
+__global__ __launch_bounds__(GNT) void split_gemm_i8_kernel(const signed char *__restrict__ As,
+                                                             const signed char *__restrict__ Bs,
+                                                             const int *__restrict__ eA, const int *__restrict__ eB,
+                                                             Tout *__restrict__ C, const int64_t *__restrict__ offCm,
+                                                             const int64_t *__restrict__ offCn, int64_t M, int64_t N,
+                                                             int64_t Mp, int64_t Np, int64_t Kp, int64_t k_begin,
+                                                             int64_t k_len, double alpha, double beta, int tilesM,
+                                                             int tilesN) {
+  constexpr int WM = GBM / GWM, WN = GBN / GWN;      // 32 x 32
+  constexpr int FM = WM / 16, FN = WN / 16;          // 2 x 2
+  constexpr int NVA = S * GBM * (IBK / 16);          // 16-byte vectors per stage
+  constexpr int NVB = S * GBN * (IBK / 16);
+  constexpr int NV = (NVA + NVB + GNT - 1) / GNT;
+  constexpr int STAGE = S * (GBM + GBN) * IBK;       // bytes per LDS buffer
+  constexpr int NBUF = 2 * STAGE <= 150 * 1024 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) signed char smem[NBUF * STAGE];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tm, tn;
+  {
+    const int total = tilesM * tilesN, X = 8, bid = blockIdx.x;
+    const int xcd = bid % X, local = bid / X, q = total / X, rem = total % X;
+    const int id = xcd * q + (xcd < rem ? xcd : rem) + local;
+    const int G = 8, per = G * tilesN, group = id / per, first = group * G;
+    const int gsize = tilesM - first < G ? tilesM - first : G;
+    const int in = id - group * per;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int64_t m0 = int64_t(tm) * GBM, n0 = int64_t(tn) * GBN;
+  const int wm0 = (wave / GWN) * WM, wn0 = (wave % GWN) * WN;
+
+  i4_t acc[S][FM][FN];       // one exact int32 accumulator per diagonal p + q
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int d = 0; d < S; ++d) acc[d][i][j] = i4_t{0, 0, 0, 0};
+  auto a_at = [&](signed char *buf, int p, int row, int c) { return buf + (p * GBM) * IBK + sw8(row, c); };
+  auto b_at = [&](signed char *buf, int p, int row, int c) {
+    return buf + S * GBM * IBK + (p * GBN) * IBK + sw8(row, c);
+  };
+  i4_t pre[NV];
+  const int64_t nst = k_len / IBK;
+  auto gload = [&](int64_t st) {
+    const int64_t k0 = k_begin + (st < nst ? st : nst - 1) * IBK;
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int v = tid + u * GNT;
+      if (v < NVA) {
+        const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, kc = (rem % 4) * 16;
+        pre[u] = *reinterpret_cast<const i4_t *>(As + (int64_t(p) * Mp + m0 + row) * Kp + k0 + kc);
+      } else if (v < NVA + NVB) {
+        const int w = v - NVA;
+        const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, kc = (rem % 4) * 16;
+        pre[u] = *reinterpret_cast<const i4_t *>(Bs + (int64_t(p) * Np + n0 + row) * Kp + k0 + kc);
+      }
+    }
+  };
+  auto lstore = [&](signed char *buf) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int v = tid + u * GNT;
+      if (v < NVA) {
+        const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, c = rem % 4;
+        *reinterpret_cast<i4_t *>(a_at(buf, p, row, c)) = pre[u];
+      } else if (v < NVA + NVB) {
+        const int w = v - NVA;
+        const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, c = rem % 4;
+        *reinterpret_cast<i4_t *>(b_at(buf, p, row, c)) = pre[u];
+      }
+    }
+  };
+  auto compute = [&](signed char *buf) {
+    i4_t bF[S][FN];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        bF[q][j] = *reinterpret_cast<const i4_t *>(b_at(buf, q, wn0 + j * 16 + (lane & 15), lane >> 4));
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      i4_t aF[FM];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        aF[i] = *reinterpret_cast<const i4_t *>(a_at(buf, p, wm0 + i * 16 + (lane & 15), lane >> 4));
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        if (p + q <= S - 1) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[p + q][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aF[i], bF[q][j], acc[p + q][i][j], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  gload(0);
+  lstore(smem);
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    signed char *cur = smem + (NBUF == 2 ? int(st & 1) * STAGE : 0);
+    gload(st + 1);
+    compute(cur);
+    if constexpr (NBUF == 2) {
+      lstore(smem + int((st + 1) & 1) * STAGE);
+      __syncthreads();
+    } else {
+      __syncthreads();
+      lstore(smem);
+      __syncthreads();
+    }
+  }
+
+  typedef typename std::conditional<sizeof(Tout) == 8, double, float>::type Te;
+  const bool read_c = beta != 0.0;
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
+    if (n >= N) continue;
+    const int64_t cn = offCn[n];
+    const int en = eB[n];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= M) continue;
+        const int em = eA[m];
+        const int64_t addr = offCm[m] + cn;
+        double sum = 0.0;
+#pragma unroll
+        for (int d = S - 1; d >= 0; --d) sum += double(acc[d][i][j][r]) * ldexp(1.0, -7 * (d + 2));
+        const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(sum, em + en);
         Te v = Te(alpha * prod);
         if (read_c) v = v + Te(beta) * Te(C[addr]);
         C[addr] = Tout(v);
@@ -388,9 +585,19 @@ hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &
       hipSuccess)
     return err;
   const int tilesM = int(sp.Mp / GBM), tilesN = int(sp.Np / GBN);
-  hipLaunchKernelGGL((split_gemm_kernel<ST, Tin, MODE, S>), dim3(tilesM * tilesN), dim3(GNT), 0, s, As, Bs, eA, eB,
-                     static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp, sp.Np, sp.Kp, alpha, beta, tilesM,
-                     tilesN);
+  if constexpr (MODE == 3) {
+    // exact int32 diagonal sums over at most IKC indices per launch; later
+    // launches add into C
+    for (int64_t k0 = 0; k0 < sp.Kp; k0 += IKC) {
+      const int64_t len = sp.Kp - k0 < IKC ? sp.Kp - k0 : IKC;
+      hipLaunchKernelGGL((split_gemm_i8_kernel<Tin, S>), dim3(tilesM * tilesN), dim3(GNT), 0, s, As, Bs, eA, eB,
+                         static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp, sp.Np, sp.Kp, k0, len, alpha,
+                         k0 == 0 ? beta : 1.0, tilesM, tilesN);
+    }
+  } else
+    hipLaunchKernelGGL((split_gemm_kernel<ST, Tin, MODE, S>), dim3(tilesM * tilesN), dim3(GNT), 0, s, As, Bs, eA,
+                       eB, static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp, sp.Np, sp.Kp, alpha, beta,
+                       tilesM, tilesN);
   return hipGetLastError();
 }
 
@@ -399,6 +606,17 @@ hipError_t dispatch(const Analysis &an, const SplitPlan &sp, const GettTables &t
                     const void *B, double beta, void *C, void *ws, hipStream_t s) {
   if (sp.mode == 1) return run_split<Tin, __bf16, 1, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
   if (sp.mode == 2) return run_split<Tin, _Float16, 2, 2>(an, sp, t, alpha, A, B, beta, C, ws, s);
+  if (sp.mode == 3) {
+    switch (sp.S) {
+      case 3: return run_split<Tin, signed char, 3, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
+      case 4: return run_split<Tin, signed char, 3, 4>(an, sp, t, alpha, A, B, beta, C, ws, s);
+      case 5: return run_split<Tin, signed char, 3, 5>(an, sp, t, alpha, A, B, beta, C, ws, s);
+      case 6: return run_split<Tin, signed char, 3, 6>(an, sp, t, alpha, A, B, beta, C, ws, s);
+      case 7: return run_split<Tin, signed char, 3, 7>(an, sp, t, alpha, A, B, beta, C, ws, s);
+      case 8: return run_split<Tin, signed char, 3, 8>(an, sp, t, alpha, A, B, beta, C, ws, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (sp.S) {
     case 3: return run_split<Tin, __bf16, 0, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
     case 4: return run_split<Tin, __bf16, 0, 4>(an, sp, t, alpha, A, B, beta, C, ws, s);
@@ -414,16 +632,22 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 Status split_prepare(const Analysis &an, SplitPlan &sp) {
   sp = SplitPlan();
-  sp.mode = an.compute == COMET_COMPUTE_SPLIT_BF16 ? 0 : an.compute == COMET_COMPUTE_SPLIT_BF16X3 ? 1 : 2;
-  sp.S = sp.mode == 0 ? an.split_slices : sp.mode == 1 ? 3 : 2;
-  if (sp.S < 3 && sp.mode == 0) return Status::error(COMET_ERR_UNSUPPORTED, "split slices must be within 3..6");
+  sp.mode = an.compute == COMET_COMPUTE_SPLIT_BF16     ? 0
+            : an.compute == COMET_COMPUTE_SPLIT_BF16X3 ? 1
+            : an.compute == COMET_COMPUTE_SPLIT_FP16X2 ? 2
+                                                       : 3;
+  sp.S = (sp.mode == 0 || sp.mode == 3) ? an.split_slices : sp.mode == 1 ? 3 : 2;
+  if (sp.mode == 0 && (sp.S < 3 || sp.S > 6))
+    return Status::error(COMET_ERR_UNSUPPORTED, "split slices must be within 3..6");
+  if (sp.mode == 3 && (sp.S < 3 || sp.S > 8))
+    return Status::error(COMET_ERR_UNSUPPORTED, "int8 split slices must be within 3..8");
   sp.Mp = round_up(an.m, GBM);
   sp.Np = round_up(an.n, GBN);
-  sp.Kp = round_up(an.k, GBK);
+  sp.Kp = round_up(an.k, sp.mode == 3 ? IBK : GBK);
   const int64_t tiles = (sp.Mp / GBM) * (sp.Np / GBN);
   if (tiles > INT_MAX || (sp.Mp / PR) * (sp.Kp / PK) > INT_MAX || (sp.Np / PR) * (sp.Kp / PK) > INT_MAX)
     return Status::error(COMET_ERR_UNSUPPORTED, "problem too large for the split path");
-  const size_t es = 2;
+  const size_t es = sp.mode == 3 ? 1 : 2;
   size_t off = 0;
   sp.offA = off;
   off = align256(off + size_t(sp.S) * sp.Mp * sp.Kp * es);

@@ -340,7 +340,7 @@ def test_config1_oracle_and_delta():
     assert np.array_equal(got, A)
 
 
-@pytest.mark.parametrize("tile", range(7))
+@pytest.mark.parametrize("tile", range(10))
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("spec,ext", [
     ("abij=acik*bkcj", dict(a=21, b=19, c=23, i=13, j=11, k=9)),      # A k-contiguous, B n-contiguous

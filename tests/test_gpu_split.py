@@ -1,7 +1,7 @@
 """Parity of the compensated split-precision modes against the FP64 oracle.
 
-Bars (relative Frobenius error): aligned BF16 slices <= 1e-9 on FP64
-storage; classic BF16x3 and FP16x2 <= 1e-5 (FP32-class accumulation); any
+Bars (relative Frobenius error): aligned BF16 and aligned INT8 slices <= 1e-9
+on FP64 storage; classic BF16x3 and FP16x2 <= 1e-5 (FP32-class accumulation); any
 split mode on FP32 storage <= 1e-5 (rounding the output to FP32 alone costs
 ~3e-8).  Integer-valued inputs are reproduced bit for bit in every mode:
 their slices and partial sums are exact.
@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 comet = pytest.importorskip("paper_2102_06827_amd")
 
-MODES = ["split_bf16", "split_bf16x3", "split_fp16x2"]
-TOL64 = {"split_bf16": 1e-9, "split_bf16x3": 1e-5, "split_fp16x2": 1e-5}
+MODES = ["split_bf16", "split_bf16x3", "split_fp16x2", "split_int8"]
+TOL64 = {"split_bf16": 1e-9, "split_bf16x3": 1e-5, "split_fp16x2": 1e-5, "split_int8": 1e-9}
 
 CASES = [
     ("abij=acik*cbkj", dict(a=16, b=16, c=16, i=16, j=16, k=16)),
@@ -148,3 +148,31 @@ def test_split_config3_full_size_sampled(mode):
     g = C[tuple(torch.from_numpy(pts).cuda().T)].cpu().numpy()
     assert oracle.relerr(g, oracle.contract_points(spec, A, B, pts)) <= TOL64[mode]
     del C
+
+
+def test_int8_slices_control_the_error():
+    """INT8 slices accumulate exactly, so the error keeps falling with S."""
+    spec, ext = CASES[1]
+    A, B, _ = inputs(spec, ext, 850, kind="normal")
+    ref = oracle.contract(spec, A, B)
+    errs = {}
+    try:
+        for S in (3, 4, 5, 6, 7, 8):
+            comet.set_int8_slices(S)
+            print_case("int8 slices", S)
+            errs[S] = oracle.relerr(run(spec, A, B, None, 1.0, 0.0, torch.float64, "split_int8"), ref)
+    finally:
+        comet.set_int8_slices(6)
+    for S in (3, 4, 5, 6, 7):
+        assert errs[S] > errs[S + 1], errs
+    assert errs[6] <= 1e-9 and errs[8] <= 1e-13, errs
+
+
+def test_int8_long_summation_is_chunked():
+    """A summation longer than one launch's exact int32 range (8192 indices)."""
+    A = synth.normal(860, (96, 20000))
+    B = synth.normal(861, (20000, 80))
+    C0 = synth.normal(862, (96, 80))
+    print_case("int8 long K")
+    got = run("ij=ik*kj", A, B, C0, 1.0, 1.0, torch.float64, "split_int8")
+    assert oracle.relerr(got, oracle.contract("ij=ik*kj", A, B, C0, beta=1.0)) <= 1e-9

@@ -66,7 +66,7 @@ def loader_indices(R, BK, VEC, layout, vec, Rtot, K, NT=256):
 
 # (BM, BN, BK, waves) of the kernel's tile table
 TILES = [(128, 128, 16, 4), (64, 64, 16, 4), (128, 128, 32, 4), (128, 128, 16, 8), (256, 128, 16, 8),
-         (128, 64, 16, 4), (64, 128, 16, 4)]
+         (128, 64, 16, 4), (64, 128, 16, 4), (96, 96, 16, 4), (128, 96, 32, 8), (192, 96, 32, 8)]
 
 
 @pytest.mark.parametrize("VEC", [2, 4])
