@@ -165,6 +165,11 @@ comet_status_t comet_contract(const char *spec, const int64_t *extents,
  * may be NULL when the size is 0) and is capturable into a HIP graph.
  * Pointer arguments of execute must satisfy the alignment the plan was
  * made for; misaligned pointers take the scalar gather, never an error.
+ * The workspace holds TTGT's permuted operands, the split modes' slices, or
+ * the partial sums of a stream-K schedule (output tiles whose summation is
+ * split over several workgroups and summed afterwards in a fixed order, so
+ * results do not depend on timing); its contents on entry do not matter and
+ * executions that share one workspace must not overlap.
  */
 comet_status_t comet_plan_create(comet_plan_t *plan, const char *spec, const int64_t *extents,
                                  const int64_t *strides_A, const int64_t *strides_B,

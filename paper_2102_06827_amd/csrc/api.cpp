@@ -82,6 +82,8 @@ struct comet_plan_s {
   std::unique_ptr<comet_plan_s> gemm;
   PermuteLaunch permA{}, permB{}, permC{};
   size_t wsA = 0, wsB = 0, wsC = 0;   // byte offsets of A_p, B_p, C_p in the workspace
+  size_t wsG = 0;                     // byte offset of the GEMM stage's own workspace
+  size_t sk_bytes = 0;                // stream-K partial sums (at offset 0 of a GETT plan's workspace)
 
   ~comet_plan_s() {
     if (dtables) (void)hipFree(dtables);
@@ -135,47 +137,139 @@ comet_status_t upload_tables(comet_plan_s *p) {
   return COMET_OK;
 }
 
-// Tile choice without timing: for every compiled tile the modeled time is
-//   ceil(tiles / (CUs * resident)) * resident * BM * BN / throughput
-// (rounds of resident workgroups; a CU running `resident` workgroups of the
-// tile delivers `throughput` output elements per unit time).  Residency and
-// throughput were measured on MI355X for each tile on a 3072^3 contraction;
-// only their ratios matter.  The autotuner replaces this with timings.
-struct TileModel {
-  int resident;
-  double throughput;
-};
-constexpr TileModel kModelF64[] = {{1, 20117}, {3, 19770}, {1, 18175}, {1, 30070}, {1, 33670},
-                                   {2, 23569}, {2, 22224}, {2, 19873}, {1, 21906}, {1, 29570}};
-constexpr TileModel kModelF32[] = {{3, 48231}, {5, 44152}, {1, 41259}, {2, 60670}, {2, 52433},
-                                   {4, 67818}, {4, 68556}};
+// Tile choice without timing.  For every compiled tile the time of one round
+// (every CU running `resident` workgroups of the tile to the end) is
+//   rt = resident * BM * BN / throughput * K / 3072,
+// with `resident` from the occupancy calculator for the exact kernel and the
+// per-CU output throughput measured on MI355X per tile on a matrix product
+// with 6144 x 6144 outputs and K = 3072 (A contiguous along K, B along N),
+// in output elements per microsecond.  T tiles over S = CUs * resident slots
+// then take floor(T / S) full rounds plus a partial round, which runs at
+// most twice as fast as a full one (fewer workgroups share each CU).  The
+// stream-K alternative replaces the partial round by an equal split of its
+// tiles' summation over all S slots, plus the partial sums it writes and
+// reads back.  The autotuner replaces this model with timings.
+constexpr double kThroughputF64[] = {28.4, 33.2, 28.6, 41.0, 38.6, 33.6, 32.7, 33.5, 34.4, 34.3};
+constexpr double kThroughputF32[] = {74.5, 64.9, 73.4, 75.8, 79.3, 69.8, 70.1};
+constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
+constexpr double kSkBytesPerUs = 4.0e6;  // partial-sum traffic rate (HBM, both directions)
+constexpr double kSkLaunchUs = 4.0;      // the two extra launches
 
-int pick_tile(const Analysis &an, int cus, bool vecA, bool vecB) {
-  const char *env = std::getenv("COMET_GETT_TILE");
-  if (env && *env) {
-    int t = std::atoi(env);
-    if (t >= 0 && t < gett_tile_count()) return t;
+int tile_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
+  GettLaunch g{};
+  g.dtype = an.dtype == COMET_F64 ? 0 : 1;
+  g.compute = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  g.layoutA = an.layoutA;
+  g.layoutB = an.layoutB;
+  g.vecA = vecA;
+  g.vecB = vecB;
+  g.tile = tile;
+  return gett_occupancy(g);
+}
+
+struct Schedule {
+  int tile = 1;
+  int sk_tiles = 0, sk_blocks = 0;
+  double us = 1e300;
+};
+
+// Modeled time of `tile`, whole tiles only and with the stream-K split;
+// returns the better of the two.
+Schedule model_tile(const Analysis &an, int tile, int resident, int cus) {
+  Schedule out;
+  out.tile = tile;
+  const bool f64 = an.compute == COMET_COMPUTE_F64;
+  const double *thr = f64 ? kThroughputF64 : kThroughputF32;
+  const int nthr = f64 ? int(sizeof(kThroughputF64) / sizeof(double)) : int(sizeof(kThroughputF32) / sizeof(double));
+  if (tile >= nthr || resident <= 0) return out;
+  int bm, bn, bk;
+  gett_tile_shape(tile, &bm, &bn, &bk);
+  const int64_t T = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+  const int64_t S = int64_t(std::max(cus, 1)) * resident;
+  const int64_t nk = (an.k + bk - 1) / bk;
+  const double rt = double(resident) * bm * bn / thr[tile] * double(nk * bk) / 3072.0;
+  const int64_t full = T / S, rem = T - full * S;
+  double partial = 0.0;
+  if (rem > 0) {
+    const int64_t per_cu = (rem + cus - 1) / std::max(cus, 1);
+    partial = rt * std::max(double(per_cu) / resident, 0.5);
   }
-  const int dt = an.dtype == COMET_F64 ? 0 : 1, cp = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
-  const bool f64 = cp == 0;
-  const int nmodel = f64 ? int(sizeof(kModelF64) / sizeof(kModelF64[0])) : int(sizeof(kModelF32) / sizeof(kModelF32[0]));
-  int best = 1;
-  double best_t = 1e300;
-  for (int t = 0; t < gett_tile_count() && t < nmodel; ++t) {
-    if (!gett_tile_valid(t, dt, cp, vecA, vecB)) continue;
-    const TileModel &tm = f64 ? kModelF64[t] : kModelF32[t];
-    int bm, bn, bk;
-    gett_tile_shape(t, &bm, &bn, &bk);
-    const int64_t tiles = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
-    const int64_t slots = int64_t(std::max(cus, 1)) * tm.resident;
-    const int64_t rounds = (tiles + slots - 1) / slots;
-    const double time = double(rounds) * tm.resident * bm * bn / tm.throughput;
-    if (time < best_t * 0.999) {
-      best_t = time;
-      best = t;
+  out.us = double(full) * rt + partial;
+  if (rem > 0 && T <= INT32_MAX) {
+    const int64_t blocks = std::min<int64_t>(S, rem * nk / kSkMinSteps);
+    if (blocks >= 2) {
+      // tiles' worth of steps per workgroup, at the speed of blocks / CUs
+      // workgroups per CU (as for a partial round)
+      const double share = double(rem) / double(blocks);
+      const double per_cu = double((blocks + cus - 1) / std::max(cus, 1));
+      const double pieces = double(std::min<int64_t>(2 * blocks, blocks + rem));
+      const double bytes = pieces * bm * bn * (f64 ? 8.0 : 4.0) * 2.0;
+      const double sk_us = double(full) * rt + rt * share * std::max(per_cu / resident, 0.5) +
+                           bytes / kSkBytesPerUs + kSkLaunchUs;
+      if (sk_us < 0.97 * out.us) {
+        out.us = sk_us;
+        out.sk_tiles = int(rem);
+        out.sk_blocks = int(blocks);
+      }
     }
   }
+  return out;
+}
+
+// Apply COMET_GETT_SK: "0" turns stream-K off, "tiles,blocks" forces a split
+// (clamped to the tile count; at least one block).
+void sk_override(const Analysis &an, Schedule &sc) {
+  const char *env = std::getenv("COMET_GETT_SK");
+  if (!env || !*env) return;
+  if (std::string(env) == "0") {
+    sc.sk_tiles = sc.sk_blocks = 0;
+    return;
+  }
+  int t = 0, b = 0;
+  if (std::sscanf(env, "%d,%d", &t, &b) != 2) return;
+  int bm, bn, bk;
+  gett_tile_shape(sc.tile, &bm, &bn, &bk);
+  const int64_t T = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+  sc.sk_tiles = int(std::max<int64_t>(0, std::min<int64_t>(t, T)));
+  sc.sk_blocks = sc.sk_tiles > 0 ? std::max(b, 1) : 0;
+}
+
+// Tile and stream-K split of the gather kernel for an analyzed contraction.
+Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int forced_tile = -1) {
+  const int dt = an.dtype == COMET_F64 ? 0 : 1, cp = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  const char *env = std::getenv("COMET_GETT_TILE");
+  if (forced_tile < 0 && env && *env) {
+    int t = std::atoi(env);
+    if (t >= 0 && t < gett_tile_count()) forced_tile = t;
+  }
+  Schedule best;
+  if (forced_tile >= 0) {
+    best = model_tile(an, forced_tile, tile_resident(an, forced_tile, vecA, vecB), cus);
+    best.tile = forced_tile;
+  } else {
+    for (int t = 0; t < gett_tile_count(); ++t) {
+      if (!gett_tile_valid(t, dt, cp, vecA, vecB)) continue;
+      Schedule sc = model_tile(an, t, tile_resident(an, t, vecA, vecB), cus);
+      if (sc.us < best.us * 0.999) best = sc;
+    }
+  }
+  // the stream-K kernels exist for the vector-load variants
+  if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
+  sk_override(an, best);
+  if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
   return best;
+}
+
+void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
+  Analysis &an = p->an;
+  Schedule sc = pick_schedule(an, cus, p->vecA_tables, p->vecB_tables, forced_tile);
+  const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
+  if (!native || an.empty_out || an.empty_sum) sc.sk_tiles = sc.sk_blocks = 0;
+  an.tile = sc.tile;
+  an.sk_tiles = sc.sk_tiles;
+  an.sk_blocks = sc.sk_blocks;
+  const size_t slot = gett_sk_slot_bytes(sc.tile, an.compute == COMET_COMPUTE_F64 ? 0 : 1);
+  p->sk_bytes = sc.sk_tiles > 0 ? align256(2 * size_t(sc.sk_blocks) * slot) : 0;
 }
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
@@ -184,7 +278,7 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
 comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
                              const int64_t *sA, const int64_t *sB, const int64_t *sC);
 comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
-                        hipStream_t s);
+                        hipStream_t s, void *ws);
 comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
                        void *ws, size_t ws_bytes, hipStream_t s);
 
@@ -300,8 +394,15 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   const int VEC = an.dtype == COMET_F64 ? 2 : 4;
   p->vecA_tables = tables_vec_ok(an.offAm, an.offAk, an.layoutA, an.runAm, an.runAk, VEC);
   p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC);
-  an.tile = pick_tile(an, cus, p->vecA_tables, p->vecB_tables);
-  if (p->gemm) p->gemm->an.tile = pick_tile(p->gemm->an, cus, p->gemm->vecA_tables, p->gemm->vecB_tables);
+  apply_schedule(p.get(), cus);
+  if (p->gemm) {
+    apply_schedule(p->gemm.get(), cus);
+    p->gemm->ws_bytes = p->gemm->sk_bytes;
+    p->wsG = p->ws_bytes;
+    p->ws_bytes += p->gemm->ws_bytes;
+  } else if (an.path == COMET_PATH_GETT) {
+    p->ws_bytes = p->sk_bytes;
+  }
   bool split = an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
                an.compute == COMET_COMPUTE_SPLIT_FP16X2 || an.compute == COMET_COMPUTE_SPLIT_INT8;
   // FP32 storage in BF16x3: split on the fly inside the gather kernel
@@ -319,8 +420,9 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   return COMET_OK;
 }
 
+// ws: the plan's stream-K workspace (sk_bytes), unused without a split
 comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
-                        hipStream_t s) {
+                        hipStream_t s, void *ws) {
   const Analysis &an = p->an;
   GettLaunch g{};
   g.A = an.swapped ? B : A;
@@ -342,6 +444,11 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
   // misaligned pointers or a tile not built for this dtype pair: the 64 x 64
   // tile has every variant
   if (!gett_tile_valid(g.tile, g.dtype, g.compute, g.vecA, g.vecB)) g.tile = 1;
+  if (an.sk_tiles > 0 && g.tile == an.tile && ws) {
+    g.sk.tiles = an.sk_tiles;
+    g.sk.blocks = an.sk_blocks;
+    g.sk.ws = ws;
+  }
   HIP_TRY(launch_gett(g, s), "gett launch");
   return COMET_OK;
 }
@@ -412,7 +519,7 @@ comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const
       Bp = pl.out;
     }
     if (tc.c_copy) {
-      comet_status_t rc = run_gett(p->gemm.get(), alpha, Ap, Bp, 0.0, w + p->wsC, s);
+      comet_status_t rc = run_gett(p->gemm.get(), alpha, Ap, Bp, 0.0, w + p->wsC, s, w + p->wsG);
       if (rc != COMET_OK) return rc;
       PermuteLaunch pl = p->permC;
       pl.in = w + p->wsC;
@@ -422,9 +529,9 @@ comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const
       HIP_TRY(launch_permute(pl, s), "permute C");
       return COMET_OK;
     }
-    return run_gett(p->gemm.get(), alpha, Ap, Bp, beta, C, s);
+    return run_gett(p->gemm.get(), alpha, Ap, Bp, beta, C, s, w + p->wsG);
   }
-  return run_gett(p, alpha, A, B, beta, C, s);
+  return run_gett(p, alpha, A, B, beta, C, s, ws);
 }
 
 // ---- autotuning -------------------------------------------------------------
@@ -471,9 +578,11 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
   Analysis &an = p->an;
   TuneCache &tc = tune_cache();
   std::lock_guard<std::mutex> lk(tc.mutex());
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) cus = 256;
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
   if (tc.mode() == 0 || !native || an.empty_out || an.empty_sum) return COMET_OK;
-  if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH")) return COMET_OK;
+  if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH") || std::getenv("COMET_GETT_SK")) return COMET_OK;
   const std::string key = tune_key(an, arch_id(p->device));
   TuneEntry best;
   if (!(tc.mode() == 1 && tc.lookup(key, &best))) {
@@ -493,15 +602,27 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
       (void)hipMemsetAsync(bufA, 0, std::max<int64_t>(an.sizeA, 1) * es, s);
       (void)hipMemsetAsync(bufB, 0, std::max<int64_t>(an.sizeB, 1) * es, s);
       best.us = 1e30;
-      const int keep = an.tile;
+      void *skws = nullptr;
+      size_t skws_bytes = 0;
       for (int tile = 0; tile < gett_tile_count(); ++tile) {
         if (!gett_tile_valid(tile, an.dtype == COMET_F64 ? 0 : 1, an.compute == COMET_COMPUTE_F64 ? 0 : 1,
                              p->vecA_tables, p->vecB_tables))
           continue;
-        an.tile = tile;
+        // each tile with its own stream-K split
+        apply_schedule(p.get(), cus, tile);
+        if (p->sk_bytes > skws_bytes) {
+          if (skws) (void)hipFree(skws);
+          skws = nullptr;
+          skws_bytes = 0;
+          if (hipMalloc(&skws, p->sk_bytes) != hipSuccess) {
+            skws = nullptr;
+            continue;
+          }
+          skws_bytes = p->sk_bytes;
+        }
         bool good;
         const comet_plan_s *pp = p.get();
-        double us = time_us([&]() { return run_gett(pp, 1.0, bufA, bufB, 0.0, bufC, s); }, s, &good);
+        double us = time_us([&]() { return run_gett(pp, 1.0, bufA, bufB, 0.0, bufC, s, skws); }, s, &good);
         if (good && us < best.us) best = TuneEntry{tile, COMET_PATH_GETT, us};
       }
       if (tt) {
@@ -510,8 +631,9 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
         double us = time_us([&]() { return execute(pt, 1.0, bufA, bufB, 0.0, bufC, ws, wsb, s); }, s, &good);
         if (good && us < best.us) best = TuneEntry{tt->gemm ? tt->gemm->an.tile : 0, COMET_PATH_TTGT, us};
       }
-      an.tile = keep;
       (void)hipStreamSynchronize(s);
+      if (skws) (void)hipFree(skws);
+      apply_schedule(p.get(), cus);
     }
     if (bufA) (void)hipFree(bufA);
     if (bufB) (void)hipFree(bufB);
@@ -529,7 +651,10 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
       return COMET_OK;
     }
   }
-  if (best.tile >= 0 && best.tile < gett_tile_count()) an.tile = best.tile;
+  if (best.tile >= 0 && best.tile < gett_tile_count()) {
+    apply_schedule(p.get(), cus, best.tile);
+    p->ws_bytes = p->sk_bytes;
+  }
   return COMET_OK;
 }
 
@@ -568,6 +693,9 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
   const char *tl = std::getenv("COMET_GETT_TILE");
   k += "|";
   if (tl) k += tl;
+  const char *skv = std::getenv("COMET_GETT_SK");
+  k += "|";
+  if (skv) k += skv;
   k += "|t" + std::to_string(tune_cache().mode());
   return k;
 }
@@ -647,6 +775,14 @@ comet_status_t comet_plan_destroy(comet_plan_t plan) {
 comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len) {
   if (!plan || !buf || !len) return fail(COMET_ERR_NULL_POINTER, "NULL argument");
   std::string js = describe_json(plan->an);
+  if (!js.empty() && js.back() == '}') {
+    // resident workgroups per CU of the gather kernel this plan launches
+    int res = 0;
+    if (plan->an.path == COMET_PATH_GETT)
+      res = tile_resident(plan->an, plan->an.tile, plan->vecA_tables, plan->vecB_tables);
+    js.pop_back();
+    js += ",\"resident\":" + std::to_string(res) + "}";
+  }
   std::strncpy(buf, js.c_str(), len - 1);
   buf[len - 1] = 0;
   if (js.size() + 1 > len) return fail(COMET_ERR_WORKSPACE, "describe buffer too small");

@@ -40,8 +40,8 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
                                             __bf16 *smem) {
   typedef Loader<float, float, TB, F3_BK, LA, V, NT> LoadA;
   typedef Loader<float, float, TB, F3_BK, LB, V, NT> LoadB;
-  __bf16 *sA = smem;
-  __bf16 *sB = smem + 3 * TB * F3_LDK;
+  lds_t<__bf16> *const sA = to_lds(smem);
+  lds_t<__bf16> *const sB = sA + 3 * TB * F3_LDK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
   f4_t acc[2][2];
@@ -73,14 +73,14 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
     for (int q = 0; q < 3; ++q)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        bF[q][j] = *reinterpret_cast<const bf16x8 *>(
+        bF[q][j] = *reinterpret_cast<const lds_t<bf16x8> *>(
             &sB[(q * TB + wn0 + j * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
       bf16x8 aF[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        aF[i] = *reinterpret_cast<const bf16x8 *>(
+        aF[i] = *reinterpret_cast<const lds_t<bf16x8> *>(
             &sA[(p * TB + wm0 + i * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -100,21 +100,24 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
   }
   const float al = float(alpha), be = float(beta);
   const bool read_c = beta != 0.0;
+  glb_t<float> *const gC = to_glb(C);
+  const glb_t<const int64_t> *const offCm = to_glb(t.offCm);
+  const glb_t<const int64_t> *const offCn = to_glb(t.offCn);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
     if (n >= N) continue;
-    const int64_t cn = t.offCn[n];
+    const int64_t cn = offCn[n];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
         if (m >= M) continue;
-        const int64_t addr = t.offCm[m] + cn;
+        const int64_t addr = offCm[m] + cn;
         float v = al * acc[i][j][r];
-        if (read_c) v = v + be * C[addr];
-        C[addr] = v;
+        if (read_c) v = v + be * gC[addr];
+        gC[addr] = v;
       }
   }
 }

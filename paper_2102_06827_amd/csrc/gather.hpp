@@ -28,6 +28,21 @@ __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// An LDS pointer with its address space spelled out.  Every access through it
+// compiles to ds_read / ds_write.  A plain pointer chosen at run time between
+// the halves of a double buffer is lowered to flat instructions instead, and a
+// flat load waits on every global load in flight (vmcnt), which serialises the
+// software pipeline.
+template <typename T> using lds_t = __attribute__((address_space(3))) T;
+template <typename T> __device__ __forceinline__ lds_t<T> *to_lds(T *p) { return (lds_t<T> *)p; }
+
+// The same for device (global) memory.  Pointers that reach a kernel through
+// a descriptor in memory, rather than as kernel arguments, would otherwise be
+// accessed with flat instructions, which count against the LDS wait counter
+// too, so every LDS fragment read would also wait for the tile prefetch.
+template <typename T> using glb_t = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ glb_t<T> *to_glb(T *p) { return (glb_t<T> *)p; }
+
 // row of the 16 x 16 output block held in accumulator element r of a lane
 template <typename Tc> __device__ __forceinline__ int acc_row(int lane, int r);
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
@@ -45,16 +60,19 @@ template <> struct V16<float> {
   typedef float type __attribute__((ext_vector_type(4)));
 };
 
-// Map a linear workgroup id to a tile id such that the workgroups the
-// hardware places on one XCD (ids congruent mod 8) get consecutive tile ids,
-// then walk tiles in groups of G tile-rows so that an XCD's tiles share A
-// rows and B columns in its L2.
-__device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int *tm, int *tn) {
-  const int total = tilesM * tilesN;
+// Map a linear workgroup id in [0, total) to a tile id in [0, total) such
+// that the workgroups the hardware places on one XCD (ids congruent mod 8)
+// get consecutive tile ids.
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
   const int X = 8;
   int xcd = bid % X, local = bid / X;
   int q = total / X, rem = total % X;
-  int id = xcd * q + (xcd < rem ? xcd : rem) + local;
+  return xcd * q + (xcd < rem ? xcd : rem) + local;
+}
+
+// Tile id -> tile coordinates, walking tiles in groups of G tile-rows so that
+// consecutive ids (one XCD's workgroups) share A rows and B columns in its L2.
+__device__ __forceinline__ void group_coords(int id, int tilesM, int tilesN, int *tm, int *tn) {
   const int G = 8;
   int per_group = G * tilesN;
   int group = id / per_group;
@@ -63,6 +81,10 @@ __device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int
   int in = id - group * per_group;
   *tm = first + in % gsize;
   *tn = in / gsize;
+}
+
+__device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int *tm, int *tn) {
+  group_coords(xcd_remap(bid, tilesM * tilesN), tilesM, tilesN, tm, tn);
 }
 
 // One operand tile: R rows (m for A, n for B) by BK summation indices.
@@ -95,14 +117,17 @@ struct Loader {
 
   Tin v[P][VEC];
   int64_t roff[P][VEC];     // hoisted row offsets (clamped to a valid row)
-  uint32_t rmask[P];        // bit i: row of element i in range
-  uint32_t vmask[P];        // bit i: element i of the last load in range
+  static_assert(P * VEC <= 32, "masks hold one bit per element");
+  uint32_t rmask;           // bit p * VEC + i: row of element i of pass p in range
+  uint32_t vmask;           // bit p * VEC + i: element i of pass p of the last load in range
   int64_t kofs[P][NKO];     // K-table entries of the step being fetched next
   int rr[P], kk[P];
 
   static constexpr bool vec = VECLD;
 
-  __device__ __forceinline__ void init(int tid, int64_t r0, int64_t Rtot, const int64_t *__restrict__ offR) {
+  __device__ __forceinline__ void init(int tid, int64_t r0, int64_t Rtot, const int64_t *__restrict__ offR_) {
+    const glb_t<const int64_t> *offR = to_glb(offR_);
+    rmask = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       int id = tid + p * NT;
@@ -114,14 +139,13 @@ struct Loader {
         rr[p] = (id % (R / VEC)) * VEC;
       }
       const int64_t gr = r0 + rr[p];
-      rmask[p] = 0;
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
         // K-contiguous and vector reads share the vector's first row offset
         const int64_t g = (LAYOUT == 0 || vec) ? gr : gr + i;
         const bool ok = g < Rtot;
         roff[p][i] = offR[ok ? g : 0];
-        rmask[p] |= (ok ? 1u : 0u) << i;
+        rmask |= (ok ? 1u : 0u) << (p * VEC + i);
       }
     }
   }
@@ -130,7 +154,8 @@ struct Loader {
   // end are clamped to the last valid start: K - 1 for single elements, and
   // K - VEC for a K-contiguous vector (K is a multiple of VEC in that mode),
   // so the clamped vector still lies inside the tensor.
-  __device__ __forceinline__ void fetch_k(const int64_t *__restrict__ offK, int64_t k0, int64_t K) {
+  __device__ __forceinline__ void fetch_k(const int64_t *__restrict__ offK_, int64_t k0, int64_t K) {
+    const glb_t<const int64_t> *offK = to_glb(offK_);
     constexpr bool kvec = LAYOUT == 0 && VECLD;
     const int64_t last = kvec ? K - VEC : K - 1;
 #pragma unroll
@@ -147,15 +172,17 @@ struct Loader {
   // load the step starting at k0, addressed by the K-table entries fetched
   // for it; the raw values are kept and masked only when stored to LDS, so
   // no instruction between here and the store waits for the loads
-  __device__ __forceinline__ void load(const Tin *__restrict__ base, int64_t k0, int64_t K) {
+  __device__ __forceinline__ void load(const Tin *__restrict__ base_, int64_t k0, int64_t K) {
+    const glb_t<const Tin> *base = to_glb(base_);
+    uint32_t vm = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const int64_t k = k0 + kk[p];
       uint32_t m = 0;
       if constexpr (VECLD) {
         const typename V16<Tin>::type x =
-            *reinterpret_cast<const typename V16<Tin>::type *>(base + roff[p][0] + kofs[p][0]);
-        const bool ok = (rmask[p] & 1u) && k < K;
+            *reinterpret_cast<const glb_t<typename V16<Tin>::type> *>(base + roff[p][0] + kofs[p][0]);
+        const bool ok = ((rmask >> (p * VEC)) & 1u) && k < K;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
         m = ok ? ((1u << VEC) - 1u) : 0u;
@@ -164,12 +191,14 @@ struct Loader {
         for (int i = 0; i < VEC; ++i) {
           const int64_t ko = kofs[p][LAYOUT == 0 ? i : 0];
           v[p][i] = base[roff[p][LAYOUT == 0 ? 0 : i] + ko];
-          const bool ok = LAYOUT == 0 ? ((rmask[p] & 1u) && k + i < K) : (((rmask[p] >> i) & 1u) && k < K);
+          const bool ok = LAYOUT == 0 ? (((rmask >> (p * VEC)) & 1u) && k + i < K)
+                                      : (((rmask >> (p * VEC + i)) & 1u) && k < K);
           m |= (ok ? 1u : 0u) << i;
         }
       }
-      vmask[p] = m;
+      vm |= m << (p * VEC);
     }
+    vmask = vm;
   }
 
   // Store as three bfloat16 slices x = b0 + b1 + b2 (b0 = bf16(x), b1 = bf16 of
@@ -177,12 +206,12 @@ struct Loader {
   // s[slice][row][k] with row pitch LDK (k contiguous, as the 16x16x32 MFMA
   // operands are read).
   template <int LDK>
-  __device__ __forceinline__ void store_split3(__bf16 *s) const {
+  __device__ __forceinline__ void store_split3(lds_t<__bf16> *s) const {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
-        const float x = ((vmask[p] >> i) & 1u) ? float(v[p][i]) : 0.0f;
+        const float x = ((vmask >> (p * VEC + i)) & 1u) ? float(v[p][i]) : 0.0f;
         const __bf16 b0 = __bf16(x);
         const float r1 = x - float(b0);
         const __bf16 b1 = __bf16(r1);
@@ -196,22 +225,22 @@ struct Loader {
     }
   }
 
-  __device__ __forceinline__ void store(Tc *s) const {
+  __device__ __forceinline__ void store(lds_t<Tc> *s) const {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       Tc x[VEC];
 #pragma unroll
-      for (int i = 0; i < VEC; ++i) x[i] = ((vmask[p] >> i) & 1u) ? Tc(v[p][i]) : Tc(0);
+      for (int i = 0; i < VEC; ++i) x[i] = ((vmask >> (p * VEC + i)) & 1u) ? Tc(v[p][i]) : Tc(0);
       // VEC consecutive elements along the contiguous dimension: one vector store
       // when they fill 16 bytes, element stores otherwise (FP32 arithmetic on
       // FP64 storage)
-      Tc *dst = s + (LAYOUT == 0 ? idx(rr[p], kk[p]) : idx(rr[p], kk[p]));
+      lds_t<Tc> *dst = s + idx(rr[p], kk[p]);
       if constexpr (VEC * sizeof(Tc) == 16) {
         typedef Tc vec_t __attribute__((ext_vector_type(VEC)));
         vec_t w;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) w[i] = x[i];
-        *reinterpret_cast<vec_t *>(dst) = w;
+        *reinterpret_cast<lds_t<vec_t> *>(dst) = w;
       } else {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) dst[i] = x[i];
@@ -227,33 +256,45 @@ constexpr int gett_lds_elems() {
   return 2 * (Loader<Tin, Tc, BM, BK, LA, VA, NT>::ELEMS + Loader<Tin, Tc, BN, BK, LB, VB, NT>::ELEMS);
 }
 
-// One BM x BN output tile at (m0, n0): gather A and B through the offset
-// tables into double-buffered LDS tiles, multiply on the 16x16x4 MFMA, and
-// write alpha * acc + beta * C through the C tables.  All threads of the
-// workgroup must call it (it synchronizes); smem holds gett_lds_elems values.
+// The register tile of one workgroup: a WGM x WGN grid of waves, each owning
+// FM x FN MFMA blocks of 16 x 16.
+template <typename Tc, int BM, int BN, int WGM, int WGN>
+struct WaveTile {
+  typedef typename AccT<Tc>::type acc_t;
+  static constexpr int NT = 64 * WGM * WGN;
+  static constexpr int WM = BM / WGM, WN = BN / WGN;
+  static constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert(FM * 16 == WM && FN * 16 == WN, "wave tile must be a multiple of 16");
+  acc_t acc[FM][FN];
+};
+
+// Accumulate the product of the BM x BN output tile at (m0, n0) over the
+// summation steps [s_begin, s_end) of BK indices each: gather A and B through
+// the offset tables into double-buffered LDS tiles and multiply on the
+// 16 x 16 x 4 MFMA.  All threads of the workgroup must call it (it
+// synchronizes); smem holds gett_lds_elems values.
 template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, int LA, int LB, bool VA, bool VB>
-__device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C,
-                                          const GettTables &t, int64_t M, int64_t N, int64_t K, double alpha,
-                                          double beta, int64_t m0, int64_t n0, Tc *smem) {
-  constexpr int NT = 64 * WGM * WGN;
+__device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &w, const Tin *__restrict__ A,
+                                                const Tin *__restrict__ B, const GettTables &t, int64_t M,
+                                                int64_t N, int64_t K, int64_t m0, int64_t n0, int64_t s_begin,
+                                                int64_t s_end, Tc *smem) {
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  constexpr int NT = WT::NT, FM = WT::FM, FN = WT::FN;
   typedef Loader<Tin, Tc, BM, BK, LA, VA, NT> LoadA;
   typedef Loader<Tin, Tc, BN, BK, LB, VB, NT> LoadB;
-  typedef typename AccT<Tc>::type acc_t;
-  constexpr int WM = BM / WGM, WN = BN / WGN;
-  constexpr int FM = WM / 16, FN = WN / 16;
-  static_assert(FM * 16 == WM && FN * 16 == WN, "wave tile must be a multiple of 16");
-  Tc *sA[2] = {smem, smem + LoadA::ELEMS};
-  Tc *sB[2] = {smem + 2 * LoadA::ELEMS, smem + 2 * LoadA::ELEMS + LoadB::ELEMS};
+  typedef typename WT::acc_t acc_t;
+  lds_t<Tc> *const s0 = to_lds(smem);
+  lds_t<Tc> *sA[2] = {s0, s0 + LoadA::ELEMS};
+  lds_t<Tc> *sB[2] = {s0 + 2 * LoadA::ELEMS, s0 + 2 * LoadA::ELEMS + LoadB::ELEMS};
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
 
-  acc_t acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    for (int j = 0; j < FN; ++j) w.acc[i][j] = acc_t{0, 0, 0, 0};
 
   LoadA la;
   LoadB lb;
@@ -263,24 +304,24 @@ __device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *
   // Software pipeline, uniform across steps: the last step also issues a
   // (masked, clamped-address) load of the step past the end, so the loop body
   // has no branches.
-  const int64_t nsteps = (K + BK - 1) / BK;
-  la.fetch_k(t.offAk, 0, K);
-  lb.fetch_k(t.offBk, 0, K);
-  la.load(A, 0, K);
-  lb.load(B, 0, K);
-  la.fetch_k(t.offAk, BK, K);
-  lb.fetch_k(t.offBk, BK, K);
+  const int64_t k_begin = s_begin * BK;
+  la.fetch_k(t.offAk, k_begin, K);
+  lb.fetch_k(t.offBk, k_begin, K);
+  la.load(A, k_begin, K);
+  lb.load(B, k_begin, K);
+  la.fetch_k(t.offAk, k_begin + BK, K);
+  lb.fetch_k(t.offBk, k_begin + BK, K);
   la.store(sA[0]);
   lb.store(sB[0]);
   __syncthreads();
-  for (int64_t step = 0; step < nsteps; ++step) {
-    const int cur = int(step & 1);
+  for (int64_t step = s_begin; step < s_end; ++step) {
+    const int cur = int((step - s_begin) & 1);
     la.load(A, (step + 1) * BK, K);
     lb.load(B, (step + 1) * BK, K);
     la.fetch_k(t.offAk, (step + 2) * BK, K);
     lb.fetch_k(t.offBk, (step + 2) * BK, K);
-    const Tc *a_s = sA[cur];
-    const Tc *b_s = sB[cur];
+    const lds_t<Tc> *a_s = sA[cur];
+    const lds_t<Tc> *b_s = sB[cur];
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
       const int kr = k4 + (lane >> 4);
@@ -292,36 +333,86 @@ __device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = mfma16(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < FN; ++j) w.acc[i][j] = mfma16(af[i], bf[j], w.acc[i][j]);
     }
     la.store(sA[cur ^ 1]);
     lb.store(sB[cur ^ 1]);
     __syncthreads();
   }
+}
 
-  // epilogue: alpha * acc + beta * C, in double for double storage or
-  // double accumulation, in float otherwise
+// C = alpha * acc + beta * C for the tile at (m0, n0), through the C tables,
+// in double for double storage or double accumulation, in float otherwise.
+template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gett_store(const WaveTile<Tc, BM, BN, WGM, WGN> &w, Tin *__restrict__ C,
+                                           const GettTables &t, int64_t M, int64_t N, double alpha, double beta,
+                                           int64_t m0, int64_t n0) {
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
   typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
   const Te al = Te(alpha), be = Te(beta);
   const bool read_c = beta != 0.0;
+  glb_t<Tin> *const gC = to_glb(C);
+  const glb_t<const int64_t> *const offCm = to_glb(t.offCm);
+  const glb_t<const int64_t> *const offCn = to_glb(t.offCn);
 #pragma unroll
-  for (int j = 0; j < FN; ++j) {
+  for (int j = 0; j < WT::FN; ++j) {
     const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
     if (n >= N) continue;
-    const int64_t cn = t.offCn[n];
+    const int64_t cn = offCn[n];
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
+    for (int i = 0; i < WT::FM; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + wm0 + i * 16 + acc_row<Tc>(lane, r);
         if (m >= M) continue;
-        const int64_t addr = t.offCm[m] + cn;
-        Te v = al * Te(acc[i][j][r]);
-        if (read_c) v = v + be * Te(C[addr]);
-        C[addr] = Tin(v);
+        const int64_t addr = offCm[m] + cn;
+        Te v = al * Te(w.acc[i][j][r]);
+        if (read_c) v = v + be * Te(gC[addr]);
+        gC[addr] = Tin(v);
       }
     }
   }
+}
+
+// A partial sum of one tile in workspace: accumulator element (i, j) of
+// thread tid at ((i * FN + j) * NT + tid), one 4-vector each, so that the
+// writes of a wave are contiguous.
+template <typename Tc, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gett_store_partial(const WaveTile<Tc, BM, BN, WGM, WGN> &w,
+                                                   typename AccT<Tc>::type *__restrict__ slot) {
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  glb_t<typename WT::acc_t> *const g = to_glb(slot);
+#pragma unroll
+  for (int i = 0; i < WT::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < WT::FN; ++j) g[(i * WT::FN + j) * WT::NT + threadIdx.x] = w.acc[i][j];
+}
+
+template <typename Tc, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gett_add_partial(WaveTile<Tc, BM, BN, WGM, WGN> &w,
+                                                 const typename AccT<Tc>::type *__restrict__ slot, bool first) {
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  const glb_t<const typename WT::acc_t> *const g = to_glb(slot);
+#pragma unroll
+  for (int i = 0; i < WT::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < WT::FN; ++j) {
+      const typename WT::acc_t v = g[(i * WT::FN + j) * WT::NT + threadIdx.x];
+      w.acc[i][j] = first ? v : w.acc[i][j] + v;
+    }
+}
+
+// One BM x BN output tile at (m0, n0) over the whole summation range.
+template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, int LA, int LB, bool VA, bool VB>
+__device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C,
+                                          const GettTables &t, int64_t M, int64_t N, int64_t K, double alpha,
+                                          double beta, int64_t m0, int64_t n0, Tc *smem) {
+  WaveTile<Tc, BM, BN, WGM, WGN> w;
+  gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(w, A, B, t, M, N, K, m0, n0, 0,
+                                                                 (K + BK - 1) / BK, smem);
+  gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, m0, n0);
 }
 
 

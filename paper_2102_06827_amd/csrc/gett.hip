@@ -34,26 +34,46 @@ namespace {
 using namespace gather;
 
 // Tile variants: workgroup tile BM x BN, K step BK, and a WGM x WGN grid of
-// waves, each owning a (BM/WGM) x (BN/WGN) block of 16 x 16 MFMA tiles.
+// waves, each owning a (BM/WGM) x (BN/WGN) block of 16 x 16 MFMA tiles.  wpe
+// is the number of waves per SIMD the register allocation must leave room
+// for (the second launch bound): the FP64 matrix core needs several waves
+// per SIMD to stay busy across the K-step barriers.
 struct TileShape {
-  int bm, bn, bk, wgm, wgn;
+  int bm, bn, bk, wgm, wgn, wpe;
 };
 constexpr TileShape kTiles[] = {
-    {128, 128, 16, 2, 2},   // 0: large problems
-    {64, 64, 16, 2, 2},     // 1: small problems; also every element-load variant
-    {128, 128, 32, 2, 2},   // 2: longer K step (fewer barriers per flop)
-    {128, 128, 16, 4, 2},   // 3: 8 waves, two per SIMD
-    {256, 128, 16, 4, 2},   // 4: 8 waves, 64 x 64 per wave
-    {128, 64, 16, 2, 2},    // 5
-    {64, 128, 16, 2, 2},    // 6
-    {96, 96, 16, 2, 2},     // 7: FP64 only; 3072^2 outputs -> 4 tiles per CU
-    {128, 96, 32, 4, 2},    // 8: FP64 only; 3072^2 outputs -> 3 tiles per CU
-    {192, 96, 32, 4, 2},    // 9: FP64 only; 3072^2 outputs -> 2 tiles per CU
+    {128, 128, 16, 2, 2, 1},   // 0: large problems
+    {64, 64, 16, 2, 2, 1},     // 1: small problems; also every element-load variant
+    {128, 128, 32, 2, 2, 1},   // 2: longer K step (fewer barriers per flop)
+    {128, 128, 16, 4, 2, 1},   // 3: 8 waves; two workgroups per CU
+    {256, 128, 16, 4, 2, 1},   // 4: 8 waves, 64 x 64 per wave
+    {128, 64, 16, 2, 2, 1},    // 5
+    {64, 128, 16, 2, 2, 1},    // 6
+    {96, 96, 16, 2, 2, 1},     // 7: FP64 only; 3072^2 outputs -> 4 tiles per CU
+    {128, 96, 32, 4, 2, 1},    // 8: FP64 only; 3072^2 outputs -> 3 tiles per CU
+    {192, 96, 32, 4, 2, 1},    // 9: FP64 only; 3072^2 outputs -> 2 tiles per CU
 };
 constexpr int kNumTiles = int(sizeof(kTiles) / sizeof(kTiles[0]));
 
+// Summation steps [a(s), a(s + 1)) of the stream-K part handled by its
+// workgroup s, with a(s) = floor(I * s / S) over I = tiles * steps-per-tile
+// steps and S workgroups: every workgroup gets the same share, give or take
+// one step, and a share may run over tile boundaries.
+__device__ __forceinline__ int64_t sk_begin(int64_t I, int S, int s) { return I * s / S; }
+
+// Workgroup of the stream-K part whose share holds step x.
+__device__ __forceinline__ int sk_owner(int64_t I, int S, int64_t x) {
+  int s = int(x * S / I);
+  if (s > S - 1) s = S - 1;
+  while (s + 1 < S && sk_begin(I, S, s + 1) <= x) ++s;
+  while (s > 0 && sk_begin(I, S, s) > x) --s;
+  return s;
+}
+
+// Whole tiles: workgroup b computes tile id b of the first gridDim.x ids in
+// the XCD-aware order (all tiles, or all but the sk.tiles stream-K ones).
 template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
-__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett_kernel(
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_kernel(
     const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
     int64_t K, double alpha, double beta, int tilesM, int tilesN) {
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
@@ -61,9 +81,83 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
   constexpr int NT = 64 * WGM * WGN;
   __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
   int tm, tn;
-  tile_coords(blockIdx.x, tilesM, tilesN, &tm, &tn);
+  group_coords(xcd_remap(blockIdx.x, gridDim.x), tilesM, tilesN, &tm, &tn);
   gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * BM,
                                                            int64_t(tn) * BN, smem);
+}
+
+// Stream-K: the last sk.tiles tiles (ids dp .. dp + sk.tiles - 1) split
+// along the summation over sk.blocks workgroups, each taking an equal number
+// of BK steps, so that the last, partial round of whole tiles becomes a full
+// round of equal pieces.  A piece that covers a whole tile is written
+// directly; other pieces go to the workspace (two slots per workgroup: its
+// first and its last tile) and gett_fixup_kernel sums them in a fixed order.
+// A separate kernel from the whole-tile one so that the latter keeps its
+// register budget (and its occupancy).
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett_sk_kernel(
+    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+    int64_t K, double alpha, double beta, int tilesM, int tilesN, StreamK sk) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
+  const int dp = tilesM * tilesN - sk.tiles;
+  int tm, tn;
+  const int s = int(blockIdx.x);
+  const int64_t nk = (K + BK - 1) / BK;
+  const int64_t I = int64_t(sk.tiles) * nk;
+  const int64_t a = sk_begin(I, sk.blocks, s), b = sk_begin(I, sk.blocks, s + 1);
+  typename WT::acc_t *const ws = static_cast<typename WT::acc_t *>(sk.ws);
+  constexpr int64_t kSlot = int64_t(WT::FM) * WT::FN * NT;   // 4-vectors per slot
+  for (int64_t it = a; it < b;) {
+    const int64_t tt = it / nk;
+    const int64_t ks = it - tt * nk;
+    const int64_t ke = ks + (b - it) < nk ? ks + (b - it) : nk;
+    group_coords(dp + int(tt), tilesM, tilesN, &tm, &tn);
+    WT w;
+    gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(w, A, B, t, M, N, K, int64_t(tm) * BM,
+                                                                   int64_t(tn) * BN, ks, ke, smem);
+    if (ks == 0 && ke == nk) {
+      gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, int64_t(tm) * BM, int64_t(tn) * BN);
+    } else {
+      const int slot = 2 * s + (tt == a / nk ? 0 : 1);
+      gett_store_partial<Tc, BM, BN, WGM, WGN>(w, ws + slot * kSlot);
+    }
+    it += ke - ks;
+  }
+}
+
+// Sum the workspace pieces of each split stream-K tile, in workgroup order,
+// and write alpha * sum + beta * C.  One workgroup per stream-K tile; tiles
+// that one workgroup covered whole were written by it and are skipped.
+template <typename Tin, typename Tc, int TILE>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett_fixup_kernel(
+    Tin *__restrict__ C, GettTables t, int64_t M, int64_t N, int64_t K, double alpha, double beta, int tilesM,
+    int tilesN, StreamK sk) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  const int dp = tilesM * tilesN - sk.tiles;
+  const int64_t tt = blockIdx.x;
+  const int64_t nk = (K + BK - 1) / BK;
+  const int64_t I = int64_t(sk.tiles) * nk;
+  const int lo = sk_owner(I, sk.blocks, tt * nk), hi = sk_owner(I, sk.blocks, (tt + 1) * nk - 1);
+  if (lo == hi) return;
+  const typename WT::acc_t *const ws = static_cast<const typename WT::acc_t *>(sk.ws);
+  constexpr int64_t kSlot = int64_t(WT::FM) * WT::FN * NT;
+  WT w;
+  for (int s = lo; s <= hi; ++s) {
+    const int64_t a = sk_begin(I, sk.blocks, s);
+    if (a == sk_begin(I, sk.blocks, s + 1)) continue;   // an empty share wrote nothing
+    const int slot = 2 * s + (tt == a / nk ? 0 : 1);
+    gett_add_partial<Tc, BM, BN, WGM, WGN>(w, ws + slot * kSlot, s == lo);
+  }
+  int tm, tn;
+  group_coords(dp + int(tt), tilesM, tilesN, &tm, &tn);
+  gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, int64_t(tm) * BM, int64_t(tn) * BN);
 }
 
 template <typename Tin, typename Tc, int TILE>
@@ -80,10 +174,29 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
   } else {
     constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn;
     constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
+    if (g.occupancy) {
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy, gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>,
+                                                          NT, 0);
+    }
     const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(tilesM * tilesN), dim3(NT), 0, s,
-                       static_cast<const Tin *>(g.A), static_cast<const Tin *>(g.B), static_cast<Tin *>(g.C), g.t,
-                       g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+    StreamK sk = g.sk;
+    if (sk.blocks <= 0 || sk.tiles <= 0 || sk.tiles > tilesM * tilesN || !sk.ws) sk = StreamK{};
+    const int dp = tilesM * tilesN - sk.tiles;
+    const Tin *A = static_cast<const Tin *>(g.A), *B = static_cast<const Tin *>(g.B);
+    Tin *C = static_cast<Tin *>(g.C);
+    if (dp > 0) {
+      hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(dp), dim3(NT), 0, s, A, B, C, g.t, g.M,
+                         g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (sk.tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((gett_sk_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(sk.blocks), dim3(NT), 0, s, A, B, C,
+                       g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, sk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((gett_fixup_kernel<Tin, Tc, TILE>), dim3(sk.tiles), dim3(NT), 0, s, C, g.t, g.M, g.N, g.K,
+                       g.alpha, g.beta, tilesM, tilesN, sk);
     return hipGetLastError();
   }
 }
@@ -151,6 +264,10 @@ __global__ __launch_bounds__(256) void scale_kernel(T *__restrict__ C, const int
 
 int gett_tile_count() { return kNumTiles; }
 
+size_t gett_sk_slot_bytes(int tile, int compute) {
+  return size_t(kTiles[tile].bm) * kTiles[tile].bn * (compute == 0 ? 8 : 4);
+}
+
 void gett_tile_shape(int tile, int *bm, int *bn, int *bk) {
   *bm = kTiles[tile].bm;
   *bn = kTiles[tile].bn;
@@ -173,6 +290,18 @@ hipError_t launch_gett(const GettLaunch &g, hipStream_t s) {
     return g.compute == 0 ? launch_tc<double, double>(g, s) : launch_tc<double, float>(g, s);
   }
   return g.compute == 0 ? launch_tc<float, double>(g, s) : launch_tc<float, float>(g, s);
+}
+
+int gett_occupancy(const GettLaunch &g) {
+  int n = 0;
+  GettLaunch q = g;
+  q.occupancy = &n;
+  q.M = q.N = 1;
+  if (launch_gett(q, nullptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
 }
 
 hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,

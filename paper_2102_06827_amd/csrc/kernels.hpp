@@ -14,6 +14,15 @@ struct GettTables {
   const int64_t *offAm, *offAk, *offBk, *offBn, *offCm, *offCn;
 };
 
+// Stream-K split of the last `tiles` output tiles over `blocks` extra
+// workgroups; ws holds 2 * blocks partial tiles (gett_sk_slot_bytes each).
+// tiles == 0: every tile is computed whole by its own workgroup.
+struct StreamK {
+  int tiles = 0;
+  int blocks = 0;
+  void *ws = nullptr;
+};
+
 // dtype_in/out: 0 = double, 1 = float.  compute: 0 = FP64 MFMA, 1 = FP32 MFMA.
 struct GettLaunch {
   const void *A;
@@ -28,10 +37,17 @@ struct GettLaunch {
   int layoutB;         // 0: B contiguous along K, 1: along N
   int vecA, vecB;      // 16-byte vector loads allowed
   int tile;            // tile variant
+  int *occupancy = nullptr;   // when set: store the resident workgroups per CU, launch nothing
+  StreamK sk;
 };
 
 hipError_t launch_gett(const GettLaunch &g, hipStream_t s);
+// Workgroups of the kernel that launch_gett would run for g that fit on one
+// CU at once (register and LDS limits), 0 if that variant does not exist.
+int gett_occupancy(const GettLaunch &g);
 int gett_tile_count();
+// bytes of one stream-K workspace slot (one partial output tile)
+size_t gett_sk_slot_bytes(int tile, int compute);
 void gett_tile_shape(int tile, int *bm, int *bn, int *bk);
 // whether a tile variant is compiled for this dtype/compute/vector combination
 bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB);

@@ -82,6 +82,9 @@ struct Analysis {
 
   // tile shape of the gather kernel (index into the kernel's variant list)
   int tile = 0;
+  // stream-K: the last sk_tiles output tiles are split along K over
+  // sk_blocks workgroups (0: every tile is computed whole)
+  int sk_tiles = 0, sk_blocks = 0;
   int split_slices = 5;
 
   TTGTChoice ttgt;

@@ -180,18 +180,26 @@ def test_batch_graph_capture_and_replay(compute):
         assert oracle.relerr(to_np(eager[rep]), ref) <= 1e-5
 
 
-@pytest.mark.parametrize("compute,path", [("f64", "gett"), ("f64", "ttgt"), ("split_bf16", "auto"),
-                                          ("split_fp16x2", "auto")])
-def test_plan_graph_capture_and_replay(compute, path):
+@pytest.mark.parametrize("compute,path,sk", [("f64", "gett", None), ("f64", "ttgt", None), ("split_bf16", "auto", None),
+                                             ("split_fp16x2", "auto", None), ("f64", "gett", "16,40"),
+                                             ("f64", "ttgt", "5,9")])
+def test_plan_graph_capture_and_replay(compute, path, sk, monkeypatch):
+    if sk:
+        # a stream-K schedule: partial tiles in the workspace, a fixup launch
+        monkeypatch.setenv("COMET_GETT_TILE", "3")
+        monkeypatch.setenv("COMET_GETT_SK", sk)
     spec = "abij=acik*bkcj"
-    ext = dict(a=20, b=18, c=22, i=9, j=7, k=10)
+    # j even: 16-byte vector loads of B, which the stream-K kernels require
+    ext = dict(a=20, b=18, c=22, i=9, j=8 if sk else 7, k=10)
     A = synth.uniform(1, shape_of("acik", ext))
     B = synth.uniform(2, shape_of("bkcj", ext))
     Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
     C = torch.zeros(shape_of("abij", ext), dtype=torch.float64, device="cuda")
     plan = comet.Plan(spec, Ad, Bd, C, compute=compute, path=path)
     ws = plan.workspace(Ad.device)
-    print_case("plan graph", compute, path)
+    print_case("plan graph", compute, path, sk)
+    if sk:
+        assert plan.workspace_bytes > 0
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):

@@ -352,3 +352,51 @@ def test_tile_variants(tile, dtype, spec, ext, monkeypatch):
     monkeypatch.setenv("COMET_GETT_TILE", str(tile))
     check(spec, ext, dtype, seed=700 + tile, kind="integer", alpha=1.0, beta=1.0)
     check(spec, ext, dtype, seed=720 + tile, alpha=-0.5, beta=0.25)
+
+
+SK_CASES = [
+    # (tile, "tiles,blocks") on a 480 x 480 x 480 contraction with ragged edges:
+    # shares inside one tile, shares over tile boundaries, more blocks than
+    # steps (empty shares), a single block, every tile split
+    (3, "4,16"), (3, "9,5"), (3, "16,40"), (9, "3,1000"), (1, "57,64"), (0, "16,3"), (4, "8,8"), (8, "12,7"),
+]
+
+
+@pytest.mark.parametrize("tile,sk", SK_CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", [
+    ("abij=acik*bkcj", dict(a=40, b=40, c=40, i=12, j=12, k=12)),
+    ("ajbi=kcia*cjkb", dict(a=18, b=9, c=12, i=16, j=24, k=6)),
+])
+def test_stream_k_split(tile, sk, dtype, spec, ext, monkeypatch):
+    """Forced stream-K splits of the gather kernel: partial tiles summed by
+    the fixup kernel must match the oracle (bit-exact on integer inputs)."""
+    if dtype == "f32" and tile in (7, 8, 9):
+        pytest.skip("FP64-only tile")
+    monkeypatch.setenv("COMET_GETT_TILE", str(tile))
+    monkeypatch.setenv("COMET_GETT_SK", sk)
+    check(spec, ext, dtype, seed=900 + tile, kind="integer", alpha=1.0, beta=1.0)
+    check(spec, ext, dtype, seed=920 + tile, alpha=-0.75, beta=0.5)
+    check(spec, ext, dtype, seed=940 + tile, alpha=1.5, beta=0.0, path="gett")
+
+
+def test_stream_k_plan_describes_split(monkeypatch):
+    monkeypatch.setenv("COMET_GETT_TILE", "3")
+    monkeypatch.setenv("COMET_GETT_SK", "9,5")
+    A = torch.zeros((40, 40, 12, 12), dtype=torch.float64, device="cuda")
+    B = torch.zeros((40, 12, 40, 12), dtype=torch.float64, device="cuda")
+    p = comet.Plan("abij=acik*bkcj", A, B, path="gett")
+    d = p.describe()
+    assert d["tile"] == 3 and d["sk_tiles"] == 9 and d["sk_blocks"] == 5
+    assert p.workspace_bytes >= 2 * 5 * 128 * 128 * 8
+
+
+def test_stream_k_is_deterministic(monkeypatch):
+    """The fixup sums the pieces in a fixed order: repeated runs agree bit for bit."""
+    monkeypatch.setenv("COMET_GETT_TILE", "3")
+    monkeypatch.setenv("COMET_GETT_SK", "16,40")
+    spec, ext = "abij=acik*bkcj", dict(a=40, b=40, c=40, i=12, j=12, k=12)
+    A, B, C0 = inputs(spec, ext, 77, kind="uniform", beta=True)
+    first = run(spec, A, B, C0, 1.0, 0.5, "f64")
+    for _ in range(3):
+        assert np.array_equal(run(spec, A, B, C0, 1.0, 0.5, "f64"), first)

@@ -106,3 +106,57 @@ def test_model_catches_the_unaligned_clamp():
     k = nsteps * BK + kk
     bad = np.where(k <= K - 1, k, K - 1)
     assert (bad + VEC - 1).max() >= K
+
+
+# (BM, BN, BK, WGM, WGN) of the kernel's tile table, for the LDS check below
+TILE_WAVES = [(128, 128, 16, 2, 2), (64, 64, 16, 2, 2), (128, 128, 32, 2, 2), (128, 128, 16, 4, 2),
+              (256, 128, 16, 4, 2), (128, 64, 16, 2, 2), (64, 128, 16, 2, 2), (96, 96, 16, 2, 2),
+              (128, 96, 32, 4, 2), (192, 96, 32, 4, 2)]
+
+
+def test_tile_tables_agree():
+    assert [(t[0], t[1], t[2], t[3] * t[4]) for t in TILE_WAVES] == TILES
+
+
+@pytest.mark.parametrize("tile", range(len(TILE_WAVES)))
+@pytest.mark.parametrize("tc_bytes,VEC", [(8, 2), (4, 4), (4, 2)])
+@pytest.mark.parametrize("layoutA,layoutB", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_lds_positions_in_buffer(tile, tc_bytes, VEC, layoutA, layoutB):
+    """Every LDS element a loader stores and every MFMA fragment read lies
+    inside its operand's buffer (ELEMS = R * (BK + KPAD) for K-contiguous
+    tiles, BK * (R + 4) otherwise), for every tile, layout and type pair."""
+    BM, BN, BK, WGM, WGN = TILE_WAVES[tile]
+    NTl = 64 * WGM * WGN
+    KPAD = 2 if tc_bytes == 8 else 4
+    for R, layout, W, wpos in ((BM, layoutA, BM // WGM, lambda w: (w // WGN)),
+                               (BN, layoutB, BN // WGN, lambda w: (w % WGN))):
+        if R * BK % (VEC * NTl):
+            continue
+        P = R * BK // (VEC * NTl)
+        LDK, LDR = BK + KPAD, R + 4
+        elems = R * LDK if layout == 0 else BK * LDR
+        idx = (lambda r, k: r * LDK + k) if layout == 0 else (lambda r, k: k * LDR + r)
+        ids = np.arange(NTl)[:, None] + NTl * np.arange(P)[None, :]
+        if layout == 0:
+            rr, kk = ids // (BK // VEC), (ids % (BK // VEC)) * VEC
+            last = idx(rr, kk + VEC - 1)
+        else:
+            kk, rr = ids // (R // VEC), (ids % (R // VEC)) * VEC
+            last = idx(rr + VEC - 1, kk)
+        assert last.max() < elems and idx(rr, kk).min() >= 0
+        # the stores of one pass cover the buffer's R x BK entries exactly once
+        cover = set()
+        for i in range(VEC):
+            pos = idx(rr + (i if layout == 1 else 0), kk + (i if layout == 0 else 0))
+            cover.update(pos.ravel().tolist())
+        assert len(cover) == R * BK
+        lane = np.arange(64)
+        reads = []
+        for w in range(WGM * WGN):
+            r0 = wpos(w) * W
+            for f in range(W // 16):
+                for k4 in range(0, BK, 4):
+                    reads.append(idx(r0 + f * 16 + (lane & 15), k4 + (lane >> 4)))
+        reads = np.concatenate(reads)
+        assert reads.min() >= 0 and reads.max() < elems
+        assert set(reads.tolist()) <= cover
