@@ -37,11 +37,23 @@ EXT = dict(a=V, b=V, c=V, i=O, j=O, k=O)
 FLOPS = 2.0 * V ** 3 * O ** 3            # 2 * M * N * K, M = N = K = 3072
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "i8": 5033.2}
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the headline kernel from FETCH_SIZE / WRITE_SIZE
+# The headline contraction runs as one launch group of the gather kernel:
+# whole output tiles (gett_kernel), the stream-K pieces of the tiles left
+# after the last full round (gett_sk_kernel) and the sum of those pieces
+# (gett_fixup_kernel).  HBM bytes of one group from FETCH_SIZE / WRITE_SIZE
 # counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
-# valid only for the kernel version named, null otherwise
-HEADLINE_KERNEL = "gett_kernel<double, double, 9, 0, 1, true, true>"
-HEADLINE_TRAFFIC = {"kernel": HEADLINE_KERNEL, "bytes": None, "kernel_version": "k4"}
+# valid only for the schedule and kernel version recorded, null otherwise.
+HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512}, "kernel_version": "k5",
+                    "bytes": None}
+KERNEL_VERSION = "k5"
+
+
+def headline_kernels(d):
+    t = d["tile"]
+    ks = ["gett_kernel<double, double, %d, 0, 1, true, true>" % t]
+    if d.get("sk_tiles"):
+        ks += ["gett_sk_kernel<double, double, %d, 0, 1, true, true>" % t, "gett_fixup_kernel<double, double, %d>" % t]
+    return ks
 MODES = {
     "f64": dict(compute="f64", mfma="f64", products=1, tol=1e-12),
     "split_bf16": dict(compute="split_bf16", mfma="bf16", products=15, tol=1e-9),
@@ -315,6 +327,14 @@ def main():
     head = modes["f64"]
     ms = head["ms"]
     achieved = FLOPS / (ms * 1e-3) / 1e12
+    Ad = torch.empty(shape("acik"), dtype=torch.float64, device="cuda")
+    Bd = torch.empty(shape("bkcj"), dtype=torch.float64, device="cuda")
+    sched = comet.Plan(SPEC, Ad, Bd, compute="f64").describe()
+    sched = {k: sched[k] for k in ("path", "tile", "sk_tiles", "sk_blocks", "resident")}
+    del Ad, Bd
+    same = (HEADLINE_TRAFFIC["kernel_version"] == KERNEL_VERSION and
+            all(HEADLINE_TRAFFIC["schedule"][k] == sched[k] for k in HEADLINE_TRAFFIC["schedule"]))
+    traffic = HEADLINE_TRAFFIC["bytes"] if same else None
     line = {
         "metric": "GFLOP/s & % MFMA peak per contraction: FP64 vs split-BF16x3 at stated rel err",
         "value": head["gflops"],
@@ -333,8 +353,8 @@ def main():
                    "spec": SPEC, "extents": EXT, "flops_per_step": FLOPS},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
-                     "traffic": HEADLINE_TRAFFIC["bytes"], "kernel": HEADLINE_KERNEL,
-                     "algorithmic_bytes": 4 * 8.0 * V * V * O * O},
+                     "traffic": traffic, "kernel": " + ".join(headline_kernels(sched)), "schedule": sched,
+                     "algorithmic_flops": FLOPS, "algorithmic_bytes": 4 * 8.0 * V * V * O * O},
         "modes": modes,
     }
     if not args.only_headline:

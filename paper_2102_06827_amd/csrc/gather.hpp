@@ -376,6 +376,33 @@ __device__ __forceinline__ void gett_store(const WaveTile<Tc, BM, BN, WGM, WGN> 
   }
 }
 
+// C = alpha * v + beta * C for accumulator element (i, j) of this thread
+// only (the same outputs gett_store writes from w.acc[i][j]).
+template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gett_store_fragment(const typename AccT<Tc>::type &v, int i, int j,
+                                                    Tin *__restrict__ C, const GettTables &t, int64_t M, int64_t N,
+                                                    double alpha, double beta, int64_t m0, int64_t n0) {
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
+  const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
+  if (n >= N) return;
+  glb_t<Tin> *const gC = to_glb(C);
+  const int64_t cn = to_glb(t.offCn)[n];
+  const glb_t<const int64_t> *const offCm = to_glb(t.offCm);
+  const Te al = Te(alpha), be = Te(beta);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t m = m0 + wm0 + i * 16 + acc_row<Tc>(lane, r);
+    if (m >= M) continue;
+    const int64_t addr = offCm[m] + cn;
+    Te x = al * Te(v[r]);
+    if (beta != 0.0) x = x + be * Te(gC[addr]);
+    gC[addr] = Tin(x);
+  }
+}
+
 // A partial sum of one tile in workspace: accumulator element (i, j) of
 // thread tid at ((i * FN + j) * NT + tid), one 4-vector each, so that the
 // writes of a wave are contiguous.
@@ -388,20 +415,6 @@ __device__ __forceinline__ void gett_store_partial(const WaveTile<Tc, BM, BN, WG
   for (int i = 0; i < WT::FM; ++i)
 #pragma unroll
     for (int j = 0; j < WT::FN; ++j) g[(i * WT::FN + j) * WT::NT + threadIdx.x] = w.acc[i][j];
-}
-
-template <typename Tc, int BM, int BN, int WGM, int WGN>
-__device__ __forceinline__ void gett_add_partial(WaveTile<Tc, BM, BN, WGM, WGN> &w,
-                                                 const typename AccT<Tc>::type *__restrict__ slot, bool first) {
-  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
-  const glb_t<const typename WT::acc_t> *const g = to_glb(slot);
-#pragma unroll
-  for (int i = 0; i < WT::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < WT::FN; ++j) {
-      const typename WT::acc_t v = g[(i * WT::FN + j) * WT::NT + threadIdx.x];
-      w.acc[i][j] = first ? v : w.acc[i][j] + v;
-    }
 }
 
 // One BM x BN output tile at (m0, n0) over the whole summation range.

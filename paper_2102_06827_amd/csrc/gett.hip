@@ -130,8 +130,10 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
 }
 
 // Sum the workspace pieces of each split stream-K tile, in workgroup order,
-// and write alpha * sum + beta * C.  One workgroup per stream-K tile; tiles
-// that one workgroup covered whole were written by it and are skipped.
+// and write alpha * sum + beta * C.  Workgroup (x, y) takes stream-K tile x
+// and accumulator element y = i * FN + j of every thread, so that a tile's
+// sum is spread over FM * FN workgroups; tiles that one workgroup covered
+// whole were written by it and are skipped.
 template <typename Tin, typename Tc, int TILE>
 __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett_fixup_kernel(
     Tin *__restrict__ C, GettTables t, int64_t M, int64_t N, int64_t K, double alpha, double beta, int tilesM,
@@ -140,24 +142,28 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
   constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
   constexpr int NT = 64 * WGM * WGN;
   typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  typedef typename WT::acc_t acc_t;
   const int dp = tilesM * tilesN - sk.tiles;
   const int64_t tt = blockIdx.x;
+  const int f = blockIdx.y;
   const int64_t nk = (K + BK - 1) / BK;
   const int64_t I = int64_t(sk.tiles) * nk;
   const int lo = sk_owner(I, sk.blocks, tt * nk), hi = sk_owner(I, sk.blocks, (tt + 1) * nk - 1);
   if (lo == hi) return;
-  const typename WT::acc_t *const ws = static_cast<const typename WT::acc_t *>(sk.ws);
+  const glb_t<const acc_t> *const ws = to_glb(static_cast<const acc_t *>(sk.ws));
   constexpr int64_t kSlot = int64_t(WT::FM) * WT::FN * NT;
-  WT w;
+  acc_t v = acc_t{0, 0, 0, 0};
   for (int s = lo; s <= hi; ++s) {
     const int64_t a = sk_begin(I, sk.blocks, s);
     if (a == sk_begin(I, sk.blocks, s + 1)) continue;   // an empty share wrote nothing
     const int slot = 2 * s + (tt == a / nk ? 0 : 1);
-    gett_add_partial<Tc, BM, BN, WGM, WGN>(w, ws + slot * kSlot, s == lo);
+    const acc_t p = ws[slot * kSlot + int64_t(f) * NT + threadIdx.x];
+    v = s == lo ? p : v + p;
   }
   int tm, tn;
   group_coords(dp + int(tt), tilesM, tilesN, &tm, &tn);
-  gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, int64_t(tm) * BM, int64_t(tn) * BN);
+  gett_store_fragment<Tin, Tc, BM, BN, WGM, WGN>(v, f / WT::FN, f % WT::FN, C, t, M, N, alpha, beta,
+                                                 int64_t(tm) * BM, int64_t(tn) * BN);
 }
 
 template <typename Tin, typename Tc, int TILE>
@@ -195,8 +201,9 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
                        g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, sk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((gett_fixup_kernel<Tin, Tc, TILE>), dim3(sk.tiles), dim3(NT), 0, s, C, g.t, g.M, g.N, g.K,
-                       g.alpha, g.beta, tilesM, tilesN, sk);
+    constexpr int FRAGS = (BM / kTiles[TILE].wgm / 16) * (BN / kTiles[TILE].wgn / 16);
+    hipLaunchKernelGGL((gett_fixup_kernel<Tin, Tc, TILE>), dim3(sk.tiles, FRAGS), dim3(NT), 0, s, C, g.t, g.M, g.N,
+                       g.K, g.alpha, g.beta, tilesM, tilesN, sk);
     return hipGetLastError();
   }
 }
