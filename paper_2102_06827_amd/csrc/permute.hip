@@ -3,77 +3,176 @@
 //
 // This is the transpose of the TTGT lowering (Section 2) and the ta.copy
 // operation (Section 5).  The paper's transpose optimization (Section 6)
-// orders the loops so the innermost indices stay innermost and then tiles;
-// on the GPU the same aim -- unit-stride access on both sides -- is met by
-// staging a 32 x 32 tile spanned by the input's and the output's unit-stride
-// dimensions through LDS: threads read along the input's unit dimension and
-// write along the output's.  When both tensors have the same unit dimension
-// no staging is needed and the kernel streams along it.  All other dimensions
-// are enumerated by the workgroup index.
+// orders the loops so that the innermost indices stay innermost and then
+// tiles; on the GPU the same aim -- unit-stride access on both sides, in
+// runs long enough to fill whole cache lines -- is met in two ways:
+//
+//   stream:    both tensors have the same unit-stride dimension u.  Every
+//              row along u is copied with 16-byte vectors; consecutive
+//              threads take consecutive vectors of a row and then the next
+//              rows, so a short u (16 FP64 values, say) still gives each
+//              wave several whole rows.
+//   transpose: the unit dimensions differ.  A 32 x 32 tile spanned by the
+//              input-contiguous group Gi (the input's unit dimension plus the
+//              dimensions that continue it contiguously, until the group
+//              holds 32 elements) and the output-contiguous group Go is
+//              staged through LDS: threads read along Gi and write along Go.
+//              The offsets of a tile's Gi entries in the output and of its Go
+//              entries in the input are computed once per tile into LDS.
+//
+// All remaining dimensions are enumerated by the workgroup index.
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "kernels.hpp"
 
 namespace comet {
 namespace {
 
-constexpr int TP = 32;   // tile edge
-constexpr int TR = 8;    // thread rows; each thread moves TP / TR elements per tile
+constexpr int TP = 32;   // transpose tile edge
+constexpr int TR = 8;    // thread rows of the transpose block
+constexpr int SB = 256;  // stream block
+constexpr int SU = 4;    // vectors per stream thread per pass
 
-struct PermArgs {
-  int ndim;
-  int ui, uo;                       // input / output unit-stride dims (may be equal)
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); static constexpr int W = 2; };
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); static constexpr int W = 4; };
+
+// A set of dimensions with both strides; index decomposition fastest first.
+struct DimSet {
+  int n = 0;
   int64_t ext[kPermMaxDims];
   int64_t s_in[kPermMaxDims];
   int64_t s_out[kPermMaxDims];
+};
+
+// Offsets of linear index x over the dimensions of d (fastest first).  I is
+// the index type of the divisions: 32-bit when every index fits, which is
+// several times cheaper than 64-bit division.
+template <typename I>
+__device__ __forceinline__ void decompose(const DimSet &d, int64_t x64, int64_t *oi, int64_t *oo) {
+  int64_t a = 0, b = 0;
+  I x = I(x64);
+  for (int k = 0; k < d.n; ++k) {
+    const I e = I(d.ext[k]);
+    const I q = x / e;
+    const I r = x - q * e;
+    x = q;
+    a += int64_t(r) * d.s_in[k];
+    b += int64_t(r) * d.s_out[k];
+  }
+  *oi = a;
+  *oo = b;
+}
+
+struct StreamArgs {
+  DimSet rows;            // every dimension but u, fastest first (output order)
+  int64_t E;              // extent of u
+  int64_t su_in, su_out;  // strides of u
+  int64_t vpr;            // vectors per row (E / W)
+  int64_t total;          // rows * vpr
+};
+
+template <typename T, int W, typename I>
+__global__ __launch_bounds__(SB) void permute_stream(const T *__restrict__ in, T *__restrict__ out, StreamArgs a,
+                                                     double alpha, double beta) {
+  typedef typename std::conditional<sizeof(T) == 8, double, float>::type Te;
+  typedef typename Vec16<T>::type vec_t;
+  const int64_t stride = int64_t(gridDim.x) * SB * SU;
+  for (int64_t q0 = int64_t(blockIdx.x) * SB * SU + threadIdx.x; q0 < a.total; q0 += stride) {
+    int64_t ai[SU], ao[SU];
+    bool ok[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int64_t q = q0 + int64_t(u) * SB;
+      ok[u] = q < a.total;
+      const I row = ok[u] ? I(q) / I(a.vpr) : I(0);
+      const int64_t c = ok[u] ? int64_t(I(q) - row * I(a.vpr)) * W : 0;
+      int64_t bi, bo;
+      decompose<I>(a.rows, int64_t(row), &bi, &bo);
+      ai[u] = bi + c * a.su_in;
+      ao[u] = bo + c * a.su_out;
+    }
+    if constexpr (W > 1) {
+      vec_t x[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+        if (ok[u]) x[u] = alpha != 0.0 ? *reinterpret_cast<const vec_t *>(in + ai[u]) : vec_t{};
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        if (!ok[u]) continue;
+        vec_t y;
+        vec_t *dst = reinterpret_cast<vec_t *>(out + ao[u]);
+        const vec_t old = beta != 0.0 ? *dst : vec_t{};
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          Te v = alpha != 0.0 ? Te(alpha) * Te(x[u][k]) : Te(0);
+          if (beta != 0.0) v = v + Te(beta) * Te(old[k]);
+          y[k] = T(v);
+        }
+        *dst = y;
+      }
+    } else {
+      T x[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+        if (ok[u]) x[u] = alpha != 0.0 ? in[ai[u]] : T(0);
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        if (!ok[u]) continue;
+        Te v = alpha != 0.0 ? Te(alpha) * Te(x[u]) : Te(0);
+        if (beta != 0.0) v = v + Te(beta) * Te(out[ao[u]]);
+        out[ao[u]] = T(v);
+      }
+    }
+  }
+}
+
+struct TileArgs {
+  DimSet gi, go, batch;      // Gi, Go fastest first; batch: the rest
+  int64_t EI, EO;            // element counts of Gi and Go
+  int64_t gi_sin, go_sout;   // stride of a Gi step in the input, of a Go step in the output
   int64_t tiles_i, tiles_o;
 };
 
-template <typename T>
-__device__ __forceinline__ void batch_base(const PermArgs &a, int64_t b, int64_t *bi, int64_t *bo) {
-  int64_t oi = 0, oo = 0;
-  for (int d = a.ndim - 1; d >= 0; --d) {
-    if (d == a.ui || d == a.uo) continue;
-    int64_t e = a.ext[d];
-    int64_t x = b % e;
-    b /= e;
-    oi += x * a.s_in[d];
-    oo += x * a.s_out[d];
-  }
-  *bi = oi;
-  *bo = oo;
-}
-
-template <typename T>
-__global__ __launch_bounds__(TP *TR) void permute_tiled(const T *__restrict__ in, T *__restrict__ out, PermArgs a,
+template <typename T, typename I>
+__global__ __launch_bounds__(TP *TR) void permute_tiled(const T *__restrict__ in, T *__restrict__ out, TileArgs a,
                                                          double alpha, double beta) {
   typedef typename std::conditional<sizeof(T) == 8, double, float>::type Te;
   __shared__ T tile[TP][TP + 1];
+  __shared__ int64_t gi_out[TP], go_in[TP];
   int64_t bid = blockIdx.x;
   const int64_t ti = bid % a.tiles_i;
   bid /= a.tiles_i;
   const int64_t to = bid % a.tiles_o;
   bid /= a.tiles_o;
   int64_t bi, bo;
-  batch_base<T>(a, bid, &bi, &bo);
-  const int64_t Ei = a.ext[a.ui], Eo = a.ext[a.uo];
+  decompose<I>(a.batch, bid, &bi, &bo);
   const int64_t i0 = ti * TP, o0 = to * TP;
   const int x = threadIdx.x, y = threadIdx.y;
-  const int64_t si_i = a.s_in[a.ui], si_o = a.s_in[a.uo];
-  const int64_t so_i = a.s_out[a.ui], so_o = a.s_out[a.uo];
+  if (y == 0) {
+    int64_t di, dout;
+    decompose<I>(a.gi, i0 + x < a.EI ? i0 + x : 0, &di, &dout);
+    gi_out[x] = dout;
+  } else if (y == 1) {
+    int64_t di, dout;
+    decompose<I>(a.go, o0 + x < a.EO ? o0 + x : 0, &di, &dout);
+    go_in[x] = di;
+  }
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < TP; r += TR) {
     const int64_t i = i0 + x, o = o0 + y + r;
-    if (alpha != 0.0 && i < Ei && o < Eo) tile[x][y + r] = in[bi + i * si_i + o * si_o];
+    if (alpha != 0.0 && i < a.EI && o < a.EO) tile[x][y + r] = in[bi + i * a.gi_sin + go_in[y + r]];
   }
   __syncthreads();
   const Te al = Te(alpha), be = Te(beta);
 #pragma unroll
   for (int r = 0; r < TP; r += TR) {
     const int64_t o = o0 + x, i = i0 + y + r;
-    if (i < Ei && o < Eo) {
-      const int64_t addr = bo + o * so_o + i * so_i;
+    if (i < a.EI && o < a.EO) {
+      const int64_t addr = bo + o * a.go_sout + gi_out[y + r];
       Te v = alpha != 0.0 ? al * Te(tile[y + r][x]) : Te(0);
       if (beta != 0.0) v = v + be * Te(out[addr]);
       out[addr] = T(v);
@@ -81,67 +180,140 @@ __global__ __launch_bounds__(TP *TR) void permute_tiled(const T *__restrict__ in
   }
 }
 
-// same unit dimension on both sides: stream along it
-template <typename T>
-__global__ __launch_bounds__(256) void permute_stream(const T *__restrict__ in, T *__restrict__ out, PermArgs a,
-                                                      double alpha, double beta) {
-  typedef typename std::conditional<sizeof(T) == 8, double, float>::type Te;
-  int64_t bid = blockIdx.x;
-  const int64_t chunk = bid % a.tiles_i;
-  bid /= a.tiles_i;
-  int64_t bi, bo;
-  batch_base<T>(a, bid, &bi, &bo);
-  const int64_t E = a.ext[a.ui];
-  const int64_t u = chunk * 256 + threadIdx.x;
-  if (u >= E) return;
-  const int64_t ai = bi + u * a.s_in[a.ui], ao = bo + u * a.s_out[a.ui];
-  Te v = alpha != 0.0 ? Te(alpha) * Te(in[ai]) : Te(0);
-  if (beta != 0.0) v = v + Te(beta) * Te(out[ao]);
-  out[ao] = T(v);
+struct Dim {
+  int64_t ext, si, so;
+};
+
+// Drop extent-1 dimensions and fuse pairs that are contiguous in both
+// tensors (the faster one continues into the slower one on both sides).
+std::vector<Dim> normalise(const PermuteLaunch &p) {
+  std::vector<Dim> d;
+  for (int k = 0; k < p.ndim; ++k)
+    if (p.ext[k] != 1) d.push_back({p.ext[k], p.s_in[k], p.s_out[k]});
+  bool merged = true;
+  while (merged) {
+    merged = false;
+    for (size_t f = 0; f < d.size() && !merged; ++f)
+      for (size_t g = 0; g < d.size() && !merged; ++g) {
+        if (f == g) continue;
+        // g continues f in both tensors
+        if (d[g].si == d[f].si * d[f].ext && d[g].so == d[f].so * d[f].ext) {
+          d[f].ext *= d[g].ext;
+          d.erase(d.begin() + g);
+          merged = true;
+        }
+      }
+  }
+  return d;
+}
+
+void fill(DimSet &s, const std::vector<Dim> &d, const std::vector<int> &idx) {
+  s.n = (int)idx.size();
+  for (int k = 0; k < s.n; ++k) {
+    s.ext[k] = d[idx[k]].ext;
+    s.s_in[k] = d[idx[k]].si;
+    s.s_out[k] = d[idx[k]].so;
+  }
 }
 
 template <typename T>
 hipError_t launch_perm_t(const PermuteLaunch &p, hipStream_t s) {
-  PermArgs a;
-  a.ndim = p.ndim;
   int64_t total = 1;
-  for (int d = 0; d < p.ndim; ++d) {
-    a.ext[d] = p.ext[d];
-    a.s_in[d] = p.s_in[d];
-    a.s_out[d] = p.s_out[d];
-    total *= p.ext[d];
-  }
+  for (int k = 0; k < p.ndim; ++k) total *= p.ext[k];
   if (total == 0) return hipSuccess;
-  if (p.ndim == 0) {
-    // a scalar: one element
-    a.ndim = 1;
-    a.ext[0] = 1;
-    a.s_in[0] = 0;
-    a.s_out[0] = 0;
-  }
-  // unit dims: smallest stride on each side
-  a.ui = 0;
-  a.uo = 0;
-  for (int d = 1; d < a.ndim; ++d) {
-    if (a.s_in[d] < a.s_in[a.ui]) a.ui = d;
-    if (a.s_out[d] < a.s_out[a.uo]) a.uo = d;
-  }
-  int64_t batch = 1;
-  for (int d = 0; d < a.ndim; ++d)
-    if (d != a.ui && d != a.uo) batch *= a.ext[d];
+  std::vector<Dim> d = normalise(p);
   const T *in = static_cast<const T *>(p.in);
   T *out = static_cast<T *>(p.out);
-  if (a.ui == a.uo) {
-    a.tiles_i = (a.ext[a.ui] + 255) / 256;
-    a.tiles_o = 1;
-    hipLaunchKernelGGL(permute_stream<T>, dim3(unsigned(a.tiles_i * batch)), dim3(256), 0, s, in, out, a, p.alpha,
-                       p.beta);
-  } else {
-    a.tiles_i = (a.ext[a.ui] + TP - 1) / TP;
-    a.tiles_o = (a.ext[a.uo] + TP - 1) / TP;
-    hipLaunchKernelGGL(permute_tiled<T>, dim3(unsigned(a.tiles_i * a.tiles_o * batch)), dim3(TP, TR), 0, s, in, out,
-                       a, p.alpha, p.beta);
+  const int n = (int)d.size();
+  // unit dimensions: the smallest stride on each side (without reads, only
+  // the output side matters)
+  int ui = -1, uo = -1;
+  for (int k = 0; k < n; ++k) {
+    if (uo < 0 || d[k].so < d[uo].so) uo = k;
+    if (ui < 0 || d[k].si < d[ui].si) ui = k;
   }
+  if (p.alpha == 0.0) ui = uo;
+  if (n == 0 || ui == uo) {
+    StreamArgs a{};
+    std::vector<int> rows;
+    for (int k = 0; k < n; ++k)
+      if (k != uo) rows.push_back(k);
+    // rows fastest first in output order
+    std::sort(rows.begin(), rows.end(), [&](int x, int y) { return d[x].so < d[y].so; });
+    fill(a.rows, d, rows);
+    a.E = n ? d[uo].ext : 1;
+    a.su_in = n ? d[uo].si : 0;
+    a.su_out = n ? d[uo].so : 0;
+    constexpr int W = Vec16<T>::W;
+    bool vec = n > 0 && a.su_out == 1 && (p.alpha == 0.0 || a.su_in == 1) && a.E % W == 0 &&
+               reinterpret_cast<uintptr_t>(out) % 16 == 0 &&
+               (p.alpha == 0.0 || reinterpret_cast<uintptr_t>(in) % 16 == 0);
+    for (int k = 0; k < a.rows.n && vec; ++k)
+      vec = a.rows.s_out[k] % W == 0 && (p.alpha == 0.0 || a.rows.s_in[k] % W == 0);
+    const int w = vec ? W : 1;
+    a.vpr = a.E / w;
+    a.total = (total / a.E) * a.vpr;
+    const int64_t want = (a.total + int64_t(SB) * SU - 1) / (int64_t(SB) * SU);
+    const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(want, 8192)));
+    // 32-bit index arithmetic when every linear index (plus a pass of the
+    // grid) stays below 2^31
+    const bool small = total < (int64_t(1) << 30);
+    if (vec && small)
+      hipLaunchKernelGGL((permute_stream<T, W, uint32_t>), dim3(grid), dim3(SB), 0, s, in, out, a, p.alpha, p.beta);
+    else if (vec)
+      hipLaunchKernelGGL((permute_stream<T, W, uint64_t>), dim3(grid), dim3(SB), 0, s, in, out, a, p.alpha, p.beta);
+    else if (small)
+      hipLaunchKernelGGL((permute_stream<T, 1, uint32_t>), dim3(grid), dim3(SB), 0, s, in, out, a, p.alpha, p.beta);
+    else
+      hipLaunchKernelGGL((permute_stream<T, 1, uint64_t>), dim3(grid), dim3(SB), 0, s, in, out, a, p.alpha, p.beta);
+    return hipGetLastError();
+  }
+  // transpose: grow Gi from ui along input contiguity and Go from uo along
+  // output contiguity, until each holds TP elements
+  std::vector<int> gi{ui}, go{uo};
+  std::vector<bool> used(n, false);
+  used[ui] = used[uo] = true;
+  int64_t EI = d[ui].ext, EO = d[uo].ext;
+  auto grow = [&](std::vector<int> &g, int64_t &E, bool input) {
+    while (E < TP) {
+      const Dim &last = d[g.back()];
+      int next = -1;
+      for (int k = 0; k < n; ++k) {
+        if (used[k]) continue;
+        if (input ? d[k].si == last.si * last.ext : d[k].so == last.so * last.ext) {
+          next = k;
+          break;
+        }
+      }
+      if (next < 0) break;
+      used[next] = true;
+      g.push_back(next);
+      E *= d[next].ext;
+    }
+  };
+  grow(gi, EI, true);
+  grow(go, EO, false);
+  std::vector<int> rest;
+  for (int k = 0; k < n; ++k)
+    if (!used[k]) rest.push_back(k);
+  std::sort(rest.begin(), rest.end(), [&](int x, int y) { return d[x].so < d[y].so; });
+  TileArgs a{};
+  fill(a.gi, d, gi);
+  fill(a.go, d, go);
+  fill(a.batch, d, rest);
+  a.EI = EI;
+  a.EO = EO;
+  a.gi_sin = d[ui].si;
+  a.go_sout = d[uo].so;
+  a.tiles_i = (EI + TP - 1) / TP;
+  a.tiles_o = (EO + TP - 1) / TP;
+  const int64_t blocks = a.tiles_i * a.tiles_o * (total / (EI * EO));
+  if (total < (int64_t(1) << 30))
+    hipLaunchKernelGGL((permute_tiled<T, uint32_t>), dim3(unsigned(blocks)), dim3(TP, TR), 0, s, in, out, a, p.alpha,
+                       p.beta);
+  else
+    hipLaunchKernelGGL((permute_tiled<T, uint64_t>), dim3(unsigned(blocks)), dim3(TP, TR), 0, s, in, out, a, p.alpha,
+                       p.beta);
   return hipGetLastError();
 }
 

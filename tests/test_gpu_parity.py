@@ -250,6 +250,14 @@ def test_determinism_bitwise():
     ("dcba=abcd", (7, 9, 11, 35)),
     ("bcda=abcd", (40, 3, 5, 7)),
     ("abcd=abcd", (3, 4, 5, 6)),
+    # shared unit dimension, short rows (vector and element streams)
+    ("aick=acik", (5, 6, 7, 8)),
+    ("abcijk=aijbck", (3, 2, 5, 4, 3, 16)),
+    ("bac=abc", (9, 7, 5)),
+    # unit dimensions shorter than the tile: merged input / output groups
+    ("abij=ijab", (5, 6, 7, 8)),
+    ("fedcba=abcdef", (3, 4, 2, 5, 3, 6)),
+    ("cadb=abcd", (2, 3, 33, 4)),
 ])
 def test_permute_bitwise(spec, shape, dtype):
     lo, li = spec.split("=")
@@ -268,6 +276,48 @@ def test_permute_bitwise(spec, shape, dtype):
     cast = np.float32 if dtype == "f32" else np.float64
     exp = (2.0 * ref.astype(np.float64) - o0.astype(cast).astype(np.float64)).astype(cast)
     assert np.array_equal(to_np(od).astype(cast), exp)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_permute_views_broadcast_and_scaling(dtype):
+    """Strided views on both sides, a broadcast (stride 0) input, alpha = 0."""
+    t = tdt(dtype)
+    big = torch_dev(synth.uniform(610, (12, 30, 20)), t)
+    x = big[1:11, ::3, 2:18]                       # (10, 10, 16), non-dense strides
+    obig = torch.zeros((20, 12, 40), dtype=t, device="cuda")
+    out = obig[2:18, 1:11, ::4]                    # (16, 10, 10) view
+    print_case("permute views", dtype)
+    comet.permute("cab=abc", x, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, x.permute(2, 0, 1))
+    assert torch.count_nonzero(obig).item() == torch.count_nonzero(out).item()   # nothing outside the view
+    col = torch_dev(synth.uniform(611, (7, 1)), t).expand(7, 9)   # stride (1, 0)
+    r = comet.permute("ji=ij", col)
+    torch.cuda.synchronize()
+    assert torch.equal(r, col.t())
+    o = torch_dev(synth.uniform(612, (9, 7)), t)
+    ref = o * 0.5
+    comet.permute("ji=ij", col, o, alpha=0.0, beta=0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(o, ref)
+
+
+@pytest.mark.parametrize("spec", ["ji=ij", "jik=ijk"])
+def test_permute_64bit_indexing(spec):
+    """More than 2^30 elements: the 64-bit index path of both kernels."""
+    if spec == "ji=ij":
+        x = torch.empty((32768, 32776), dtype=torch.float32, device="cuda")
+    else:
+        x = torch.empty((1024, 1024, 1040), dtype=torch.float32, device="cuda")
+    assert x.numel() > (1 << 30)
+    x.copy_(torch.arange(x.numel(), device="cuda", dtype=torch.float32).view(x.shape) % 8191)
+    print_case("permute 64-bit", spec)
+    out = comet.permute(spec, x)
+    torch.cuda.synchronize()
+    lo, li = spec.split("=")
+    assert torch.equal(out, x.permute(*[li.index(c) for c in lo]))
+    del x, out
+    torch.cuda.empty_cache()
 
 
 # --------------------------------------------------------------------------
