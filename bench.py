@@ -13,6 +13,7 @@ The same line also carries, each timed with HIP events on the launch stream:
   backward   forward + dA + dB of the same contraction (FP64 and aligned split);
   triples    the 6D-output contraction C[a,b,c,i,j,k] = sum_d A[d,a,i,j] B[b,c,d,k]
              (virtual 32, occupied 16), bound by writing C to HBM;
+  permute    the transpose kernel of the TTGT lowering on three shapes;
   batch      1024 independent 4D contractions of six patterns with per-label
              extents from {8,...,64}, forward + backward in one persistent
              launch replayed from a HIP graph (FP32 and BF16x3);
@@ -44,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
 # valid only for the schedule and kernel version recorded, null otherwise.
 HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512}, "kernel_version": "k5",
-                    "bytes": None}
+                    "bytes": 883231437}
 KERNEL_VERSION = "k5"
 
 
@@ -61,6 +62,8 @@ MODES = {
     "split_fp16x2": dict(compute="split_fp16x2", mfma="f16", products=3, tol=1e-5),
     "split_int8": dict(compute="split_int8", mfma="i8", products=21, tol=1e-9),
     "f32": dict(compute="default", mfma="f32", products=1, tol=1e-5, dtype="f32"),
+    # the TTGT lowering of Section 2 (permute A, B, C around one matrix product)
+    "f64_ttgt": dict(compute="f64", mfma="f64", products=1, tol=1e-12, path="ttgt"),
 }
 
 
@@ -121,7 +124,11 @@ def bench_modes(comet, oracle, A, B, C0, steps, warmup, want):
         tdt = torch.float32 if cfg.get("dtype") == "f32" else torch.float64
         Ad, Bd = torch.from_numpy(A).to(dev, tdt), torch.from_numpy(B).to(dev, tdt)
         Cd = torch.from_numpy(C0).to(dev, tdt)
-        run = lambda: comet.contract(SPEC, Ad, Bd, Cd, alpha=1.0, beta=1.0, compute=cfg["compute"])
+        if cfg.get("path"):
+            plan = comet.Plan(SPEC, Ad, Bd, Cd, compute=cfg["compute"], path=cfg["path"])
+            run = lambda: plan(Ad, Bd, Cd, alpha=1.0, beta=1.0)
+        else:
+            run = lambda: comet.contract(SPEC, Ad, Bd, Cd, alpha=1.0, beta=1.0, compute=cfg["compute"])
         run()
         torch.cuda.synchronize()
         idx = torch.from_numpy(pts).to(dev)
@@ -195,8 +202,12 @@ def bench_triples(comet, oracle, reps):
     ref = oracle.contract_points(spec, A, B, pts)
     flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
     out = {}
-    for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2", "split_int8"):
-        run = lambda: comet.contract(spec, Ad, Bd, C, compute=mode)
+    for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2", "split_int8", "f64_ttgt"):
+        if mode == "f64_ttgt":
+            plan = comet.Plan(spec, Ad, Bd, C, compute="f64", path="ttgt")
+            run = lambda: plan(Ad, Bd, C)
+        else:
+            run = lambda: comet.contract(spec, Ad, Bd, C, compute=mode)
         run()
         torch.cuda.synchronize()
         err = oracle.relerr(C[tuple(torch.from_numpy(pts).to(dev).T)].cpu().numpy(), ref)
@@ -209,6 +220,43 @@ def bench_triples(comet, oracle, reps):
                      "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                      "frac_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "relerr_vs_oracle": err}
     del C, flush
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_permute(comet, reps):
+    """The permute kernel (TTGT's transposes and ta.copy): HBM bytes moved per second.
+
+    Cases: a config-2 operand brought into (M, K) order, the config-3 output
+    returned from (M, N) order to its own (both share a short unit dimension),
+    and a plain 8192 x 8192 transpose."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+    cases = [("aick=acik", dict(a=96, c=96, i=32, k=32)),
+             ("abcijk=aijbck", dict(a=32, b=32, c=32, i=16, j=16, k=16)),
+             ("ji=ij", dict(i=8192, j=8192))]
+    out = {}
+    g = torch.Generator(device=dev)
+    g.manual_seed(15)
+    for spec, ext in cases:
+        lo, li = spec.split("=")
+        x = torch.rand(tuple(ext[c] for c in li), dtype=torch.float64, device=dev, generator=g)
+        y = torch.empty(tuple(ext[c] for c in lo), dtype=torch.float64, device=dev)
+        comet.permute(spec, x, y)
+        torch.cuda.synchronize()
+        exact = bool(torch.equal(y, x.permute(*[li.index(c) for c in lo])))
+        tot = 0.0
+        for _ in range(reps):
+            flush.fill_(1.0)
+            tot += timed(lambda: comet.permute(spec, x, y), 1, stream)
+        ms = tot / reps
+        nbytes = 2.0 * x.numel() * 8
+        out[spec] = {"ms": round(ms, 4), "bytes": nbytes, "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "exact": exact}
+        del x, y
+    del flush
     torch.cuda.empty_cache()
     return out
 
@@ -360,6 +408,7 @@ def main():
     if not args.only_headline:
         line["backward"] = bench_backward(comet, oracle, A, B, C0, reps=5)
         line["triples"] = bench_triples(comet, oracle, reps=5)
+        line["permute"] = bench_permute(comet, reps=5)
         line["batch"] = bench_batch(comet, oracle, reps=3)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(A, B, C0)
