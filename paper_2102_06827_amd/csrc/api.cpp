@@ -170,8 +170,47 @@ int tile_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
 struct Schedule {
   int tile = 1;
   int sk_tiles = 0, sk_blocks = 0;
+  int persist = 0;
   double us = 1e300;
 };
+
+// Workgroups of the persistent kernel of `tile` resident per CU (0: none).
+int persistent_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
+  GettLaunch g{};
+  g.dtype = an.dtype == COMET_F64 ? 0 : 1;
+  g.compute = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  g.layoutA = an.layoutA;
+  g.layoutB = an.layoutB;
+  g.vecA = vecA;
+  g.vecB = vecB;
+  g.tile = tile;
+  g.persistent = 1;
+  return gett_occupancy(g);
+}
+
+// Short summations: a workgroup per tile spends most of its life on the
+// latency of its first loads and on draining its pipeline (about three
+// K steps' worth on MI355X), so with at most kPersistMaxSteps steps per tile
+// and at least two tiles per resident workgroup the persistent kernel, which
+// overlaps one tile's epilogue and the next tile's loads, takes over.
+constexpr int kPersistMaxSteps = 8;
+
+void persist_choice(const Analysis &an, int cus, bool vecA, bool vecB, Schedule &sc) {
+  const char *env = std::getenv("COMET_GETT_PERSIST");
+  int bm, bn, bk;
+  gett_tile_shape(sc.tile, &bm, &bn, &bk);
+  const int64_t T = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+  const int64_t nk = (an.k + bk - 1) / bk;
+  const int res = persistent_resident(an, sc.tile, vecA, vecB);
+  if (env && *env) {
+    const int v = std::atoi(env);
+    sc.persist = (v > 0 && res > 0) ? v : 0;
+  } else {
+    const int64_t S = int64_t(std::max(cus, 1)) * res;
+    sc.persist = (res > 0 && nk <= kPersistMaxSteps && T >= 2 * S) ? int(S) : 0;
+  }
+  if (sc.persist > 0) sc.sk_tiles = sc.sk_blocks = 0;
+}
 
 // Modeled time of `tile`, whole tiles only and with the stream-K split;
 // returns the better of the two.
@@ -257,6 +296,7 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
   if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
   sk_override(an, best);
   if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
+  persist_choice(an, cus, vecA, vecB, best);
   return best;
 }
 
@@ -264,10 +304,11 @@ void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
   Analysis &an = p->an;
   Schedule sc = pick_schedule(an, cus, p->vecA_tables, p->vecB_tables, forced_tile);
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
-  if (!native || an.empty_out || an.empty_sum) sc.sk_tiles = sc.sk_blocks = 0;
+  if (!native || an.empty_out || an.empty_sum) sc.sk_tiles = sc.sk_blocks = sc.persist = 0;
   an.tile = sc.tile;
   an.sk_tiles = sc.sk_tiles;
   an.sk_blocks = sc.sk_blocks;
+  an.persist = sc.persist;
   const size_t slot = gett_sk_slot_bytes(sc.tile, an.compute == COMET_COMPUTE_F64 ? 0 : 1);
   p->sk_bytes = sc.sk_tiles > 0 ? align256(2 * size_t(sc.sk_blocks) * slot) : 0;
 }
@@ -449,6 +490,7 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
     g.sk.blocks = an.sk_blocks;
     g.sk.ws = ws;
   }
+  if (an.persist > 0 && g.tile == an.tile) g.persistent = an.persist;
   HIP_TRY(launch_gett(g, s), "gett launch");
   return COMET_OK;
 }
@@ -582,7 +624,9 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) cus = 256;
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
   if (tc.mode() == 0 || !native || an.empty_out || an.empty_sum) return COMET_OK;
-  if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH") || std::getenv("COMET_GETT_SK")) return COMET_OK;
+  if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH") || std::getenv("COMET_GETT_SK") ||
+      std::getenv("COMET_GETT_PERSIST"))
+    return COMET_OK;
   const std::string key = tune_key(an, arch_id(p->device));
   TuneEntry best;
   if (!(tc.mode() == 1 && tc.lookup(key, &best))) {
@@ -696,6 +740,9 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
   const char *skv = std::getenv("COMET_GETT_SK");
   k += "|";
   if (skv) k += skv;
+  const char *pv = std::getenv("COMET_GETT_PERSIST");
+  k += "|";
+  if (pv) k += pv;
   k += "|t" + std::to_string(tune_cache().mode());
   return k;
 }

@@ -126,7 +126,14 @@ struct Loader {
   static constexpr bool vec = VECLD;
 
   __device__ __forceinline__ void init(int tid, int64_t r0, int64_t Rtot, const int64_t *__restrict__ offR_) {
-    const glb_t<const int64_t> *offR = to_glb(offR_);
+    init_from(tid, r0, Rtot, to_glb(offR_), 0);
+  }
+
+  // Row offsets from `rows`, where rows[g - base] holds the table entry of
+  // row g (base 0: the table itself; base r0: a copy of the tile's R entries
+  // staged in LDS).  Rows past Rtot are masked and read entry `base`.
+  template <typename Rows>
+  __device__ __forceinline__ void init_from(int tid, int64_t r0, int64_t Rtot, Rows rows, int64_t base) {
     rmask = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -144,7 +151,7 @@ struct Loader {
         // K-contiguous and vector reads share the vector's first row offset
         const int64_t g = (LAYOUT == 0 || vec) ? gr : gr + i;
         const bool ok = g < Rtot;
-        roff[p][i] = offR[ok ? g : 0];
+        roff[p][i] = rows[(ok ? g : base) - base];
         rmask |= (ok ? 1u : 0u) << (p * VEC + i);
       }
     }
@@ -260,6 +267,7 @@ constexpr int gett_lds_elems() {
 // FM x FN MFMA blocks of 16 x 16.
 template <typename Tc, int BM, int BN, int WGM, int WGN>
 struct WaveTile {
+  typedef Tc elem_t;
   typedef typename AccT<Tc>::type acc_t;
   static constexpr int NT = 64 * WGM * WGN;
   static constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -267,6 +275,28 @@ struct WaveTile {
   static_assert(FM * 16 == WM && FN * 16 == WN, "wave tile must be a multiple of 16");
   acc_t acc[FM][FN];
 };
+
+// One BK step of the product from the LDS tiles a_s (BM x BK) and b_s
+// (BN x BK): every wave multiplies its FM x FN MFMA blocks.
+template <typename LoadA, typename LoadB, int BK, typename WT>
+__device__ __forceinline__ void gett_mma_step(WT &w, const lds_t<typename WT::elem_t> *a_s,
+                                              const lds_t<typename WT::elem_t> *b_s, int lane, int wm0,
+                                              int wn0) {
+  typedef typename WT::elem_t Tc;
+#pragma unroll
+  for (int k4 = 0; k4 < BK; k4 += 4) {
+    const int kr = k4 + (lane >> 4);
+    Tc af[WT::FM], bf[WT::FN];
+#pragma unroll
+    for (int i = 0; i < WT::FM; ++i) af[i] = a_s[LoadA::idx(wm0 + i * 16 + (lane & 15), kr)];
+#pragma unroll
+    for (int j = 0; j < WT::FN; ++j) bf[j] = b_s[LoadB::idx(wn0 + j * 16 + (lane & 15), kr)];
+#pragma unroll
+    for (int i = 0; i < WT::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < WT::FN; ++j) w.acc[i][j] = mfma16(af[i], bf[j], w.acc[i][j]);
+  }
+}
 
 // Accumulate the product of the BM x BN output tile at (m0, n0) over the
 // summation steps [s_begin, s_end) of BK indices each: gather A and B through
@@ -320,21 +350,7 @@ __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &
     lb.load(B, (step + 1) * BK, K);
     la.fetch_k(t.offAk, (step + 2) * BK, K);
     lb.fetch_k(t.offBk, (step + 2) * BK, K);
-    const lds_t<Tc> *a_s = sA[cur];
-    const lds_t<Tc> *b_s = sB[cur];
-#pragma unroll
-    for (int k4 = 0; k4 < BK; k4 += 4) {
-      const int kr = k4 + (lane >> 4);
-      Tc af[FM], bf[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = a_s[LoadA::idx(wm0 + i * 16 + (lane & 15), kr)];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = b_s[LoadB::idx(wn0 + j * 16 + (lane & 15), kr)];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) w.acc[i][j] = mfma16(af[i], bf[j], w.acc[i][j]);
-    }
+    gett_mma_step<LoadA, LoadB, BK>(w, sA[cur], sB[cur], lane, wm0, wn0);
     la.store(sA[cur ^ 1]);
     lb.store(sB[cur ^ 1]);
     __syncthreads();
@@ -368,6 +384,39 @@ __device__ __forceinline__ void gett_store(const WaveTile<Tc, BM, BN, WGM, WGN> 
         const int64_t m = m0 + wm0 + i * 16 + acc_row<Tc>(lane, r);
         if (m >= M) continue;
         const int64_t addr = offCm[m] + cn;
+        Te v = al * Te(w.acc[i][j][r]);
+        if (read_c) v = v + be * Te(gC[addr]);
+        gC[addr] = Tin(v);
+      }
+    }
+  }
+}
+
+// gett_store with the tile's C offsets read from LDS: cm[r] = offCm[m0 + r],
+// cn[c] = offCn[n0 + c] (entries past M or N are never read).
+template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM, WGN> &w, Tin *__restrict__ C,
+                                                  const lds_t<int64_t> *cm, const lds_t<int64_t> *cn, int64_t M,
+                                                  int64_t N, double alpha, double beta, int64_t m0, int64_t n0) {
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
+  const Te al = Te(alpha), be = Te(beta);
+  const bool read_c = beta != 0.0;
+  glb_t<Tin> *const gC = to_glb(C);
+#pragma unroll
+  for (int j = 0; j < WT::FN; ++j) {
+    const int nl = wn0 + j * 16 + (lane & 15);
+    if (n0 + nl >= N) continue;
+    const int64_t cnv = cn[nl];
+#pragma unroll
+    for (int i = 0; i < WT::FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ml = wm0 + i * 16 + acc_row<Tc>(lane, r);
+        if (m0 + ml >= M) continue;
+        const int64_t addr = cm[ml] + cnv;
         Te v = al * Te(w.acc[i][j][r]);
         if (read_c) v = v + be * Te(gC[addr]);
         gC[addr] = Tin(v);

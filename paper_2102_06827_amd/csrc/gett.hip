@@ -129,6 +129,159 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
   }
 }
 
+// Persistent schedule for short summations (a few BK steps per tile), where
+// a workgroup per tile would spend most of its life on the latency of its
+// first loads and on draining its pipeline.  Workgroup s of S walks the tiles
+// s, s + S, s + 2S, ... (tile ids in the XCD-aware order, so they stay on the
+// workgroup's XCD) as one flat sequence of BK steps: the first step of the
+// next tile is loaded while the last step of the current one is multiplied,
+// and the current tile's results are stored while the next tile's data are
+// in flight.  The row-offset entries a tile's loads need are staged in LDS
+// two tiles ahead and its C offsets one tile ahead (each double-buffered by
+// tile parity), so that no table read sits on the critical path.
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_persistent_kernel(
+    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+    int64_t K, double alpha, double beta, int tilesM, int tilesN) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  typedef Loader<Tin, Tc, BM, BK, LA, VA, NT> LoadA;
+  typedef Loader<Tin, Tc, BN, BK, LB, VB, NT> LoadB;
+  typedef typename WT::acc_t acc_t;
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
+  __shared__ int64_t rows_s[2][BM + BN];   // offAm / offBn entries of a tile
+  __shared__ int64_t ctab_s[2][BM + BN];   // offCm / offCn entries of a tile
+  lds_t<Tc> *const s0 = to_lds(smem);
+  lds_t<Tc> *sA[2] = {s0, s0 + LoadA::ELEMS};
+  lds_t<Tc> *sB[2] = {s0 + 2 * LoadA::ELEMS, s0 + 2 * LoadA::ELEMS + LoadB::ELEMS};
+  lds_t<int64_t> *const rows = to_lds(&rows_s[0][0]);
+  lds_t<int64_t> *const ctab = to_lds(&ctab_s[0][0]);
+
+  const int T = tilesM * tilesN, S = gridDim.x, sb = blockIdx.x;
+  if (sb >= T) return;   // uniform: a workgroup without tiles
+  const int ntile = (T - 1 - sb) / S + 1;
+  const int64_t nk = (K + BK - 1) / BK;
+  const int64_t total = int64_t(ntile) * nk;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
+  auto origin = [&](int j, int64_t *m0, int64_t *n0) {
+    int tm, tn;
+    tile_coords(sb + j * S, tilesM, tilesN, &tm, &tn);
+    *m0 = int64_t(tm) * BM;
+    *n0 = int64_t(tn) * BN;
+  };
+  // table entry x of tile j for the staging threads: rows (offAm, offBn) and
+  // C offsets (offCm, offCn); x < BM: M side, else N side
+  auto table_entry = [&](int j, int x, const int64_t *tm_, const int64_t *tn_) -> int64_t {
+    int64_t m0, n0;
+    origin(j, &m0, &n0);
+    if (x < BM) {
+      const int64_t m = m0 + x < M ? m0 + x : M - 1;
+      return to_glb(tm_)[m];
+    }
+    const int64_t n = n0 + (x - BM) < N ? n0 + (x - BM) : N - 1;
+    return to_glb(tn_)[n];
+  };
+
+  WT w;
+#pragma unroll
+  for (int i = 0; i < WT::FM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < WT::FN; ++jj) w.acc[i][jj] = acc_t{0, 0, 0, 0};
+  LoadA la;
+  LoadB lb;
+  int64_t m0, n0;
+  origin(0, &m0, &n0);
+  la.init(tid, m0, M, t.offAm);
+  lb.init(tid, n0, N, t.offBn);
+  // prologue: rows of tile 1 and C offsets of tile 0 into LDS, step 0 loaded
+  for (int x = tid; x < BM + BN; x += NT) {
+    if (ntile > 1) rows[1 * (BM + BN) + x] = table_entry(1, x, t.offAm, t.offBn);
+    ctab[x] = table_entry(0, x, t.offCm, t.offCn);
+  }
+  la.fetch_k(t.offAk, 0, K);
+  lb.fetch_k(t.offBk, 0, K);
+  la.load(A, 0, K);
+  lb.load(B, 0, K);
+  la.fetch_k(t.offAk, nk > 1 ? BK : 0, K);
+  lb.fetch_k(t.offBk, nk > 1 ? BK : 0, K);
+  la.store(sA[0]);
+  lb.store(sB[0]);
+  __syncthreads();
+
+  int j = 0;
+  int64_t k = 0;
+  for (int64_t g = 0; g < total; ++g) {
+    const int cur = int(g & 1);
+    const bool last = k == nk - 1;
+    // tables of tiles j + 2 (rows) and j + 1 (C offsets), fetched now and
+    // written to LDS after this step's product
+    int64_t rv[(BM + BN + NT - 1) / NT], cv[(BM + BN + NT - 1) / NT];
+    const bool stage = k == 0;
+    if (stage) {
+#pragma unroll
+      for (int q = 0; q < (BM + BN + NT - 1) / NT; ++q) {
+        const int x = tid + q * NT;
+        if (x < BM + BN) {
+          rv[q] = j + 2 < ntile ? table_entry(j + 2, x, t.offAm, t.offBn) : 0;
+          cv[q] = j + 1 < ntile ? table_entry(j + 1, x, t.offCm, t.offCn) : 0;
+        }
+      }
+    }
+    // the next step's data: the next tile's first step after a last step
+    if (g + 1 < total) {
+      if (last) {
+        int64_t m1, n1;
+        origin(j + 1, &m1, &n1);
+        const lds_t<int64_t> *r1 = rows + ((j + 1) & 1) * (BM + BN);
+        la.init_from(tid, m1, M, r1, m1);
+        lb.init_from(tid, n1, N, r1 + BM, n1);
+      }
+      const int64_t k1 = last ? 0 : k + 1;
+      la.load(A, k1 * BK, K);
+      lb.load(B, k1 * BK, K);
+      // K-table entries for the step after that
+      const int64_t k2 = (k1 + 1 == nk) ? 0 : k1 + 1;
+      la.fetch_k(t.offAk, k2 * BK, K);
+      lb.fetch_k(t.offBk, k2 * BK, K);
+    }
+    gett_mma_step<LoadA, LoadB, BK>(w, sA[cur], sB[cur], lane, wm0, wn0);
+    if (last) {
+      origin(j, &m0, &n0);
+      const lds_t<int64_t> *ct = ctab + (j & 1) * (BM + BN);
+      gett_store_staged<Tin, Tc, BM, BN, WGM, WGN>(w, C, ct, ct + BM, M, N, alpha, beta, m0, n0);
+#pragma unroll
+      for (int i = 0; i < WT::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < WT::FN; ++jj) w.acc[i][jj] = acc_t{0, 0, 0, 0};
+    }
+    if (stage) {
+#pragma unroll
+      for (int q = 0; q < (BM + BN + NT - 1) / NT; ++q) {
+        const int x = tid + q * NT;
+        if (x < BM + BN) {
+          rows[(j & 1) * (BM + BN) + x] = rv[q];
+          ctab[((j + 1) & 1) * (BM + BN) + x] = cv[q];
+        }
+      }
+    }
+    if (g + 1 < total) {
+      la.store(sA[cur ^ 1]);
+      lb.store(sB[cur ^ 1]);
+    }
+    __syncthreads();
+    if (last) {
+      ++j;
+      k = 0;
+    } else {
+      ++k;
+    }
+  }
+}
+
 // Sum the workspace pieces of each split stream-K tile, in workgroup order,
 // and write alpha * sum + beta * C.  Workgroup (x, y) takes stream-K tile x
 // and accumulator element y = i * FN + j of every thread, so that a tile's
@@ -166,6 +319,17 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
                                                  int64_t(tm) * BM, int64_t(tn) * BN);
 }
 
+// the persistent kernel's LDS: the tile buffers plus two staged copies of a
+// tile's row and C offsets
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+constexpr bool persistent_fits() {
+  constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
+  return int(sizeof(Tc)) * gett_lds_elems<Tin, Tc, kTiles[TILE].bm, kTiles[TILE].bn, kTiles[TILE].bk, NT, LA, LB,
+                                          VA, VB>() +
+             4 * (kTiles[TILE].bm + kTiles[TILE].bn) * 8 <=
+         160 * 1024;
+}
+
 template <typename Tin, typename Tc, int TILE>
 constexpr bool tile_fits() {
   constexpr int V = 16 / int(sizeof(Tin));
@@ -181,10 +345,30 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
     constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn;
     constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
     if (g.occupancy) {
+      if (g.persistent > 0) {
+        if constexpr (!persistent_fits<Tin, Tc, TILE, LA, LB, VA, VB>()) {
+          *g.occupancy = 0;
+          return hipSuccess;
+        } else {
+          return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              g.occupancy, gett_persistent_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
+        }
+      }
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy, gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>,
                                                           NT, 0);
     }
     const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
+    if (g.persistent > 0) {
+      if constexpr (!persistent_fits<Tin, Tc, TILE, LA, LB, VA, VB>()) {
+        return hipErrorInvalidValue;
+      } else {
+        hipLaunchKernelGGL((gett_persistent_kernel<Tin, Tc, TILE, LA, LB, VA, VB>),
+                           dim3(std::min(g.persistent, tilesM * tilesN)), dim3(NT), 0, s,
+                           static_cast<const Tin *>(g.A), static_cast<const Tin *>(g.B), static_cast<Tin *>(g.C), g.t,
+                           g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+        return hipGetLastError();
+      }
+    }
     StreamK sk = g.sk;
     if (sk.blocks <= 0 || sk.tiles <= 0 || sk.tiles > tilesM * tilesN || !sk.ws) sk = StreamK{};
     const int dp = tilesM * tilesN - sk.tiles;

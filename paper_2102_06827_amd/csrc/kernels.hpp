@@ -39,6 +39,7 @@ struct GettLaunch {
   int tile;            // tile variant
   int *occupancy = nullptr;   // when set: store the resident workgroups per CU, launch nothing
   StreamK sk;
+  int persistent = 0;         // > 0: this many persistent workgroups walk the tiles (no stream-K)
 };
 
 hipError_t launch_gett(const GettLaunch &g, hipStream_t s);

@@ -85,6 +85,8 @@ struct Analysis {
   // stream-K: the last sk_tiles output tiles are split along K over
   // sk_blocks workgroups (0: every tile is computed whole)
   int sk_tiles = 0, sk_blocks = 0;
+  // > 0: the persistent kernel with this many workgroups (short summations)
+  int persist = 0;
   int split_slices = 5;
 
   TTGTChoice ttgt;

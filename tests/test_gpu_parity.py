@@ -450,3 +450,31 @@ def test_stream_k_is_deterministic(monkeypatch):
     first = run(spec, A, B, C0, 1.0, 0.5, "f64")
     for _ in range(3):
         assert np.array_equal(run(spec, A, B, C0, 1.0, 0.5, "f64"), first)
+
+
+PERSIST_CASES = [(3, "4"), (3, "1000"), (1, "5"), (0, "7"), (4, "2"), (5, "3"), (8, "3"), (2, "6")]
+
+
+@pytest.mark.parametrize("tile,grid", PERSIST_CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", [
+    ("abcijk=daij*bcdk", dict(a=5, b=6, c=7, d=9, i=4, j=6, k=8)),     # K = 9: one step per tile
+    ("abij=acik*bkcj", dict(a=20, b=18, c=6, i=9, j=8, k=6)),         # K = 36: two or three steps
+    ("ajbi=kcia*cjkb", dict(a=18, b=9, c=12, i=16, j=24, k=6)),       # A m-contiguous, K = 72
+])
+def test_persistent_schedule(tile, grid, dtype, spec, ext, monkeypatch):
+    """The persistent kernel (few workgroups walking many tiles, next tile's
+    loads overlapped with the current tile's epilogue) against the oracle."""
+    if dtype == "f32" and tile in (7, 8, 9):
+        pytest.skip("FP64-only tile")
+    monkeypatch.setenv("COMET_GETT_TILE", str(tile))
+    monkeypatch.setenv("COMET_GETT_PERSIST", grid)
+    check(spec, ext, dtype, seed=960 + tile, kind="integer", alpha=1.0, beta=1.0)
+    check(spec, ext, dtype, seed=980 + tile, alpha=-0.75, beta=0.5)
+
+
+def test_persistent_chosen_for_short_sums():
+    A = torch.zeros((32, 32, 16, 16), dtype=torch.float64, device="cuda")
+    B = torch.zeros((32, 32, 32, 16), dtype=torch.float64, device="cuda")
+    d = comet.Plan("abcijk=daij*bcdk", A, B).describe()
+    assert d["persist"] > 0 and d["sk_tiles"] == 0
