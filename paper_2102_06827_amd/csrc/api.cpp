@@ -828,7 +828,9 @@ comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len) {
     if (plan->an.path == COMET_PATH_GETT)
       res = tile_resident(plan->an, plan->an.tile, plan->vecA_tables, plan->vecB_tables);
     js.pop_back();
-    js += ",\"resident\":" + std::to_string(res) + "}";
+    js += ",\"resident\":" + std::to_string(res);
+    if (plan->split.ws_bytes > 0) js += ",\"split_tile\":" + std::to_string(plan->split.tile);
+    js += "}";
   }
   std::strncpy(buf, js.c_str(), len - 1);
   buf[len - 1] = 0;

@@ -36,12 +36,21 @@
 // also the transpose of TTGT), and the slice-pair matrix product on
 // v_mfma_f32_16x16x32_{bf16,f16}.
 #include <climits>
+#include <cstdlib>
 #include <type_traits>
 
 #include "split.hpp"
 
 namespace comet {
 namespace {
+
+// LDS and global pointers with their address spaces spelled out, so that
+// accesses compile to ds_* and global_* instructions (a flat access waits on
+// both memory counters).
+template <typename T> using lds_t = __attribute__((address_space(3))) T;
+template <typename T> using glb_t = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ lds_t<T> *to_lds(T *p) { return (lds_t<T> *)p; }
+template <typename T> __device__ __forceinline__ glb_t<T> *to_glb(T *p) { return (glb_t<T> *)p; }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -377,6 +386,170 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
   }
 }
 
+// ------------------------------------------ large-tile slice-pair GEMM --
+//
+// For the classic splits (BF16x3, FP16x2: FP32 accumulation, no periodic
+// fold) on large products: a 192 x 192 workgroup tile of 8 waves, each
+// owning 96 x 48 outputs (6 x 3 blocks of the 16x16x32 MFMA).  Every
+// fragment read from LDS then feeds 3 or 6 MFMAs (the 32 x 32 wave tile
+// above: 2), which takes the kernel off the LDS read limit, and a 3072^2
+// output is exactly 256 tiles, one per CU.
+
+constexpr int XBM = 192, XBN = 192;            // block tile
+constexpr int XWM = 2, XWN = 4;                // wave grid
+constexpr int XNT = 64 * XWM * XWN;
+
+template <typename ST, typename Tout, int MODE, int S>
+__global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restrict__ As, const ST *__restrict__ Bs,
+                                                              const int *__restrict__ eA, const int *__restrict__ eB,
+                                                              Tout *__restrict__ C, const int64_t *__restrict__ offCm,
+                                                              const int64_t *__restrict__ offCn, int64_t M, int64_t N,
+                                                              int64_t Mp, int64_t Np, int64_t Kp, double alpha,
+                                                              double beta, int tilesM, int tilesN) {
+  typedef Pairs<MODE, S> PP;
+  static_assert(PP::FOLD == 0, "the large tile keeps FP32 accumulators only");
+  typedef typename Vec8<ST>::type v8;
+  constexpr int WM = XBM / XWM, WN = XBN / XWN;      // 96 x 48
+  constexpr int FM = WM / 16, FN = WN / 16;          // 6 x 3
+  constexpr int NVA = S * XBM * (GBK / 8);           // 16-byte vectors per stage
+  constexpr int NVB = S * XBN * (GBK / 8);
+  constexpr int NV = (NVA + NVB) / XNT;              // per thread
+  static_assert(NV * XNT == NVA + NVB, "stage must split evenly over the workgroup");
+  constexpr int STAGE = S * (XBM + XBN) * GBK;       // elements per LDS buffer
+  static_assert(2 * STAGE * int(sizeof(ST)) <= 160 * 1024, "two stages must fit in LDS");
+  __shared__ __attribute__((aligned(16))) ST smem_[2 * STAGE];
+  lds_t<ST> *const smem = to_lds(smem_);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tm, tn;
+  {
+    const int total = tilesM * tilesN, X = 8, bid = blockIdx.x;
+    const int xcd = bid % X, local = bid / X, q = total / X, rem = total % X;
+    const int id = xcd * q + (xcd < rem ? xcd : rem) + local;
+    const int G = 4, per = G * tilesN, group = id / per, first = group * G;
+    const int gsize = tilesM - first < G ? tilesM - first : G;
+    const int in = id - group * per;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int64_t m0 = int64_t(tm) * XBM, n0 = int64_t(tn) * XBN;
+  const int wm0 = (wave / XWN) * WM, wn0 = (wave % XWN) * WN;
+
+  f4_t acc[PP::NACC][FM][FN];
+#pragma unroll
+  for (int a = 0; a < PP::NACC; ++a)
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[a][i][j] = f4_t{0, 0, 0, 0};
+
+  // a buffer holds A slices [S][XBM rows] then B slices [S][XBN rows]
+  auto a_at = [&](lds_t<ST> *buf, int p, int row, int c) { return buf + (p * XBM) * GBK + sw(row, c); };
+  auto b_at = [&](lds_t<ST> *buf, int p, int row, int c) {
+    return buf + S * XBM * GBK + (p * XBN) * GBK + sw(row, c);
+  };
+  const glb_t<const ST> *gA = to_glb(As);
+  const glb_t<const ST> *gB = to_glb(Bs);
+
+  v8 pre[NV];
+  const int64_t nst = Kp / GBK;
+  auto gload = [&](int64_t st) {
+    const int64_t k0 = (st < nst ? st : nst - 1) * GBK;
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int v = tid + u * XNT;
+      if (v < NVA) {
+        const int p = v / (XBM * 4), rem = v % (XBM * 4), row = rem / 4, kc = (rem % 4) * 8;
+        pre[u] = *reinterpret_cast<const glb_t<v8> *>(gA + (int64_t(p) * Mp + m0 + row) * Kp + k0 + kc);
+      } else {
+        const int w = v - NVA;
+        const int p = w / (XBN * 4), rem = w % (XBN * 4), row = rem / 4, kc = (rem % 4) * 8;
+        pre[u] = *reinterpret_cast<const glb_t<v8> *>(gB + (int64_t(p) * Np + n0 + row) * Kp + k0 + kc);
+      }
+    }
+  };
+  auto lstore = [&](lds_t<ST> *buf) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int v = tid + u * XNT;
+      if (v < NVA) {
+        const int p = v / (XBM * 4), rem = v % (XBM * 4), row = rem / 4, c = rem % 4;
+        *reinterpret_cast<lds_t<v8> *>(a_at(buf, p, row, c)) = pre[u];
+      } else {
+        const int w = v - NVA;
+        const int p = w / (XBN * 4), rem = w % (XBN * 4), row = rem / 4, c = rem % 4;
+        *reinterpret_cast<lds_t<v8> *>(b_at(buf, p, row, c)) = pre[u];
+      }
+    }
+  };
+  auto compute = [&](lds_t<ST> *buf) {
+    v8 bF[S][FN];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        bF[q][j] = *reinterpret_cast<const lds_t<v8> *>(b_at(buf, q, wn0 + j * 16 + (lane & 15), lane >> 4));
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      v8 aF[FM];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        aF[i] = *reinterpret_cast<const lds_t<v8> *>(a_at(buf, p, wm0 + i * 16 + (lane & 15), lane >> 4));
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        if (PP::use(p, q)) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[PP::acc(p, q)][i][j] = mfma_slice(aF[i], bF[q][j], acc[PP::acc(p, q)][i][j]);
+        }
+      }
+    }
+  };
+
+  gload(0);
+  lstore(smem);
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    lds_t<ST> *cur = smem + int(st & 1) * STAGE;
+    gload(st + 1);
+    compute(cur);
+    // the other buffer was last read before the previous barrier
+    lstore(smem + int((st + 1) & 1) * STAGE);
+    __syncthreads();
+  }
+
+  // epilogue: C = alpha * 2^(eA + eB) * sum_a scale(a) * acc[a] + beta * C
+  typedef typename std::conditional<sizeof(Tout) == 8, double, float>::type Te;
+  const bool read_c = beta != 0.0;
+  glb_t<Tout> *const gC = to_glb(C);
+#pragma unroll
+  for (int j = 0; j < FN; ++j) {
+    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
+    if (n >= N) continue;
+    const int64_t cn = offCn[n];
+    const int en = eB[n];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= M) continue;
+        const int em = eA[m];
+        double sum = 0.0;
+#pragma unroll
+        for (int a = 0; a < PP::NACC; ++a) sum += double(acc[a][i][j][r]) * PP::scale(a);
+        const int64_t addr = offCm[m] + cn;
+        const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(sum, em + en);
+        Te v = Te(alpha * prod);
+        if (read_c) v = v + Te(beta) * Te(gC[addr]);
+        gC[addr] = Tout(v);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------ INT8 slice-pair GEMM --
 
 constexpr int IBK = 64;          // summation indices per stage (one 16x16x64 MFMA)
@@ -594,6 +767,14 @@ hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &
                          static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp, sp.Np, sp.Kp, k0, len, alpha,
                          k0 == 0 ? beta : 1.0, tilesM, tilesN);
     }
+  } else if (sp.tile == 1) {
+    if constexpr (Pairs<MODE, S>::FOLD == 0) {
+      hipLaunchKernelGGL((split_gemm_big_kernel<ST, Tin, MODE, S>), dim3(int(sp.Mp / XBM) * int(sp.Np / XBN)),
+                         dim3(XNT), 0, s, As, Bs, eA, eB, static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp,
+                         sp.Np, sp.Kp, alpha, beta, int(sp.Mp / XBM), int(sp.Np / XBN));
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else
     hipLaunchKernelGGL((split_gemm_kernel<ST, Tin, MODE, S>), dim3(tilesM * tilesN), dim3(GNT), 0, s, As, Bs, eA,
                        eB, static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp, sp.Np, sp.Kp, alpha, beta,
@@ -641,10 +822,19 @@ Status split_prepare(const Analysis &an, SplitPlan &sp) {
     return Status::error(COMET_ERR_UNSUPPORTED, "split slices must be within 3..6");
   if (sp.mode == 3 && (sp.S < 3 || sp.S > 8))
     return Status::error(COMET_ERR_UNSUPPORTED, "int8 split slices must be within 3..8");
-  sp.Mp = round_up(an.m, GBM);
-  sp.Np = round_up(an.n, GBN);
+  // the large tile for the classic splits on large products, when padding
+  // to 192 wastes little (COMET_SPLIT_TILE=0/1 overrides)
+  sp.tile = 0;
+  if (sp.mode == 1 || sp.mode == 2) {
+    const double waste = double(round_up(an.m, XBM)) * double(round_up(an.n, XBN)) / (double(an.m) * double(an.n));
+    sp.tile = (an.m >= 1536 && an.n >= 1536 && waste <= 1.1) ? 1 : 0;
+    const char *env = std::getenv("COMET_SPLIT_TILE");
+    if (env && *env) sp.tile = std::atoi(env) == 1 ? 1 : 0;
+  }
+  sp.Mp = round_up(an.m, sp.tile == 1 ? XBM : GBM);
+  sp.Np = round_up(an.n, sp.tile == 1 ? XBN : GBN);
   sp.Kp = round_up(an.k, sp.mode == 3 ? IBK : GBK);
-  const int64_t tiles = (sp.Mp / GBM) * (sp.Np / GBN);
+  const int64_t tiles = sp.tile == 1 ? (sp.Mp / XBM) * (sp.Np / XBN) : (sp.Mp / GBM) * (sp.Np / GBN);
   if (tiles > INT_MAX || (sp.Mp / PR) * (sp.Kp / PK) > INT_MAX || (sp.Np / PR) * (sp.Kp / PK) > INT_MAX)
     return Status::error(COMET_ERR_UNSUPPORTED, "problem too large for the split path");
   const size_t es = sp.mode == 3 ? 1 : 2;

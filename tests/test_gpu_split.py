@@ -176,3 +176,31 @@ def test_int8_long_summation_is_chunked():
     print_case("int8 long K")
     got = run("ij=ik*kj", A, B, C0, 1.0, 1.0, torch.float64, "split_int8")
     assert oracle.relerr(got, oracle.contract("ij=ik*kj", A, B, C0, beta=1.0)) <= 1e-9
+
+
+@pytest.mark.parametrize("mode", ["split_bf16x3", "split_fp16x2"])
+@pytest.mark.parametrize("spec,ext", CASES)
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_split_large_tile_forced(spec, ext, mode, storage, monkeypatch):
+    """The 192 x 192 slice-pair kernel on ragged problems (operands padded to
+    multiples of 192): same bars, integer inputs bit for bit."""
+    monkeypatch.setenv("COMET_SPLIT_TILE", "1")
+    tdt = torch.float64 if storage == "f64" else torch.float32
+    cast = np.float64 if storage == "f64" else np.float32
+    print_case("split large tile", spec, mode, storage)
+    A, B, C0 = inputs(spec, ext, 830, kind="normal", beta=True)
+    A, B, C0 = A.astype(cast), B.astype(cast), C0.astype(cast)
+    got = run(spec, A, B, C0, 1.25, -0.5, tdt, mode)
+    ref = oracle.contract(spec, A, B, C0, alpha=1.25, beta=-0.5)
+    assert oracle.relerr(got, ref) <= 1e-5
+    Ai, Bi, _ = inputs(spec, ext, 831, kind="integer", beta=False)
+    gi = run(spec, Ai, Bi, None, 1.0, 0.0, tdt, mode)
+    assert np.array_equal(gi, oracle.contract(spec, Ai.astype(cast), Bi.astype(cast)))
+
+
+def test_split_large_tile_is_chosen_for_large_products():
+    V, O = 96, 32
+    A = torch.zeros((V, V, O, O), dtype=torch.float64, device="cuda")
+    B = torch.zeros((V, O, V, O), dtype=torch.float64, device="cuda")
+    d = comet.Plan("abij=acik*bkcj", A, B, compute="split_bf16x3").describe()
+    assert d.get("split_tile") == 1
