@@ -35,6 +35,7 @@
 // the operand's unit-stride label, then write K-contiguous slices -- this is
 // also the transpose of TTGT), and the slice-pair matrix product on
 // v_mfma_f32_16x16x32_{bf16,f16}.
+#include <algorithm>
 #include <climits>
 #include <cstdlib>
 #include <type_traits>
@@ -76,30 +77,72 @@ __device__ __forceinline__ f4_t mfma_slice(f16x8 a, f16x8 b, f4_t c) {
 // ---------------------------------------------------------------- slicing --
 
 constexpr int PR = 64;    // slicer tile rows
-constexpr int PK = 32;    // slicer tile summation indices
+constexpr int PK = 64;    // slicer tile summation indices
 constexpr int PT = 256;   // slicer threads
+constexpr int PI = PR * PK / PT;   // elements per thread per tile
 
-// Gather a PR x PK tile into LDS (zeros outside the operand).  Threads walk
-// the operand's unit-stride dimension: k for LAYOUT 0, rows for LAYOUT 1.
+// Element e (0..PI-1) of thread tid in a PR x PK tile.  Threads walk the
+// operand's unit-stride dimension: k for LAYOUT 0, rows for LAYOUT 1.
+template <int LAYOUT>
+__device__ __forceinline__ void tile_pos(int tid, int e, int *rl, int *kl) {
+  if (LAYOUT == 0) {
+    *kl = tid % PK;
+    *rl = tid / PK + (PT / PK) * e;
+  } else {
+    *rl = tid % PR;
+    *kl = tid / PR + (PT / PR) * e;
+  }
+}
+
+// The PI elements of a thread in the PR x PK tile at (r0, k0), zero outside
+// the operand.  ro[e] holds the row offset of element e (hoisted by the
+// caller: rows are fixed per thread).  The loads are branch-free -- clamped
+// indices, zeros applied afterwards -- so that all of them are in flight at
+// once instead of one wait per element.
 template <typename Tin, int LAYOUT>
-__device__ __forceinline__ void gather_tile(double (*t)[PK + 1], const Tin *__restrict__ base,
-                                            const int64_t *__restrict__ offR, const int64_t *__restrict__ offK,
-                                            int64_t r0, int64_t k0, int64_t R, int64_t K) {
+__device__ __forceinline__ void load_tile(double *x, const Tin *__restrict__ base, const int64_t *ro,
+                                          const int64_t *__restrict__ offK, int64_t r0, int64_t k0, int64_t R,
+                                          int64_t K) {
   const int tid = threadIdx.x;
+  Tin v[PI];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int e = 0; e < PI; ++e) {
     int rl, kl;
-    if (LAYOUT == 0) {
-      kl = tid % PK;
-      rl = tid / PK + 8 * i;
-    } else {
-      rl = tid % PR;
-      kl = tid / PR + 4 * i;
-    }
-    const int64_t r = r0 + rl, k = k0 + kl;
-    double x = 0.0;
-    if (r < R && k < K) x = double(base[offR[r] + offK[k]]);
-    t[rl][kl] = x;
+    tile_pos<LAYOUT>(tid, e, &rl, &kl);
+    const int64_t k = k0 + kl;
+    v[e] = base[ro[e] + offK[k < K ? k : K - 1]];
+  }
+#pragma unroll
+  for (int e = 0; e < PI; ++e) {
+    int rl, kl;
+    tile_pos<LAYOUT>(tid, e, &rl, &kl);
+    x[e] = (r0 + rl < R && k0 + kl < K) ? double(v[e]) : 0.0;
+  }
+}
+
+// Gather a PR x PK tile into LDS (zeros outside the operand).
+template <typename Tin, int LAYOUT>
+__device__ __forceinline__ void gather_tile(double (*t)[PK + 1], const Tin *__restrict__ base, const int64_t *ro,
+                                            const int64_t *__restrict__ offK, int64_t r0, int64_t k0, int64_t R,
+                                            int64_t K) {
+  double x[PI];
+  load_tile<Tin, LAYOUT>(x, base, ro, offK, r0, k0, R, K);
+#pragma unroll
+  for (int e = 0; e < PI; ++e) {
+    int rl, kl;
+    tile_pos<LAYOUT>(threadIdx.x, e, &rl, &kl);
+    t[rl][kl] = x[e];
+  }
+}
+
+// Row offsets of a thread's elements (fixed for every tile of the same rows).
+template <int LAYOUT>
+__device__ __forceinline__ void row_offsets(int64_t *ro, const int64_t *__restrict__ offR, int64_t r0, int64_t R) {
+#pragma unroll
+  for (int e = 0; e < PI; ++e) {
+    int rl, kl;
+    tile_pos<LAYOUT>(threadIdx.x, e, &rl, &kl);
+    ro[e] = offR[r0 + rl < R ? r0 + rl : R - 1];
   }
 }
 
@@ -108,42 +151,51 @@ __global__ __launch_bounds__(256) void fill_int_kernel(int *__restrict__ p, int6
     p[i] = v;
 }
 
-// e[r] = max over k of the binary exponent of the operand row r
+// e[r] = max over k of the binary exponent of the operand row r.  Block
+// (x, y) takes rows [64x, 64x + 64) and the y-th of gridDim.y equal ranges of
+// summation tiles; the maxima stay in registers over the range, so a row
+// receives one atomic update per block.
 template <typename Tin, int LAYOUT>
 __global__ __launch_bounds__(PT) void split_exp_kernel(const Tin *__restrict__ base, const int64_t *__restrict__ offR,
                                                        const int64_t *__restrict__ offK, int64_t R, int64_t K,
-                                                       int64_t tilesR, int *__restrict__ e) {
+                                                       int *__restrict__ e) {
   __shared__ int emax[PR];
   const int tid = threadIdx.x;
   if (tid < PR) emax[tid] = kExpNone;
-  __syncthreads();
-  const int64_t r0 = (int64_t(blockIdx.x) % tilesR) * PR, k0 = (int64_t(blockIdx.x) / tilesR) * PK;
+  const int64_t r0 = int64_t(blockIdx.x) * PR;
+  const int64_t tilesK = (K + PK - 1) / PK;
+  const int64_t kt0 = tilesK * blockIdx.y / gridDim.y, kt1 = tilesK * (blockIdx.y + 1) / gridDim.y;
+  int64_t ro[PI];
+  row_offsets<LAYOUT>(ro, offR, r0, R);
+  // LAYOUT 0: a thread's elements lie in PI rows; LAYOUT 1: in one row
+  constexpr int NR = LAYOUT == 0 ? PI : 1;
+  int mx[NR];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int q = 0; q < NR; ++q) mx[q] = kExpNone;
+  for (int64_t kt = kt0; kt < kt1; ++kt) {
+    double x[PI];
+    load_tile<Tin, LAYOUT>(x, base, ro, offK, r0, kt * PK, R, K);
+#pragma unroll
+    for (int q = 0; q < PI; ++q) {
+      int ex = kExpNone;
+      if (x[q] != 0.0) (void)frexp(x[q], &ex);
+      mx[LAYOUT == 0 ? q : 0] = ex > mx[LAYOUT == 0 ? q : 0] ? ex : mx[LAYOUT == 0 ? q : 0];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
     int rl, kl;
-    if (LAYOUT == 0) {
-      kl = tid % PK;
-      rl = tid / PK + 8 * i;
-    } else {
-      rl = tid % PR;
-      kl = tid / PR + 4 * i;
-    }
-    const int64_t r = r0 + rl, k = k0 + kl;
-    if (r < R && k < K) {
-      const double x = double(base[offR[r] + offK[k]]);
-      if (x != 0.0) {
-        int ex;
-        (void)frexp(x, &ex);
-        atomicMax(&emax[rl], ex);
-      }
-    }
+    tile_pos<LAYOUT>(tid, q, &rl, &kl);
+    if (mx[q] != kExpNone) atomicMax(&emax[rl], mx[q]);
   }
   __syncthreads();
   if (tid < PR && r0 + tid < R && emax[tid] != kExpNone) atomicMax(&e[r0 + tid], emax[tid]);
 }
 
 // Cut a PR x PK tile into S slices, written K-contiguous: out[p][r][k]
-// (pitch Kp, Rp rows per slice).  Thread t writes 8 consecutive k of row t/4.
+// (pitch Kp, Rp rows per slice).  Thread t writes 16 consecutive k of row
+// t/4, so the four threads of a row write one 128-byte line per 16-bit slice.
 template <typename Tin, typename ST, int LAYOUT, int MODE, int S>
 __global__ __launch_bounds__(PT) void split_pack_kernel(const Tin *__restrict__ base,
                                                         const int64_t *__restrict__ offR,
@@ -152,48 +204,56 @@ __global__ __launch_bounds__(PT) void split_pack_kernel(const Tin *__restrict__ 
                                                         ST *__restrict__ out, int64_t Rp, int64_t Kp) {
   __shared__ double t[PR][PK + 1];
   const int64_t r0 = (int64_t(blockIdx.x) % tilesR) * PR, k0 = (int64_t(blockIdx.x) / tilesR) * PK;
-  gather_tile<Tin, LAYOUT>(t, base, offR, offK, r0, k0, R, K);
+  {
+    int64_t ro[PI];
+    row_offsets<LAYOUT>(ro, offR, r0, R);
+    gather_tile<Tin, LAYOUT>(t, base, ro, offK, r0, k0, R, K);
+  }
   __syncthreads();
   const int tid = threadIdx.x;
-  const int rl = tid / 4, kc = (tid % 4) * 8;
+  const int rl = tid / 4;
   const int64_t r = r0 + rl;
   const int ex = r < R ? e[r] : kExpNone;
-  typename Vec8<ST>::type sl[S];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    double xs = ex == kExpNone ? 0.0 : ldexp(t[rl][kc + j], -ex);   // |xs| < 1, exact
-    if (MODE == 0) {
+  for (int half = 0; half < 2; ++half) {
+    const int kc = (tid % 4) * 16 + half * 8;
+    typename Vec8<ST>::type sl[S];
 #pragma unroll
-      for (int p = 0; p < S; ++p) {
-        const double tt = xs * 256.0;
-        const double s = trunc(tt);                                   // |s| <= 255
-        sl[p][j] = ST(float(ldexp(s, -8 * (p + 1))));                 // exact in 16 bits
-        xs = tt - s;                                                  // exact remainder
-      }
-    } else if (MODE == 1) {
+    for (int j = 0; j < 8; ++j) {
+      double xs = ex == kExpNone ? 0.0 : ldexp(t[rl][kc + j], -ex);   // |xs| < 1, exact
+      if (MODE == 0) {
 #pragma unroll
-      for (int p = 0; p < S; ++p) {
-        const ST b = ST(float(xs));
-        sl[p][j] = b;
-        xs = xs - double(float(b));
-      }
-    } else if (MODE == 2) {
-      const ST h0 = ST(float(xs));
-      sl[0][j] = h0;
-      sl[1][j] = ST(float((xs - double(float(h0))) * 2048.0));
-    } else {
+        for (int p = 0; p < S; ++p) {
+          const double tt = xs * 256.0;
+          const double s = trunc(tt);                                   // |s| <= 255
+          sl[p][j] = ST(float(ldexp(s, -8 * (p + 1))));                 // exact in 16 bits
+          xs = tt - s;                                                  // exact remainder
+        }
+      } else if (MODE == 1) {
 #pragma unroll
-      for (int p = 0; p < S; ++p) {
-        const double tt = xs * 128.0;
-        const double s = trunc(tt);                                   // |s| <= 127
-        sl[p][j] = ST(int(s));
-        xs = tt - s;
+        for (int p = 0; p < S; ++p) {
+          const ST b = ST(float(xs));
+          sl[p][j] = b;
+          xs = xs - double(float(b));
+        }
+      } else if (MODE == 2) {
+        const ST h0 = ST(float(xs));
+        sl[0][j] = h0;
+        sl[1][j] = ST(float((xs - double(float(h0))) * 2048.0));
+      } else {
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          const double tt = xs * 128.0;
+          const double s = trunc(tt);                                   // |s| <= 127
+          sl[p][j] = ST(int(s));
+          xs = tt - s;
+        }
       }
     }
-  }
 #pragma unroll
-  for (int p = 0; p < S; ++p)
-    *reinterpret_cast<typename Vec8<ST>::type *>(out + (int64_t(p) * Rp + r) * Kp + k0 + kc) = sl[p];
+    for (int p = 0; p < S; ++p)
+      *reinterpret_cast<typename Vec8<ST>::type *>(out + (int64_t(p) * Rp + r) * Kp + k0 + kc) = sl[p];
+  }
 }
 
 // ------------------------------------------------------- slice-pair GEMM --
@@ -728,12 +788,14 @@ template <typename Tin>
 hipError_t exp_operand(const void *base, const int64_t *offR, const int64_t *offK, int64_t R, int64_t K, int layout,
                        int *e, hipStream_t s) {
   const int64_t tilesR = (R + PR - 1) / PR, tilesK = (K + PK - 1) / PK;
-  const dim3 grid(unsigned(tilesR * tilesK));
+  // split the summation range so that about 2048 blocks run
+  const int64_t ky = std::max<int64_t>(1, std::min<int64_t>(tilesK, (2048 + tilesR - 1) / tilesR));
+  const dim3 grid = dim3(unsigned(tilesR), unsigned(ky));
   const Tin *b = static_cast<const Tin *>(base);
   if (layout == 0)
-    hipLaunchKernelGGL((split_exp_kernel<Tin, 0>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e);
+    hipLaunchKernelGGL((split_exp_kernel<Tin, 0>), grid, dim3(PT), 0, s, b, offR, offK, R, K, e);
   else
-    hipLaunchKernelGGL((split_exp_kernel<Tin, 1>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e);
+    hipLaunchKernelGGL((split_exp_kernel<Tin, 1>), grid, dim3(PT), 0, s, b, offR, offK, R, K, e);
   return hipGetLastError();
 }
 
@@ -833,7 +895,7 @@ Status split_prepare(const Analysis &an, SplitPlan &sp) {
   }
   sp.Mp = round_up(an.m, sp.tile == 1 ? XBM : GBM);
   sp.Np = round_up(an.n, sp.tile == 1 ? XBN : GBN);
-  sp.Kp = round_up(an.k, sp.mode == 3 ? IBK : GBK);
+  sp.Kp = round_up(an.k, PK);   // whole slicer tiles (a multiple of GBK and IBK)
   const int64_t tiles = sp.tile == 1 ? (sp.Mp / XBM) * (sp.Np / XBN) : (sp.Mp / GBM) * (sp.Np / GBN);
   if (tiles > INT_MAX || (sp.Mp / PR) * (sp.Kp / PK) > INT_MAX || (sp.Np / PR) * (sp.Kp / PK) > INT_MAX)
     return Status::error(COMET_ERR_UNSUPPORTED, "problem too large for the split path");
