@@ -171,11 +171,13 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BatchDesc *__restrict__
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int64_t item = s_item;
+    // the item index is the same in every lane: say so, so that the item and
+    // its descriptor are read with scalar loads into scalar registers
+    const int64_t item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (item >= total) break;   // every workgroup ends here once the list is drained
     const BatchItem w = items[item];
-    const BatchDesc d = descs[w.problem];
+    const BatchDesc d = descs[__builtin_amdgcn_readfirstlane(w.problem)];
     const int64_t m0 = int64_t(w.tile / d.tilesN) * TB, n0 = int64_t(w.tile % d.tilesN) * TB;
     switch (d.variant) {
       case 0: run_item<T, MODE, 0, 0, true>(d, m0, n0, smem); break;
