@@ -230,6 +230,20 @@ comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dty
                              void *stream);
 
 /*
+ * comet_fill -- the ta.fill operation of Section 5: every element of the
+ * tensor at `out` (device pointer, owned by the caller) is set to `value`
+ * (rounded to FP32 for FP32 storage).  The tensor has `rank` dimensions
+ * (0 <= rank <= COMET_MAX_RANK; rank 0 is one element) with the given
+ * extents and element strides (NULL: dense row-major); strides must not make
+ * two elements share an address.  Enqueued on `stream`, nothing is read.
+ * Errors: COMET_ERR_INVALID_SHAPE (rank or a negative extent),
+ * COMET_ERR_INVALID_STRIDE (negative or overlapping strides),
+ * COMET_ERR_NULL_POINTER (out NULL for a non-empty tensor), COMET_ERR_HIP.
+ */
+comet_status_t comet_fill(int rank, const int64_t *extents, comet_dtype_t dtype, double value, void *out,
+                          const int64_t *strides, void *stream);
+
+/*
  * Autotuner.  mode 0: off (heuristic tiles); 1: use the cache at cache_path
  * and time candidates for problem classes it does not hold, appending them;
  * 2: re-time everything.  A corrupt cache file is ignored and rewritten.

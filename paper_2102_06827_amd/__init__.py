@@ -40,7 +40,7 @@ SYMBOLS = [
     "comet_contract", "comet_plan_create", "comet_plan_create_ex", "comet_plan_workspace_size",
     "comet_plan_execute", "comet_plan_destroy", "comet_plan_describe", "comet_analyze",
     "comet_batch_create", "comet_batch_workspace_size", "comet_batch_execute", "comet_batch_destroy",
-    "comet_permute", "comet_autotune", "comet_set_split_slices", "comet_set_int8_slices", "comet_last_error",
+    "comet_permute", "comet_fill", "comet_autotune", "comet_set_split_slices", "comet_set_int8_slices", "comet_last_error",
     "comet_version",
 ]
 
@@ -100,6 +100,7 @@ def lib():
         L.comet_batch_execute.argtypes = [P, P, ctypes.c_size_t, P]
         L.comet_batch_destroy.argtypes = [P]
         L.comet_permute.argtypes = [S, I64P, I, D, P, I64P, D, P, I64P, P]
+        L.comet_fill.argtypes = [I, I64P, I, D, P, I64P, P]
         L.comet_autotune.argtypes = [S, I]
         L.comet_set_split_slices.argtypes = [I]
         L.comet_set_int8_slices.argtypes = [I]
@@ -212,6 +213,15 @@ def permute(spec, x, out=None, alpha=1.0, beta=0.0, stream=None):
                              _i64(out.stride()), _stream_handle(stream))
     _check(rc)
     return out
+
+
+def fill(x, value, stream=None):
+    """Set every element of the tensor x (any strides) to value; returns x."""
+    dt = _dtype_code(x, x)
+    rc = lib().comet_fill(x.dim(), _i64(list(x.shape)), dt, float(value), ctypes.c_void_p(x.data_ptr()),
+                          _i64(list(x.stride())), _stream_handle(stream))
+    _check(rc)
+    return x
 
 
 def analyze(spec, extents, strides_A=None, strides_B=None, strides_C=None, dtype="f64", compute="default",

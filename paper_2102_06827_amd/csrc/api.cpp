@@ -966,6 +966,52 @@ comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dty
   return COMET_OK;
 }
 
+comet_status_t comet_fill(int rank, const int64_t *extents, comet_dtype_t dtype, double value, void *out,
+                          const int64_t *strides, void *stream) {
+  if (rank < 0 || rank > COMET_MAX_RANK) return fail(COMET_ERR_INVALID_SHAPE, "rank must be within 0..12");
+  if (dtype != COMET_F64 && dtype != COMET_F32) return fail(COMET_ERR_UNSUPPORTED, "unknown dtype");
+  if (rank > 0 && !extents) return fail(COMET_ERR_NULL_POINTER, "extents is NULL");
+  std::vector<int64_t> e(extents, extents + rank);
+  int64_t total = 1;
+  for (int64_t x : e) {
+    if (x < 0) return fail(COMET_ERR_INVALID_SHAPE, "negative extent");
+    if (__builtin_mul_overflow(total, x, &total)) return fail(COMET_ERR_INVALID_SHAPE, "size overflows int64");
+  }
+  std::vector<int64_t> st = strides ? std::vector<int64_t>(strides, strides + rank) : dense_strides(e);
+  for (int64_t x : st)
+    if (x < 0) return fail(COMET_ERR_INVALID_STRIDE, "negative stride");
+  if (total == 0) return COMET_OK;   // an empty tensor: strides do not matter
+  {
+    std::vector<std::pair<int64_t, int64_t>> sd;
+    for (int p = 0; p < rank; ++p) {
+      if (e[p] <= 1) continue;
+      if (st[p] == 0) return fail(COMET_ERR_INVALID_STRIDE, "stride 0 on a dimension of extent > 1");
+      sd.push_back({st[p], e[p]});
+    }
+    std::sort(sd.begin(), sd.end());
+    for (size_t i = 0; i + 1 < sd.size(); ++i)
+      if (sd[i + 1].first < sd[i].first * sd[i].second)
+        return fail(COMET_ERR_INVALID_STRIDE, "dimensions overlap in memory");
+  }
+  if (!out) return fail(COMET_ERR_NULL_POINTER, "out is NULL");
+  // the stream form of the permute kernel with nothing read: out = fill
+  PermuteLaunch pl{};
+  pl.ndim = rank;
+  for (int i = 0; i < rank; ++i) {
+    pl.ext[i] = e[i];
+    pl.s_in[i] = st[i];
+    pl.s_out[i] = st[i];
+  }
+  pl.in = out;
+  pl.out = out;
+  pl.alpha = 0.0;
+  pl.beta = 0.0;
+  pl.dtype = dtype == COMET_F64 ? 0 : 1;
+  pl.fill = dtype == COMET_F32 ? double(float(value)) : value;
+  HIP_TRY(launch_permute(pl, static_cast<hipStream_t>(stream)), "fill launch");
+  return COMET_OK;
+}
+
 comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_problem_t *problems, comet_dtype_t dtype,
                                   comet_compute_t compute) {
   if (!batch) return fail(COMET_ERR_NULL_POINTER, "batch is NULL");

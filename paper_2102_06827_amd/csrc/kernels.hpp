@@ -96,6 +96,7 @@ struct PermuteLaunch {
   int64_t s_out[kPermMaxDims];
   double alpha, beta;
   int dtype;
+  double fill = 0.0;   // with alpha == 0: out = fill + beta * out
 };
 hipError_t launch_permute(const PermuteLaunch &p, hipStream_t s);
 

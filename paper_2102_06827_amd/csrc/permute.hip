@@ -72,6 +72,7 @@ struct StreamArgs {
   int64_t su_in, su_out;  // strides of u
   int64_t vpr;            // vectors per row (E / W)
   int64_t total;          // rows * vpr
+  double fill;            // value of the alpha term when alpha == 0 (nothing is read then)
 };
 
 template <typename T, int W, typename I>
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(SB) void permute_stream(const T *__restrict__ in, T
         const vec_t old = beta != 0.0 ? *dst : vec_t{};
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          Te v = alpha != 0.0 ? Te(alpha) * Te(x[u][k]) : Te(0);
+          Te v = alpha != 0.0 ? Te(alpha) * Te(x[u][k]) : Te(a.fill);
           if (beta != 0.0) v = v + Te(beta) * Te(old[k]);
           y[k] = T(v);
         }
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(SB) void permute_stream(const T *__restrict__ in, T
 #pragma unroll
       for (int u = 0; u < SU; ++u) {
         if (!ok[u]) continue;
-        Te v = alpha != 0.0 ? Te(alpha) * Te(x[u]) : Te(0);
+        Te v = alpha != 0.0 ? Te(alpha) * Te(x[u]) : Te(a.fill);
         if (beta != 0.0) v = v + Te(beta) * Te(out[ao[u]]);
         out[ao[u]] = T(v);
       }
@@ -241,6 +242,7 @@ hipError_t launch_perm_t(const PermuteLaunch &p, hipStream_t s) {
     // rows fastest first in output order
     std::sort(rows.begin(), rows.end(), [&](int x, int y) { return d[x].so < d[y].so; });
     fill(a.rows, d, rows);
+    a.fill = p.fill;
     a.E = n ? d[uo].ext : 1;
     a.su_in = n ? d[uo].si : 0;
     a.su_out = n ? d[uo].so : 0;

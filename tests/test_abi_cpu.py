@@ -89,6 +89,20 @@ def test_contract_validates_before_device():
     assert rc == NULLP
 
 
+def test_fill_validates_before_device():
+    """comet_fill reports argument errors before any device call (out is NULL here)."""
+    L = comet.lib()
+    i64 = lambda xs: (ctypes.c_int64 * max(1, len(xs)))(*xs)
+    assert L.comet_fill(13, i64([1] * 13), 0, 1.0, None, None, None) == SHAPE
+    assert L.comet_fill(2, i64([3, -1]), 0, 1.0, None, None, None) == SHAPE
+    assert L.comet_fill(2, i64([3, 4]), 0, 1.0, None, i64([4, -1]), None) == STRIDE
+    assert L.comet_fill(2, i64([3, 4]), 0, 1.0, None, i64([0, 1]), None) == STRIDE     # stride 0, extent 3
+    assert L.comet_fill(2, i64([3, 4]), 0, 1.0, None, i64([2, 1]), None) == STRIDE     # rows overlap
+    assert L.comet_fill(2, i64([3, 4]), 0, 1.0, None, None, None) == NULLP
+    assert L.comet_fill(2, i64([3, 0]), 0, 1.0, None, None, None) == OK                # empty: nothing to do
+    assert L.comet_fill(2, i64([3, 4]), 2, 1.0, None, None, None) == UNSUP             # unknown dtype
+
+
 def test_set_split_slices_range():
     L = comet.lib()
     assert L.comet_set_split_slices(2) == UNSUP

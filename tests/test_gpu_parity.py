@@ -302,6 +302,33 @@ def test_permute_views_broadcast_and_scaling(dtype):
     assert torch.equal(o, ref)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fill(dtype):
+    """comet_fill: dense, a strided view (nothing outside it changes), rank 0,
+    the FP32 rounding of the value."""
+    t = tdt(dtype)
+    x = torch.zeros((7, 9, 5), dtype=t, device="cuda")
+    print_case("fill", dtype)
+    comet.fill(x, -2.5)
+    torch.cuda.synchronize()
+    assert torch.equal(x, torch.full_like(x, -2.5))
+    big = torch.zeros((12, 30), dtype=t, device="cuda")
+    v = big[2:9, 1::3]
+    comet.fill(v, 1.0 / 3.0)
+    torch.cuda.synchronize()
+    exp = torch.zeros_like(big)
+    exp[2:9, 1::3] = torch.tensor(1.0 / 3.0, dtype=t)
+    assert torch.equal(big, exp)
+    s = torch.zeros((), dtype=t, device="cuda")
+    comet.fill(s, 7.0)
+    torch.cuda.synchronize()
+    assert s.item() == 7.0
+    odd = torch.zeros((3, 5, 7), dtype=t, device="cuda").permute(2, 0, 1)
+    comet.fill(odd, 4.0)
+    torch.cuda.synchronize()
+    assert torch.equal(odd, torch.full_like(odd, 4.0))
+
+
 @pytest.mark.parametrize("spec", ["ji=ij", "jik=ijk"])
 def test_permute_64bit_indexing(spec):
     """More than 2^30 elements: the 64-bit index path of both kernels."""
