@@ -151,6 +151,7 @@ comet_status_t upload_tables(comet_plan_s *p) {
 // reads back.  The autotuner replaces this model with timings.
 constexpr double kThroughputF64[] = {28.4, 33.2, 28.6, 41.0, 38.6, 33.6, 32.7, 33.5, 34.4, 34.3};
 constexpr double kThroughputF32[] = {74.5, 64.9, 73.4, 75.8, 79.3, 69.8, 70.1};
+constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
 constexpr double kSkBytesPerUs = 4.0e6;  // partial-sum traffic rate (HBM, both directions)
 constexpr double kSkLaunchUs = 4.0;      // the two extra launches
@@ -315,7 +316,8 @@ void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
                           const int64_t *sA, const int64_t *sB, const int64_t *sC, comet_dtype_t dtype,
-                          comet_compute_t compute, comet_path_t path, bool tune = true);
+                          comet_compute_t compute, comet_path_t path, bool tune = true,
+                          const TTGTChoice *forced_ttgt = nullptr);
 comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
                              const int64_t *sA, const int64_t *sB, const int64_t *sC);
 comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
@@ -418,11 +420,12 @@ comet_status_t build_ttgt(comet_plan_s *p) {
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
                           const int64_t *sA, const int64_t *sB, const int64_t *sC, comet_dtype_t dtype,
-                          comet_compute_t compute, comet_path_t path, bool tune) {
+                          comet_compute_t compute, comet_path_t path, bool tune, const TTGTChoice *forced_ttgt) {
   std::unique_ptr<comet_plan_s> p(new comet_plan_s());
   Status st = analyze(spec, extents, sA, sB, sC, dtype, compute, path, g_split_slices, p->an, g_int8_slices);
   if (!st.ok()) return fail(st);
   Analysis &an = p->an;
+  if (forced_ttgt && an.path == COMET_PATH_TTGT) an.ttgt = *forced_ttgt;
   HIP_TRY(hipGetDevice(&p->device), "hipGetDevice");
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) cus = 256;
@@ -637,7 +640,7 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
     std::unique_ptr<comet_plan_s> tt;
     comet_status_t rc = build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false);
     if (rc != COMET_OK) tt.reset();
-    const size_t wsb = tt ? tt->ws_bytes : 0;
+    size_t wsb = tt ? tt->ws_bytes : 0;
     bool ok = hipStreamCreate(&s) == hipSuccess && hipMalloc(&bufA, std::max<int64_t>(an.sizeA, 1) * es) == hipSuccess &&
               hipMalloc(&bufB, std::max<int64_t>(an.sizeB, 1) * es) == hipSuccess &&
               hipMalloc(&bufC, std::max<int64_t>(an.sizeC, 1) * es) == hipSuccess &&
@@ -670,10 +673,34 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
         if (good && us < best.us) best = TuneEntry{tile, COMET_PATH_GETT, us};
       }
       if (tt) {
-        bool good;
-        const comet_plan_s *pt = tt.get();
-        double us = time_us([&]() { return execute(pt, 1.0, bufA, bufB, 0.0, bufC, ws, wsb, s); }, s, &good);
-        if (good && us < best.us) best = TuneEntry{tt->gemm ? tt->gemm->an.tile : 0, COMET_PATH_TTGT, us};
+        // every TTGT flattening, cheapest by the cost model first, up to
+        // kTuneTTGT of them (the model ranks them poorly on MI355X, so it only
+        // orders the search)
+        std::vector<TTGTChoice> cands = ttgt_candidates(tt->an);
+        if (cands.size() > size_t(kTuneTTGT)) cands.resize(kTuneTTGT);
+        for (const TTGTChoice &ch : cands) {
+          std::unique_ptr<comet_plan_s> cp;
+          if (build_plan(cp, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false, &ch) !=
+              COMET_OK)
+            continue;
+          if (cp->ws_bytes > wsb) {
+            if (ws) (void)hipFree(ws);
+            ws = nullptr;
+            wsb = 0;
+            if (hipMalloc(&ws, cp->ws_bytes) != hipSuccess) {
+              ws = nullptr;
+              continue;
+            }
+            wsb = cp->ws_bytes;
+          }
+          bool good;
+          const comet_plan_s *pt = cp.get();
+          double us = time_us([&]() { return execute(pt, 1.0, bufA, bufB, 0.0, bufC, ws, wsb, s); }, s, &good);
+          if (good && us < best.us) {
+            best = TuneEntry{cp->gemm ? cp->gemm->an.tile : 0, COMET_PATH_TTGT, us,
+                             ch.a_order + "|" + ch.b_order + "|" + ch.c_order};
+          }
+        }
       }
       (void)hipStreamSynchronize(s);
       if (skws) (void)hipFree(skws);
@@ -688,8 +715,14 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
     tc.store(key, best);
   }
   if (best.path == COMET_PATH_TTGT) {
+    // the recorded flattening, if it is still one of this problem's
+    const TTGTChoice *forced = nullptr;
+    std::vector<TTGTChoice> cands = ttgt_candidates(an);
+    for (const TTGTChoice &ch : cands)
+      if (ch.a_order + "|" + ch.b_order + "|" + ch.c_order == best.ttgt) forced = &ch;
     std::unique_ptr<comet_plan_s> tt;
-    comet_status_t rc = build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false);
+    comet_status_t rc =
+        build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false, forced);
     if (rc == COMET_OK) {
       p = std::move(tt);
       return COMET_OK;

@@ -286,6 +286,60 @@ TTGTChoice choose_ttgt(const Analysis &an) {
   return best;
 }
 
+std::vector<TTGTChoice> ttgt_candidates(const Analysis &an) {
+  const std::string &c = an.spec_c, &a = an.spec_a, &b = an.spec_b;
+  std::string Mset, Nset, Kset;
+  for (char ch : a) (c.find(ch) != std::string::npos ? Mset : Kset) += ch;
+  for (char ch : b)
+    if (c.find(ch) != std::string::npos) Nset += ch;
+  auto perms = [](std::string x) {
+    std::vector<std::string> v;
+    std::sort(x.begin(), x.end());
+    do v.push_back(x);
+    while (std::next_permutation(x.begin(), x.end()));
+    return v;
+  };
+  auto ext_of = [&](char ch) {
+    return an.extents[std::find(an.labels.begin(), an.labels.end(), ch) - an.labels.begin()];
+  };
+  auto exts = [&](const std::string &s) {
+    std::vector<int64_t> e;
+    for (char ch : s) e.push_back(ext_of(ch));
+    return e;
+  };
+  const bool denseA = dense_rowmajor(exts(a), an.strA), denseB = dense_rowmajor(exts(b), an.strB),
+             denseC = dense_rowmajor(exts(c), an.strC);
+  std::vector<TTGTChoice> out;
+  std::vector<std::string> seen;
+  for (const auto &mo : perms(Mset))
+    for (const auto &no : perms(Nset))
+      for (const auto &ko : perms(Kset))
+        for (int swap = 0; swap < 2; ++swap)
+          for (int la = 0; la < 2; ++la)
+            for (int lb = 0; lb < 2; ++lb) {
+              const std::string rows = swap ? no : mo, cols = swap ? mo : no;
+              const std::string left = la ? ko + rows : rows + ko;
+              const std::string right = lb ? cols + ko : ko + cols;
+              TTGTChoice ch;
+              ch.swap = swap;
+              ch.a_order = swap ? right : left;
+              ch.b_order = swap ? left : right;
+              ch.c_order = rows + cols;
+              const std::string key = ch.a_order + "|" + ch.b_order + "|" + ch.c_order;
+              if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+              seen.push_back(key);
+              ch.a_copy = !(ch.a_order == a && denseA);
+              ch.b_copy = !(ch.b_order == b && denseB);
+              ch.c_copy = !(ch.c_order == c && denseC);
+              ch.cost = (ch.a_copy ? ttgt_cost(a, ch.a_order == a ? std::string(a.size(), '#') : ch.a_order, 1) : 0) +
+                        (ch.b_copy ? ttgt_cost(b, ch.b_order == b ? std::string(b.size(), '#') : ch.b_order, 1) : 0) +
+                        (ch.c_copy ? ttgt_cost(c, ch.c_order == c ? std::string(c.size(), '#') : ch.c_order, 2) : 0);
+              out.push_back(ch);
+            }
+  std::stable_sort(out.begin(), out.end(), [](const TTGTChoice &x, const TTGTChoice &y) { return x.cost < y.cost; });
+  return out;
+}
+
 PermuteDesc make_permute(const std::string &out_labels, const std::vector<int64_t> &out_strides,
                          const std::string &in_labels, const std::vector<int64_t> &in_strides,
                          const std::vector<int64_t> &ext_by_out) {

@@ -106,6 +106,10 @@ Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_
 // flattening of A, B and C, with and without exchanging A and B, costed by
 // the positions of the dimensions it moves; the cheapest wins.
 TTGTChoice choose_ttgt(const Analysis &an);
+// Every valid TTGT flattening (each order of the M, N and K label groups, each
+// operand stored K-major or not, with and without exchanging A and B), with
+// its cost-model value, cheapest first.  The autotuner times them.
+std::vector<TTGTChoice> ttgt_candidates(const Analysis &an);
 int64_t ttgt_cost(const std::string &orig, const std::string &perm, int64_t weight);
 
 // Describe the permutation `in_labels` (with strides) -> `out_labels` (with

@@ -2,7 +2,7 @@
 //
 // File format (one object; unknown or malformed content makes the whole file
 // ignored and rewritten):
-//   {"format": "comet-tune-1", "entries": {"<key>": {"tile": 3, "path": 1, "us": 1234.5}, ...}}
+//   {"format": "comet-tune-2", "entries": {"<key>": {"tile": 3, "path": 1, "us": 1234.5, "ttgt": ""}, ...}}
 #include "tune.hpp"
 
 #include <cmath>
@@ -16,8 +16,8 @@
 namespace comet {
 
 namespace {
-const char *kFormat = "comet-tune-1";
-const char *kKernelVersion = "k5";   // bump when kernels change in a way that invalidates timings
+const char *kFormat = "comet-tune-2";
+const char *kKernelVersion = "k6";   // bump when kernels change in a way that invalidates timings
 
 int bucket(int64_t x) {
   int b = 0;
@@ -60,6 +60,14 @@ bool parse(const std::string &text, std::map<std::string, TuneEntry> &out) {
     e.tile = tile;
     e.path = path;
     e.us = us;
+    const size_t tq = body.find("\"ttgt\": \"");
+    if (tq != std::string::npos) {
+      const size_t t0 = tq + 9, t1 = body.find('"', t0);
+      if (t1 == std::string::npos) return false;
+      e.ttgt = body.substr(t0, t1 - t0);
+      for (char ch : e.ttgt)
+        if (!((ch >= 'a' && ch <= 'z') || (ch >= 'A' && ch <= 'Z') || ch == '|')) return false;
+    }
     out[key] = e;
     p = c + 1;
   }
@@ -94,10 +102,10 @@ void TuneCache::save() const {
     if (!f) return;
     f << "{\"format\": \"" << kFormat << "\", \"entries\": {";
     bool first = true;
-    char buf[128];
+    char buf[256];
     for (const auto &kv : entries_) {
-      std::snprintf(buf, sizeof buf, "{\"tile\": %d, \"path\": %d, \"us\": %.3f}", kv.second.tile, kv.second.path,
-                    kv.second.us);
+      std::snprintf(buf, sizeof buf, "{\"tile\": %d, \"path\": %d, \"us\": %.3f, \"ttgt\": \"%s\"}", kv.second.tile,
+                    kv.second.path, kv.second.us, kv.second.ttgt.c_str());
       f << (first ? "\n" : ",\n") << "  \"" << kv.first << "\": " << buf;
       first = false;
     }

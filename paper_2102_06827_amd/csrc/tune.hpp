@@ -15,6 +15,7 @@ struct TuneEntry {
   int tile = 0;
   int path = COMET_PATH_GETT;
   double us = 0.0;
+  std::string ttgt;   // for path TTGT: "A order|B order|C order" of the fastest flattening
 };
 
 class TuneCache {

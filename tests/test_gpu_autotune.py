@@ -35,13 +35,17 @@ def test_autotune_records_and_reuses(cache, dtype):
     torch.cuda.synchronize()
     assert np.array_equal(to_np(C), oracle.contract(spec, A, B))
     data = json.loads(cache.read_text())
-    assert data["format"] == "comet-tune-1" and len(data["entries"]) == 1
+    assert data["format"] == "comet-tune-2" and len(data["entries"]) == 1
     (key, entry), = data["entries"].items()
     assert entry["path"] in (1, 2) and entry["us"] > 0
     chosen = plan.describe()
     assert chosen["path"] == ("ttgt" if entry["path"] == 2 else "gett")
     if entry["path"] == 1:
-        assert chosen["tile"] == entry["tile"]
+        assert chosen["tile"] == entry["tile"] and entry["ttgt"] == ""
+    else:
+        # the fastest of the timed flattenings, recorded and used
+        t = chosen["ttgt"]
+        assert entry["ttgt"] == "%s|%s|%s" % (t["A"], t["B"], t["C"])
     # a second plan of the same class reads the cache (no new entry, same choice)
     mtime = cache.stat().st_mtime_ns
     plan2 = comet.Plan(spec, Ad, Bd)
@@ -53,7 +57,7 @@ def test_autotune_records_and_reuses(cache, dtype):
 
 
 def test_autotune_rewrites_corrupt_cache(cache):
-    cache.write_text('{"format": "comet-tune-1", "entries": {"x": {"tile": ')
+    cache.write_text('{"format": "comet-tune-2", "entries": {"x": {"tile": ')
     comet.autotune(str(cache), 1)
     A = torch_dev(synth.uniform(3, (200, 150)), torch.float64)
     B = torch_dev(synth.uniform(4, (150, 170)), torch.float64)
@@ -63,3 +67,24 @@ def test_autotune_rewrites_corrupt_cache(cache):
     assert oracle.relerr(to_np(C), oracle.contract("ij=ik*kj", to_np(A), to_np(B))) <= 1e-12
     data = json.loads(cache.read_text())
     assert len(data["entries"]) == 1 and "x" not in data["entries"]
+
+
+def test_autotune_searches_ttgt_flattenings(cache, monkeypatch):
+    """With the gather path ruled out by forcing TTGT plans to compete only with
+    each other (a problem whose TTGT flattenings differ), the recorded
+    flattening is one of the candidates and the tuned plan is exact."""
+    spec = "abcd=aebf*dfce"
+    ext = dict(a=13, b=11, c=12, d=9, e=10, f=7)
+    A = synth.integers(5, shape_of("aebf", ext))
+    B = synth.integers(6, shape_of("dfce", ext))
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    print_case("autotune ttgt search")
+    comet.autotune(str(cache), 2)
+    plan = comet.Plan(spec, Ad, Bd)
+    C = plan(Ad, Bd)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), oracle.contract(spec, A, B))
+    (key, entry), = json.loads(cache.read_text())["entries"].items()
+    if entry["path"] == 2:
+        a, b, c = entry["ttgt"].split("|")
+        assert sorted(a) == sorted("aebf") and sorted(b) == sorted("dfce") and sorted(c) == sorted("abcd")
