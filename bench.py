@@ -18,6 +18,8 @@ The same line also carries, each timed with HIP events on the launch stream:
   permute    the transpose kernel of the TTGT lowering on three shapes;
   ttgt_study every TTGT flattening of configs 2 and 3 timed, the planner's
              cost-model pick ranked among them, against GETT;
+  chain      multi-operand chains of the paper's Table 1 shapes: the grouping
+             with the fewest operations against the natural order;
   batch      1024 independent 4D contractions of six patterns with per-label
              extents from {8,...,64}, forward + backward in one persistent
              launch replayed from a HIP graph (FP32 and BF16x3);
@@ -328,6 +330,49 @@ def bench_config1(comet, reps=50):
             "oracle_ms_1thread": None, "oracle_ms_all_cores": None, "A": A, "B": B}
 
 
+def bench_chain(comet, reps=5):
+    """Multi-operand chains (Section 6; the shapes of the paper's Table 1) at
+    NWChem-like extents (occupied 32, virtual 96): the planner's grouping
+    against the natural left-to-right order, both on the GPU, FP64."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    O_, V_ = 32, 96
+    out = {}
+    g = torch.Generator(device=dev)
+    g.manual_seed(17)
+    for rhs in ("cdmn*inad*mc", "cdmn*id*na*mc", "mnef*am*fn*ebij"):
+        ops = rhs.split("*")
+        once = [l for l in dict.fromkeys("".join(ops)) if sum(l in o for o in ops) == 1]
+        spec = "".join(once) + "=" + rhs
+        ext = {l: (O_ if l in "ijmn" else V_) for l in set(rhs) - {"*"}}
+        ts = [torch.rand(tuple(ext[l] for l in o), dtype=torch.float64, device=dev, generator=g) for o in ops]
+        plan = comet.chain_plan(spec, ext)
+        res = comet.contract_chain(spec, ts)
+        t_best = timed(lambda: comet.contract_chain(spec, ts, res), reps, stream)
+
+        def natural():
+            acc, lab = ts[0], ops[0]
+            for i in range(1, len(ops)):
+                rest = set(once).union(*[set(o) for o in ops[i + 1:]])
+                keep = "".join(once) if i == len(ops) - 1 else \
+                    "".join(l for l in dict.fromkeys(lab + ops[i]) if l in rest)
+                acc = comet.contract("%s=%s*%s" % (keep, lab, ops[i]), acc, ts[i])
+                lab = keep
+            return acc
+        nat = natural()
+        torch.cuda.synchronize()
+        err = float(((nat - res).norm() / res.norm()).item())
+        t_nat = timed(natural, 1, stream)
+        out[spec] = {"flops": plan["flops"], "natural_flops": plan["natural_flops"],
+                     "order": [st["spec"] for st in plan["steps"]], "ms": round(t_best, 4),
+                     "natural_ms": round(t_nat, 4), "speedup": round(t_nat / t_best, 1),
+                     "relerr_vs_natural": err}
+        del ts, res, nat
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_permute(comet, reps):
     """The permute kernel (TTGT's transposes and ta.copy): HBM bytes moved per second.
 
@@ -594,6 +639,7 @@ def main():
         line["config1"] = bench_config1(comet)
         line["permute"] = bench_permute(comet, reps=5)
         line["ttgt_study"] = bench_ttgt_study(comet)
+        line["chain"] = bench_chain(comet)
         line["batch"] = bench_batch(comet, reps=3)
     if not args.no_cpu:
         # the CPU leg: oracle references for every recorded check, and the

@@ -230,6 +230,32 @@ comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dty
                              void *stream);
 
 /*
+ * Multi-operand contraction chains (Section 5: ta.mult, ta.set; Section 6,
+ * "Multi-Operand Expression").  spec "C=A1*A2*...*An", 2 <= n <= 8, every
+ * label in exactly two of the tensors; extents one per distinct label, in
+ * order of first appearance scanning C then A1..An.
+ *
+ * comet_chain_plan (host only, no device needed) chooses the grouping with
+ * the fewest algorithmic operations (a search over every binary tree) and
+ * writes it as JSON into buf: {"flops", "natural_flops" (left to right),
+ * "steps": [{"left", "right", "spec", "flops"}]} where operands 0..n-1 are
+ * the inputs and n.. the intermediates in step order.  COMET_ERR_WORKSPACE if
+ * buf is too small.
+ *
+ * comet_contract_chain computes C = alpha * (A1 * ... * An) + beta * C in
+ * that order, one binary contraction per step through the comet_contract
+ * path; intermediates are dense, held in a library-owned device buffer that
+ * grows as needed (so, like comet_contract, it refuses to run under stream
+ * capture).  operands[i] are device pointers, strides[i] their element
+ * strides (strides or any strides[i] NULL: dense row-major).
+ */
+comet_status_t comet_chain_plan(const char *spec, const int64_t *extents, char *buf, size_t len);
+comet_status_t comet_contract_chain(const char *spec, const int64_t *extents, comet_dtype_t dtype,
+                                    comet_compute_t compute, double alpha, int n, const void *const *operands,
+                                    const int64_t *const *strides, double beta, void *C,
+                                    const int64_t *strides_C, void *stream);
+
+/*
  * comet_fill -- the ta.fill operation of Section 5: every element of the
  * tensor at `out` (device pointer, owned by the caller) is set to `value`
  * (rounded to FP32 for FP32 storage).  The tensor has `rank` dimensions

@@ -40,7 +40,7 @@ SYMBOLS = [
     "comet_contract", "comet_plan_create", "comet_plan_create_ex", "comet_plan_workspace_size",
     "comet_plan_execute", "comet_plan_destroy", "comet_plan_describe", "comet_analyze",
     "comet_batch_create", "comet_batch_workspace_size", "comet_batch_execute", "comet_batch_destroy",
-    "comet_permute", "comet_fill", "comet_autotune", "comet_set_split_slices", "comet_set_int8_slices", "comet_last_error",
+    "comet_permute", "comet_fill", "comet_chain_plan", "comet_contract_chain", "comet_autotune", "comet_set_split_slices", "comet_set_int8_slices", "comet_last_error",
     "comet_version",
 ]
 
@@ -101,6 +101,9 @@ def lib():
         L.comet_batch_destroy.argtypes = [P]
         L.comet_permute.argtypes = [S, I64P, I, D, P, I64P, D, P, I64P, P]
         L.comet_fill.argtypes = [I, I64P, I, D, P, I64P, P]
+        L.comet_chain_plan.argtypes = [S, I64P, ctypes.c_char_p, ctypes.c_size_t]
+        L.comet_contract_chain.argtypes = [S, I64P, I, I, D, I, ctypes.POINTER(P), ctypes.POINTER(I64P), D, P,
+                                           I64P, P]
         L.comet_autotune.argtypes = [S, I]
         L.comet_set_split_slices.argtypes = [I]
         L.comet_set_int8_slices.argtypes = [I]
@@ -213,6 +216,60 @@ def permute(spec, x, out=None, alpha=1.0, beta=0.0, stream=None):
                              _i64(out.stride()), _stream_handle(stream))
     _check(rc)
     return out
+
+
+def _chain_parts(spec):
+    s = "".join(spec.split())
+    out, rhs = s.split("=")
+    return out, rhs.split("*")
+
+
+def chain_labels(spec):
+    """Distinct labels of a chain spec in order of first appearance (C, then A1..An)."""
+    out, ops = _chain_parts(spec)
+    seen = []
+    for t in [out] + ops:
+        for ch in t:
+            if ch not in seen:
+                seen.append(ch)
+    return seen
+
+
+def chain_plan(spec, extents):
+    """Host-only: the grouping of a multi-operand chain with the fewest
+    operations.  extents: dict label -> extent, or a list in chain_labels order."""
+    if isinstance(extents, dict):
+        extents = [extents[ch] for ch in chain_labels(spec)]
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().comet_chain_plan(spec.encode(), _i64(extents), buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def contract_chain(spec, tensors, C=None, alpha=1.0, beta=0.0, compute="default", stream=None):
+    """C = alpha * (A1 * ... * An) + beta * C for spec "C=A1*...*An", in the
+    order with the fewest operations (intermediates held by the library)."""
+    out, ops = _chain_parts(spec)
+    if len(ops) != len(tensors):
+        raise ValueError("spec has %d operands, %d tensors given" % (len(ops), len(tensors)))
+    ext = {}
+    for labels, t in zip(ops, tensors):
+        if len(labels) != t.dim():
+            raise ValueError("rank mismatch for operand " + labels)
+        for ch, e in zip(labels, t.shape):
+            if ext.setdefault(ch, int(e)) != int(e):
+                raise ValueError("extent mismatch for label " + ch)
+    if C is None:
+        C = torch.empty(tuple(ext[ch] for ch in out), dtype=tensors[0].dtype, device=tensors[0].device)
+    dt = _dtype_code(*(list(tensors) + [C]))
+    n = len(tensors)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in tensors])
+    strs = [_i64(t.stride()) for t in tensors]
+    sarr = (ctypes.POINTER(ctypes.c_int64) * n)(*[ctypes.cast(x, ctypes.POINTER(ctypes.c_int64)) for x in strs])
+    rc = lib().comet_contract_chain(spec.encode(), _i64([ext[ch] for ch in chain_labels(spec)]), dt,
+                                    COMPUTE[compute], float(alpha), n, ptrs, sarr, float(beta),
+                                    ctypes.c_void_p(C.data_ptr()), _i64(C.stride()), _stream_handle(stream))
+    _check(rc)
+    return C
 
 
 def fill(x, value, stream=None):

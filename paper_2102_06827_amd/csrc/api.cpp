@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "chain.hpp"
 #include "comet.h"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -996,6 +997,96 @@ comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dty
     pl.alpha = 0.0;
   }
   HIP_TRY(launch_permute(pl, static_cast<hipStream_t>(stream)), "permute launch");
+  return COMET_OK;
+}
+
+comet_status_t comet_chain_plan(const char *spec, const int64_t *extents, char *buf, size_t len) {
+  if (!buf || !len) return fail(COMET_ERR_NULL_POINTER, "buf is NULL");
+  ChainPlan cp;
+  Status st = chain_plan(spec, extents, cp);
+  if (!st.ok()) return fail(st);
+  const std::string js = chain_json(cp);
+  std::strncpy(buf, js.c_str(), len - 1);
+  buf[len - 1] = 0;
+  if (js.size() + 1 > len) return fail(COMET_ERR_WORKSPACE, "chain plan buffer too small");
+  return COMET_OK;
+}
+
+namespace {
+// per-device buffer for the intermediates of comet_contract_chain
+std::map<int, DeviceWorkspace> g_chain_ws;
+}  // namespace
+
+comet_status_t comet_contract_chain(const char *spec, const int64_t *extents, comet_dtype_t dtype,
+                                    comet_compute_t compute, double alpha, int n, const void *const *operands,
+                                    const int64_t *const *strides, double beta, void *C,
+                                    const int64_t *strides_C, void *stream) {
+  ChainPlan cp;
+  Status st = chain_plan(spec, extents, cp);
+  if (!st.ok()) return fail(st);
+  if (n != int(cp.operands.size())) return fail(COMET_ERR_INVALID_SPEC, "operand count does not match the spec");
+  if (!operands) return fail(COMET_ERR_NULL_POINTER, "operands is NULL");
+  if (dtype != COMET_F64 && dtype != COMET_F32) return fail(COMET_ERR_UNSUPPORTED, "unknown dtype");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(COMET_ERR_UNSUPPORTED, "comet_contract_chain allocates; it cannot run under capture");
+  auto ext_of = [&](char ch) {
+    return cp.extents[std::find(cp.labels.begin(), cp.labels.end(), ch) - cp.labels.begin()];
+  };
+  // intermediates: dense, one allocation
+  const size_t es = elem_size(dtype);
+  std::vector<size_t> off(cp.steps.size(), 0);
+  size_t total = 0;
+  for (size_t i = 0; i + 1 < cp.steps.size(); ++i) {
+    size_t cnt = 1;
+    for (char ch : cp.steps[i].out_labels) cnt *= size_t(ext_of(ch));
+    off[i] = total;
+    total += align256(std::max<size_t>(cnt, 1) * es);
+  }
+  char *inter = nullptr;
+  if (total > 0) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceWorkspace &w = g_chain_ws[dev];
+    if (total > w.bytes) {
+      if (w.ptr) {
+        HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        HIP_TRY(hipFree(w.ptr), "hipFree(chain intermediates)");
+        w.ptr = nullptr;
+        w.bytes = 0;
+      }
+      HIP_TRY(hipMalloc(&w.ptr, total), "hipMalloc(chain intermediates)");
+      w.bytes = total;
+    }
+    inter = static_cast<char *>(w.ptr);
+  }
+  const int ns = int(cp.steps.size());
+  std::vector<const void *> ptr(size_t(n) + size_t(ns), nullptr);
+  std::vector<const int64_t *> str(size_t(n) + size_t(ns), nullptr);
+  for (int i = 0; i < n; ++i) {
+    ptr[i] = operands[i];
+    str[i] = strides ? strides[i] : nullptr;
+  }
+  for (int i = 0; i < ns; ++i) {
+    const ChainStep &stp = cp.steps[i];
+    const bool last = i == ns - 1;
+    std::string seen;
+    std::vector<int64_t> ext;
+    for (char ch : stp.spec)
+      if (ch != '=' && ch != '*' && seen.find(ch) == std::string::npos) {
+        seen += ch;
+        ext.push_back(ext_of(ch));
+      }
+    void *out = last ? C : static_cast<void *>(inter + off[i]);
+    comet_status_t rc = comet_contract(stp.spec.c_str(), ext.data(), dtype, compute, last ? alpha : 1.0,
+                                       ptr[stp.left], str[stp.left], ptr[stp.right], str[stp.right],
+                                       last ? beta : 0.0, out, last ? strides_C : nullptr, stream);
+    if (rc != COMET_OK) return rc;
+    ptr[n + i] = out;
+    str[n + i] = nullptr;
+  }
   return COMET_OK;
 }
 

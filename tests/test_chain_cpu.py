@@ -1,0 +1,125 @@
+"""Multi-operand chains on the host (Section 6, "Multi-Operand Expression"):
+the planner's grouping against an independent brute force over every order of
+pairwise contractions, the natural (left to right) count, the validity of the
+emitted binary steps, and the spec checks.  No device needed."""
+import itertools
+import math
+
+import pytest
+
+comet = pytest.importorskip("paper_2102_06827_amd")
+
+OK, SPEC, SHAPE, STRIDE, NULLP, UNSUP = 0, 1, 2, 3, 4, 5
+
+
+def parse(spec):
+    out, rhs = spec.replace(" ", "").split("=")
+    return out, rhs.split("*")
+
+
+def brute_force(spec, ext):
+    """Min over every sequence of pairwise contractions (which covers every
+    binary tree) of the summed cost 2 * prod(extents of the labels touched)."""
+    out, ops = parse(spec)
+
+    def keep(labels, others):
+        rest = set(out).union(*others) if others else set(out)
+        return frozenset(l for l in labels if l in rest)
+
+    best = math.inf
+
+    def go(items, cost):
+        nonlocal best
+        if len(items) == 1:
+            best = min(best, cost)
+            return
+        for i, j in itertools.combinations(range(len(items)), 2):
+            touched = items[i] | items[j]
+            others = [items[k] for k in range(len(items)) if k not in (i, j)]
+            new = keep(touched, others)
+            c = 2 * math.prod(ext[l] for l in touched)
+            go(others + [new], cost + c)
+
+    go([frozenset(o) for o in ops], 0)
+    return best
+
+
+def natural(spec, ext):
+    out, ops = parse(spec)
+    acc, total = frozenset(ops[0]), 0
+    for i in range(1, len(ops)):
+        rest = set(out).union(*[set(o) for o in ops[i + 1:]])
+        touched = acc | frozenset(ops[i])
+        total += 2 * math.prod(ext[l] for l in touched)
+        acc = frozenset(l for l in touched if l in rest)
+    return total
+
+
+# The shapes of the paper's Table 1 (3 and 4 operands; output = the labels
+# that occur once), with occupied labels (i, j, m, n) of extent O and virtual
+# ones (a .. f) of extent V: NWChem-like, skinny in the occupied labels.
+TABLE1 = [
+    "cdmn*inad*mc", "dcmn*inad*mc", "cdmn*id*na*mc", "dcmn*id*na*mc", "mnej*ei*am*bn",
+    "mnfe*ei*fn*abmj", "mnef*am*fn*ebij", "mnef*bm*fn*eaji", "nmef*am*fn*ebij", "nmef*bm*fn*eaji",
+    "mnef*ei*fn*abmj", "mnef*ej*fn*bami", "mnfe*ej*fn*bami",
+]
+
+
+def with_output(rhs):
+    ops = rhs.split("*")
+    once = [l for l in dict.fromkeys("".join(ops)) if sum(l in o for o in ops) == 1]
+    return "".join(once) + "=" + rhs
+
+
+@pytest.mark.parametrize("rhs", TABLE1)
+@pytest.mark.parametrize("O,V", [(8, 32), (16, 96), (5, 100)])
+def test_table1_shapes_against_brute_force(rhs, O, V):
+    spec = with_output(rhs)
+    ext = {l: (O if l in "ijmn" else V) for l in set(spec) - {"=", "*"}}
+    plan = comet.chain_plan(spec, ext)
+    assert plan["flops"] == brute_force(spec, ext)
+    assert plan["natural_flops"] == natural(spec, ext)
+    assert plan["flops"] <= plan["natural_flops"]
+    assert sum(s["flops"] for s in plan["steps"]) == plan["flops"]
+
+
+@pytest.mark.parametrize("spec,ext", [
+    ("abil=acik*cbkj*jl", dict(a=8, b=8, i=8, l=4, c=8, k=8, j=8)),
+    ("ai=cdmn*inad*mc", dict(a=100, i=100, c=5, d=100, m=100, n=100)),
+    ("ij=ik*kl*lm*mj", dict(i=300, k=10, l=300, m=10, j=300)),
+    ("ij=ik*kl*lm*mn*nj", dict(i=7, k=500, l=3, m=400, n=9, j=11)),
+    ("=ab*bc*ca", dict(a=3, b=4, c=5)),
+])
+def test_steps_are_valid_binary_contractions(spec, ext):
+    plan = comet.chain_plan(spec, ext)
+    out, ops = parse(spec)
+    labels = list(ops)
+    assert plan["flops"] == brute_force(spec, ext)
+    for k, st in enumerate(plan["steps"]):
+        c, ab = st["spec"].split("=")
+        a, b = ab.split("*")
+        assert a == labels[st["left"]] and b == labels[st["right"]]
+        # every label of the step in exactly two of its three tensors
+        for l in set(a + b + c):
+            assert (l in a) + (l in b) + (l in c) == 2
+        assert st["flops"] == 2 * math.prod(ext[l] for l in set(a + b))
+        labels.append(c)
+    assert sorted(labels[-1]) == sorted(out) and labels[-1] == out
+
+
+def status(spec, ext):
+    import ctypes
+    buf = ctypes.create_string_buffer(4096)
+    arr = (ctypes.c_int64 * max(1, len(ext)))(*ext)
+    return comet.lib().comet_chain_plan(spec.encode(), arr, buf, len(buf))
+
+
+def test_chain_validation():
+    assert status("ij=ik*kl*lj", [2, 3, 4, 5]) == OK
+    assert status("ij=ik*kl*lkj", [2, 3, 4, 5]) == UNSUP      # k in three tensors
+    assert status("ij=ik*kl*lm", [2, 3, 4, 5, 6]) == SPEC     # j and m once
+    assert status("ij=ij", [2, 3]) == SPEC                    # one operand
+    assert status("ij=ik**kj", [2, 3, 4]) == SPEC             # empty operand
+    assert status("ij=ik*kl*lj", [2, -3, 4, 5]) == SHAPE
+    nine = "=" + "*".join(["ab", "bc", "cd", "de", "ef", "fg", "gh", "hi", "ia"])
+    assert status(nine, [2] * 9) == UNSUP
