@@ -15,7 +15,8 @@
  *
  * The free (external) indices each appear in exactly one input and in the
  * output; the contraction (summation) indices appear in both inputs and not
- * in the output (Section 2).  beta == 0 means C is not read; alpha == 0 means
+ * in the output (Section 2).  A label in all three tensors (a batch label)
+ * indexes the output and both inputs and is not summed.  beta == 0 means C is not read; alpha == 0 means
  * A and B are not read (BLAS convention; the paper only has "=" (beta 0) and
  * "+=" / "-=" (beta 1, alpha negated for "-=")).
  *
@@ -111,7 +112,13 @@ static int or_table(const or_spec_t *sp, const int64_t *dims[3],
   }
   for (int r = 0; r < tb->n; ++r) {
     int cnt = tb->in[0][r] + tb->in[1][r] + tb->in[2][r];
-    if (cnt != 2) return OR_ERR_SPEC;      /* in one tensor only, or in all three */
+    /* A label in all three tensors is a batch label: it indexes C, A and B
+     * alike and is not summed (the label grammar of Section 4 does not forbid
+     * it).  The sum below already treats it that way -- it is one of C's
+     * labels, so it fixes A's and B's addresses for each output element and
+     * is not among A's contracted labels. */
+    if (cnt < 2) return OR_ERR_SPEC;       /* in one tensor only */
+    if (cnt == 3 && !tb->in[0][r]) return OR_ERR_SPEC;
   }
   return OR_OK;
 }

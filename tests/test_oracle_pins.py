@@ -141,6 +141,52 @@ def test_oracle_integer_inputs_exact_vs_integer_einsum(case):
 
 
 # --------------------------------------------------------------------------
+# batch labels (in C, A and B: they index all three and are not summed)
+# --------------------------------------------------------------------------
+
+def random_batch_spec(rng, max_per_class=2):
+    letters = list("abcdefghijklmnopqrstuvwxyz")
+    rng.shuffle(letters)
+    nx = rng.randint(1, 2)
+    nm, nn, nk = (rng.randint(0, max_per_class) for _ in range(3))
+    x = letters[:nx]
+    m = letters[nx:nx + nm]
+    n = letters[nx + nm:nx + nm + nn]
+    k = letters[nx + nm + nn:nx + nm + nn + nk]
+    a, b, c = x + m + k, x + k + n, x + m + n
+    for t in (a, b, c):
+        rng.shuffle(t)
+    return "%s=%s*%s" % ("".join(c), "".join(a), "".join(b))
+
+
+@pytest.mark.parametrize("case", range(30))
+def test_batch_labels_equal_python_loop_einsum_and_bruteforce(case):
+    rng = random.Random(5000 + case)
+    spec = random_batch_spec(rng)
+    ext = random_extents(rng, spec, 1, 4)
+    A, B, C0 = make_inputs(spec, ext, 15000 + 10 * case, integer=case % 2 == 1, beta=True)
+    got = oracle.contract(spec, A, B, C0, alpha=0.5, beta=-1.0)
+    assert np.array_equal(got, python_loop(spec, A, B, C0, 0.5, -1.0)), spec
+    assert np.allclose(oracle.contract(spec, A, B), einsum(spec, A, B), rtol=1e-13, atol=1e-14), spec
+    brute = oracle.bruteforce(spec, A, B, C0, alpha=0.5, beta=-1.0)
+    if case % 2:
+        assert np.array_equal(got, brute), spec
+    else:
+        assert oracle.relerr(got, brute) <= 1e-14, spec
+
+
+def test_hadamard_product_closed_form():
+    """All labels batch labels: C = A * B elementwise, exactly."""
+    A = synth.uniform(121, (5, 7, 3))
+    B = synth.uniform(122, (5, 7, 3))
+    assert np.array_equal(oracle.contract("ijk=ijk*ijk", A, B), A * B)
+    # a batch of matrix products against numpy matmul
+    X = synth.uniform(123, (4, 6, 5))
+    Y = synth.uniform(124, (4, 5, 7))
+    assert oracle.relerr(oracle.contract("bij=bik*bkj", X, Y), np.matmul(X, Y)) <= 1e-15
+
+
+# --------------------------------------------------------------------------
 # closed forms on the benchmark configurations' specs
 # --------------------------------------------------------------------------
 
@@ -382,7 +428,7 @@ def test_thread_count_does_not_change_bits():
     "abij=acik*cbk",      # j only in C
     "abij=acik*cbkjj",    # repeated label within a tensor
     "abij=aik*cbkj",      # c only in B
-    "aij=acik*ackj",      # a in all three
+    "abij=acik*ckj",      # b only in C
     "abij-acik*cbkj",     # no '='
     "abij=acik",          # no '*'
     "ab1j=acik*cbkj",     # bad character
