@@ -15,10 +15,15 @@
  * spec     "C=A*B" label strings, e.g. "abij=acik*cbkj".  One ASCII letter per
  *          tensor dimension, blanks ignored, rank <= COMET_MAX_RANK per tensor
  *          (rank 0 is allowed for C: a full contraction to a scalar).  Every
- *          label must appear in exactly two of C, A, B (free labels in C and
- *          one input; summation labels in A and B).  A label in all three
- *          tensors returns COMET_ERR_UNSUPPORTED; a label in one tensor only,
- *          or repeated inside one tensor, returns COMET_ERR_INVALID_SPEC.
+ *          label must appear in at least two of C, A, B: free labels in C and
+ *          one input, summation labels in A and B, and batch labels in all
+ *          three.  A batch label indexes C, A and B alike and is not summed
+ *          (e.g. "bij=bik*bkj" is a batch of matrix products, "ij=ij*ij" the
+ *          elementwise product); the operation grammar of Section 4 does not
+ *          rule such labels out.  The TTGT path (COMET_PATH_TTGT) has no
+ *          batch labels and returns COMET_ERR_UNSUPPORTED for them.  A label
+ *          in one tensor only, or repeated inside one tensor, returns
+ *          COMET_ERR_INVALID_SPEC.
  * extents  one int64 per distinct label, in order of first appearance when
  *          scanning C's labels, then A's, then B's.  Negative extents and
  *          tensor sizes that overflow int64 return COMET_ERR_INVALID_SHAPE.
@@ -31,6 +36,11 @@
  *          and B.  C must not overlap itself: stride 0 on a C dimension of
  *          extent > 1, or dimensions that interleave, return
  *          COMET_ERR_INVALID_STRIDE.
+ *          A stepped index range [lo:hi:step] of a label (Section 4, index
+ *          labels with a range; read here as the indices lo, lo + step, ...
+ *          below hi) is a view: pass the base pointer moved to element lo,
+ *          the extent ceil((hi - lo) / step) and the stride multiplied by
+ *          step.
  * pointers A, B, C and workspaces are device pointers owned by the caller;
  *          the library never frees them and keeps none after the call
  *          returns (except inside a graph the caller captured).  C must not
@@ -46,8 +56,9 @@
  *          failing call of the calling thread.  A HIP launch failure returns
  *          COMET_ERR_HIP; a device fault surfaces at the caller's next sync.
  * determinism  the same plan and inputs give bit-identical outputs: no
- *          atomics in any reduction, no split of the summation across
- *          workgroups.
+ *          atomics in any reduction; where the summation of an output tile
+ *          is split across workgroups (stream-K), the pieces are added in a
+ *          fixed order.
  */
 #ifndef COMET_H
 #define COMET_H
@@ -207,7 +218,9 @@ comet_status_t comet_analyze(const char *spec, const int64_t *extents,
  * native MFMA (DEFAULT, or F64 / F32 matching the dtype), or SPLIT_BF16X3
  * with FP32 storage (operands split into three bfloat16 slices inside the
  * loader).  Problems with an empty summation or alpha == 0 are scaled by
- * beta before the launch.  The workspace holds the work counter (256 bytes).
+ * beta before the launch.  A problem with batch labels contributes one
+ * problem per batch entry to the work list.  The workspace holds the work
+ * counter (256 bytes).
  * comet_batch_create plans every problem and uploads the work list and
  * offset tables (not capturable); comet_batch_execute is capturable.
  */

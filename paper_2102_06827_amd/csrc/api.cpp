@@ -72,8 +72,9 @@ std::vector<int64_t> dense_strides(const std::vector<int64_t> &ext) {
 struct comet_plan_s {
   Analysis an;
   int device = 0;
-  void *dtables = nullptr;     // the six offset tables, one device allocation
+  void *dtables = nullptr;     // the six offset tables (and three batch tables), one device allocation
   GettTables t{};
+  const int64_t *offAx = nullptr, *offBx = nullptr, *offCx = nullptr;   // batch tables (device), or null
   bool vecA_tables = false, vecB_tables = false;
   bool fused3 = false;         // FP32 operands split into BF16x3 inside the gather kernel
   size_t ws_bytes = 0;
@@ -97,6 +98,8 @@ struct comet_batch_s {
     const int64_t *offCm, *offCn;
     int64_t m, n;
     double beta;
+    const int64_t *offCb;          // batch entries of C (device), or null
+    int64_t nb;
   };
   int device = 0;
   comet_dtype_t dtype = COMET_F64;
@@ -117,15 +120,16 @@ namespace {
 
 comet_status_t upload_tables(comet_plan_s *p) {
   const Analysis &an = p->an;
-  const std::vector<int64_t> *tabs[6] = {&an.offAm, &an.offAk, &an.offBk, &an.offBn, &an.offCm, &an.offCn};
-  size_t off[6], total = 0;
-  for (int i = 0; i < 6; ++i) {
+  const std::vector<int64_t> *tabs[9] = {&an.offAm, &an.offAk, &an.offBk, &an.offBn, &an.offCm,
+                                         &an.offCn, &an.offAx, &an.offBx, &an.offCx};
+  size_t off[9], total = 0;
+  for (int i = 0; i < 9; ++i) {
     off[i] = total;
     total += align256(std::max<size_t>(tabs[i]->size(), 1) * sizeof(int64_t));
   }
   HIP_TRY(hipMalloc(&p->dtables, total), "hipMalloc(offset tables)");
   std::vector<char> host(total, 0);
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 9; ++i)
     if (!tabs[i]->empty()) std::memcpy(host.data() + off[i], tabs[i]->data(), tabs[i]->size() * sizeof(int64_t));
   HIP_TRY(hipMemcpy(p->dtables, host.data(), total, hipMemcpyHostToDevice), "hipMemcpy(offset tables)");
   char *b = static_cast<char *>(p->dtables);
@@ -135,6 +139,11 @@ comet_status_t upload_tables(comet_plan_s *p) {
   p->t.offBn = reinterpret_cast<const int64_t *>(b + off[3]);
   p->t.offCm = reinterpret_cast<const int64_t *>(b + off[4]);
   p->t.offCn = reinterpret_cast<const int64_t *>(b + off[5]);
+  if (!an.offAx.empty()) {
+    p->offAx = reinterpret_cast<const int64_t *>(b + off[6]);
+    p->offBx = reinterpret_cast<const int64_t *>(b + off[7]);
+    p->offCx = reinterpret_cast<const int64_t *>(b + off[8]);
+  }
   return COMET_OK;
 }
 
@@ -225,7 +234,7 @@ Schedule model_tile(const Analysis &an, int tile, int resident, int cus) {
   if (tile >= nthr || resident <= 0) return out;
   int bm, bn, bk;
   gett_tile_shape(tile, &bm, &bn, &bk);
-  const int64_t T = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+  const int64_t T = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn) * std::max<int64_t>(an.nb, 1);
   const int64_t S = int64_t(std::max(cus, 1)) * resident;
   const int64_t nk = (an.k + bk - 1) / bk;
   const double rt = double(resident) * bm * bn / thr[tile] * double(nk * bk) / 3072.0;
@@ -289,7 +298,7 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
     best.tile = forced_tile;
   } else {
     for (int t = 0; t < gett_tile_count(); ++t) {
-      if (!gett_tile_valid(t, dt, cp, vecA, vecB)) continue;
+      if (!gett_tile_valid(t, dt, cp, vecA, vecB, !an.X.empty())) continue;
       Schedule sc = model_tile(an, t, tile_resident(an, t, vecA, vecB), cus);
       if (sc.us < best.us * 0.999) best = sc;
     }
@@ -306,7 +315,7 @@ void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
   Analysis &an = p->an;
   Schedule sc = pick_schedule(an, cus, p->vecA_tables, p->vecB_tables, forced_tile);
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
-  if (!native || an.empty_out || an.empty_sum) sc.sk_tiles = sc.sk_blocks = sc.persist = 0;
+  if (!native || an.empty_out || an.empty_sum || !an.X.empty()) sc.sk_tiles = sc.sk_blocks = sc.persist = 0;
   an.tile = sc.tile;
   an.sk_tiles = sc.sk_tiles;
   an.sk_blocks = sc.sk_blocks;
@@ -325,6 +334,8 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
                         hipStream_t s, void *ws);
 comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
                        void *ws, size_t ws_bytes, hipStream_t s);
+comet_status_t execute_one(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
+                           void *ws, hipStream_t s);
 
 comet_status_t build_ttgt(comet_plan_s *p) {
   Analysis &an = p->an;
@@ -437,8 +448,14 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   comet_status_t rc = upload_tables(p.get());
   if (rc != COMET_OK) return rc;
   const int VEC = an.dtype == COMET_F64 ? 2 : 4;
-  p->vecA_tables = tables_vec_ok(an.offAm, an.offAk, an.layoutA, an.runAm, an.runAk, VEC);
-  p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC);
+  // with batch labels every entry's base offset keeps the alignment too
+  auto all_vec = [&](const std::vector<int64_t> &x) {
+    for (int64_t v : x)
+      if (v % VEC) return false;
+    return true;
+  };
+  p->vecA_tables = tables_vec_ok(an.offAm, an.offAk, an.layoutA, an.runAm, an.runAk, VEC) && all_vec(an.offAx);
+  p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC) && all_vec(an.offBx);
   apply_schedule(p.get(), cus);
   if (p->gemm) {
     apply_schedule(p->gemm.get(), cus);
@@ -488,13 +505,21 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
   g.tile = an.tile;
   // misaligned pointers or a tile not built for this dtype pair: the 64 x 64
   // tile has every variant
-  if (!gett_tile_valid(g.tile, g.dtype, g.compute, g.vecA, g.vecB)) g.tile = 1;
+  if (!gett_tile_valid(g.tile, g.dtype, g.compute, g.vecA, g.vecB, p->offAx != nullptr)) g.tile = 1;
   if (an.sk_tiles > 0 && g.tile == an.tile && ws) {
     g.sk.tiles = an.sk_tiles;
     g.sk.blocks = an.sk_blocks;
     g.sk.ws = ws;
   }
   if (an.persist > 0 && g.tile == an.tile) g.persistent = an.persist;
+  if (p->offAx) {
+    g.bt.offA = p->offAx;
+    g.bt.offB = p->offBx;
+    g.bt.offC = p->offCx;
+    g.bt.count = an.nb;
+    g.sk = StreamK{};
+    g.persistent = 0;
+  }
   HIP_TRY(launch_gett(g, s), "gett launch");
   return COMET_OK;
 }
@@ -512,11 +537,37 @@ comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const
     beta = double(float(beta));
   }
   if (alpha == 0.0 || an.empty_sum) {
-    HIP_TRY(launch_scale(C, an.dtype == COMET_F64 ? 0 : 1, p->t.offCm, p->t.offCn, an.m, an.n, beta, s), "scale");
+    HIP_TRY(launch_scale(C, an.dtype == COMET_F64 ? 0 : 1, p->t.offCm, p->t.offCn, an.m, an.n, beta, s, p->offCx,
+                         an.nb),
+            "scale");
     return COMET_OK;
   }
   if (p->ws_bytes > 0 && (!ws || ws_bytes < p->ws_bytes))
     return fail(COMET_ERR_WORKSPACE, "workspace smaller than comet_plan_workspace_size");
+  const bool split = an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
+                     an.compute == COMET_COMPUTE_SPLIT_FP16X2 || an.compute == COMET_COMPUTE_SPLIT_INT8;
+  if (!an.offAx.empty() && (p->fused3 || split)) {
+    // batch labels on the split and fused BF16x3 paths: one contraction per
+    // batch entry, in order on the stream (they share the workspace)
+    const size_t es = elem_size(an.dtype);
+    const int64_t *xa = an.swapped ? an.offBx.data() : an.offAx.data();
+    const int64_t *xb = an.swapped ? an.offAx.data() : an.offBx.data();
+    for (int64_t e = 0; e < an.nb; ++e) {
+      comet_status_t rc = execute_one(p, alpha, static_cast<const char *>(A) + xa[e] * es,
+                                      static_cast<const char *>(B) + xb[e] * es, beta,
+                                      static_cast<char *>(C) + an.offCx[e] * es, ws, s);
+      if (rc != COMET_OK) return rc;
+    }
+    return COMET_OK;
+  }
+  return execute_one(p, alpha, A, B, beta, C, ws, s);
+}
+
+// One batch entry (the whole contraction without batch labels) after the
+// checks of execute().
+comet_status_t execute_one(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
+                           void *ws, hipStream_t s) {
+  const Analysis &an = p->an;
   if (p->fused3) {
     GettLaunch g{};
     g.A = an.swapped ? B : A;
@@ -639,8 +690,10 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
     void *bufA = nullptr, *bufB = nullptr, *bufC = nullptr, *ws = nullptr;
     hipStream_t s = nullptr;
     std::unique_ptr<comet_plan_s> tt;
-    comet_status_t rc = build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false);
-    if (rc != COMET_OK) tt.reset();
+    if (an.X.empty()) {   // the TTGT lowering has no batch labels
+      comet_status_t rc = build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false);
+      if (rc != COMET_OK) tt.reset();
+    }
     size_t wsb = tt ? tt->ws_bytes : 0;
     bool ok = hipStreamCreate(&s) == hipSuccess && hipMalloc(&bufA, std::max<int64_t>(an.sizeA, 1) * es) == hipSuccess &&
               hipMalloc(&bufB, std::max<int64_t>(an.sizeB, 1) * es) == hipSuccess &&
@@ -654,7 +707,7 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
       size_t skws_bytes = 0;
       for (int tile = 0; tile < gett_tile_count(); ++tile) {
         if (!gett_tile_valid(tile, an.dtype == COMET_F64 ? 0 : 1, an.compute == COMET_COMPUTE_F64 ? 0 : 1,
-                             p->vecA_tables, p->vecB_tables))
+                             p->vecA_tables, p->vecB_tables, !an.X.empty()))
           continue;
         // each tile with its own stream-K split
         apply_schedule(p.get(), cus, tile);
@@ -1166,69 +1219,86 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
     if (reads && (pr.C == pr.A || pr.C == pr.B))
       return fail(COMET_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": C aliases an input");
   }
-  // device buffer: descriptors, work items, then every problem's six tables
-  std::vector<BatchDesc> descs(n);
+  // one descriptor per batch entry of each problem (a problem without batch
+  // labels has one); device buffer: descriptors, work items, then every
+  // problem's six tables and its C batch table
+  std::vector<int64_t> first(n + 1, 0);
+  for (int i = 0; i < n; ++i) first[i + 1] = first[i] + (an[i].empty_out ? 1 : an[i].nb);
+  const int64_t nd = first[n];
+  if (nd > INT32_MAX) return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 batch entries");
+  std::vector<BatchDesc> descs(static_cast<size_t>(nd));
   std::vector<size_t> tab_off(n, 0);
-  size_t bytes = align256(sizeof(BatchDesc) * std::max(n, 1));
+  size_t bytes = align256(sizeof(BatchDesc) * std::max<int64_t>(nd, 1));
   const size_t items_off = bytes;
   int64_t total = 0;
-  std::vector<int> order;
+  std::vector<int64_t> order;
   for (int i = 0; i < n; ++i) {
     const Analysis &a = an[i];
     if (a.empty_out || a.empty_sum || problems[i].alpha == 0.0) continue;
-    order.push_back(i);
-    total += ((a.m + kBatchTile - 1) / kBatchTile) * ((a.n + kBatchTile - 1) / kBatchTile);
+    for (int64_t e = 0; e < a.nb; ++e) order.push_back(first[i] + e);
+    total += a.nb * ((a.m + kBatchTile - 1) / kBatchTile) * ((a.n + kBatchTile - 1) / kBatchTile);
   }
   if (total > INT32_MAX) return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 tiles");
   bytes += align256(sizeof(BatchItem) * std::max<int64_t>(total, 1));
   for (int i = 0; i < n; ++i) {
     tab_off[i] = bytes;
     const Analysis &a = an[i];
-    for (const std::vector<int64_t> *v : {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn})
+    for (const std::vector<int64_t> *v : {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn, &a.offCx})
       bytes += align256(std::max<size_t>(v->size(), 1) * sizeof(int64_t));
   }
   HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
   HIP_TRY(hipMalloc(&b->dbuf, bytes), "hipMalloc(batch)");
   std::vector<char> host(bytes, 0);
   char *dev = static_cast<char *>(b->dbuf);
+  const size_t es = elem_size(dtype);
+  std::vector<int64_t> kof(size_t(nd), 0);   // summation length of each descriptor
   for (int i = 0; i < n; ++i) {
     const Analysis &a = an[i];
     const comet_problem_t &pr = problems[i];
     size_t off = tab_off[i];
-    const int64_t *ptr[6];
+    const int64_t *ptr[7];
     int k = 0;
-    for (const std::vector<int64_t> *v : {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn}) {
+    for (const std::vector<int64_t> *v : {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn, &a.offCx}) {
       if (!v->empty()) std::memcpy(host.data() + off, v->data(), v->size() * sizeof(int64_t));
       ptr[k++] = reinterpret_cast<const int64_t *>(dev + off);
       off += align256(std::max<size_t>(v->size(), 1) * sizeof(int64_t));
     }
-    BatchDesc &d = descs[i];
-    d.A = a.swapped ? pr.B : pr.A;
-    d.B = a.swapped ? pr.A : pr.B;
-    d.C = pr.C;
-    d.t = GettTables{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5]};
-    d.M = a.m;
-    d.N = a.n;
-    d.K = a.k;
-    d.alpha = dtype == COMET_F32 ? double(float(pr.alpha)) : pr.alpha;
-    d.beta = dtype == COMET_F32 ? double(float(pr.beta)) : pr.beta;
-    const bool vec = tables_vec_ok(a.offAm, a.offAk, a.layoutA, a.runAm, a.runAk, VEC) &&
-                     tables_vec_ok(a.offBn, a.offBk, a.layoutB, a.runBn, a.runBk, VEC) &&
-                     reinterpret_cast<uintptr_t>(d.A) % 16 == 0 && reinterpret_cast<uintptr_t>(d.B) % 16 == 0;
-    d.variant = a.layoutA * 2 + a.layoutB + (vec ? 0 : 4);
-    d.tilesN = int((a.n + kBatchTile - 1) / kBatchTile);
+    const double alpha = dtype == COMET_F32 ? double(float(pr.alpha)) : pr.alpha;
+    const double beta = dtype == COMET_F32 ? double(float(pr.beta)) : pr.beta;
+    const void *pa = a.swapped ? pr.B : pr.A, *pb = a.swapped ? pr.A : pr.B;
+    const bool vec_tables = tables_vec_ok(a.offAm, a.offAk, a.layoutA, a.runAm, a.runAk, VEC) &&
+                            tables_vec_ok(a.offBn, a.offBk, a.layoutB, a.runBn, a.runBk, VEC);
+    for (int64_t e = 0; e < (a.empty_out ? 1 : a.nb); ++e) {
+      BatchDesc &d = descs[size_t(first[i] + e)];
+      const bool bx = !a.offAx.empty() && !a.empty_out;
+      d.A = pa ? static_cast<const char *>(pa) + (bx ? a.offAx[e] * es : 0) : nullptr;
+      d.B = pb ? static_cast<const char *>(pb) + (bx ? a.offBx[e] * es : 0) : nullptr;
+      d.C = pr.C ? static_cast<char *>(pr.C) + (bx ? a.offCx[e] * es : 0) : nullptr;
+      d.t = GettTables{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5]};
+      d.M = a.m;
+      d.N = a.n;
+      d.K = a.k;
+      d.alpha = alpha;
+      d.beta = beta;
+      const bool vec = vec_tables && reinterpret_cast<uintptr_t>(d.A) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(d.B) % 16 == 0;
+      d.variant = a.layoutA * 2 + a.layoutB + (vec ? 0 : 4);
+      d.tilesN = int((a.n + kBatchTile - 1) / kBatchTile);
+      kof[size_t(first[i] + e)] = a.k;
+    }
     if (!a.empty_out && (a.empty_sum || pr.alpha == 0.0))
-      b->scales.push_back({pr.C, ptr[4], ptr[5], a.m, a.n, d.beta});
+      b->scales.push_back({pr.C, ptr[4], ptr[5], a.m, a.n, beta, a.offCx.empty() ? nullptr : ptr[6], a.nb});
   }
   // longest summation first, so the heaviest tiles start early
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return an[x].k > an[y].k; });
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return kof[size_t(x)] > kof[size_t(y)]; });
   BatchItem *items = reinterpret_cast<BatchItem *>(host.data() + items_off);
   int64_t w = 0;
-  for (int i : order) {
-    const int64_t tiles = ((an[i].m + kBatchTile - 1) / kBatchTile) * ((an[i].n + kBatchTile - 1) / kBatchTile);
-    for (int64_t t = 0; t < tiles; ++t) items[w++] = BatchItem{i, int(t)};
+  for (int64_t j : order) {
+    const BatchDesc &d = descs[size_t(j)];
+    const int64_t tiles = ((d.M + kBatchTile - 1) / kBatchTile) * d.tilesN;
+    for (int64_t t = 0; t < tiles; ++t) items[w++] = BatchItem{int(j), int(t)};
   }
-  if (n > 0) std::memcpy(host.data(), descs.data(), sizeof(BatchDesc) * n);
+  if (nd > 0 && n > 0) std::memcpy(host.data(), descs.data(), sizeof(BatchDesc) * size_t(nd));
   HIP_TRY(hipMemcpy(b->dbuf, host.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(batch)");
   b->descs = reinterpret_cast<const BatchDesc *>(dev);
   b->items = reinterpret_cast<const BatchItem *>(dev + items_off);
@@ -1252,7 +1322,8 @@ comet_status_t comet_batch_execute(comet_batch_t batch, void *workspace, size_t 
   if (!workspace || ws_bytes < 256) return fail(COMET_ERR_WORKSPACE, "batch workspace needs 256 bytes");
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (const auto &sc : batch->scales)
-    HIP_TRY(launch_scale(sc.C, batch->dtype == COMET_F64 ? 0 : 1, sc.offCm, sc.offCn, sc.m, sc.n, sc.beta, s),
+    HIP_TRY(launch_scale(sc.C, batch->dtype == COMET_F64 ? 0 : 1, sc.offCm, sc.offCn, sc.m, sc.n, sc.beta, s,
+                         sc.offCb, sc.nb),
             "batch scale");
   HIP_TRY(launch_batch(batch->descs, batch->items, batch->total, static_cast<int *>(workspace),
                        batch->dtype == COMET_F64 ? 0 : 1, batch->mode, batch->grid, s),

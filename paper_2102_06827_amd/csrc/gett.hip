@@ -86,6 +86,30 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
                                                            int64_t(tn) * BN, smem);
 }
 
+// Batch labels: blockIdx.y selects batch entry bt.first + blockIdx.y, whose
+// slices of A, B and C the three base pointers move to, and blockIdx.x the
+// tile in the XCD-aware order (the XCD of a workgroup is its linear id
+// modulo 8, so the tiles the remap groups still share one).  A kernel of its
+// own so that gett_kernel keeps its register budget; the entry comes from
+// the grid rather than a division of a flat id, which costs registers.
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_batch_kernel(
+    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+    int64_t K, double alpha, double beta, int tilesM, int tilesN, GettBatch bt) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
+  const int64_t x = bt.first + blockIdx.y;
+  int tm, tn;
+  group_coords(xcd_remap(blockIdx.x, gridDim.x), tilesM, tilesN, &tm, &tn);
+  gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(A + bt.offA[x], B + bt.offB[x], C + bt.offC[x], t, M, N,
+                                                           K, alpha, beta, int64_t(tm) * BM, int64_t(tn) * BN, smem);
+}
+
+// the tile variants compiled with batch labels
+constexpr bool batch_tile(int tile) { return tile == 1 || tile == 3; }
+
 // Stream-K: the last sk.tiles tiles (ids dp .. dp + sk.tiles - 1) split
 // along the summation over sk.blocks workgroups, each taking an equal number
 // of BK steps, so that the last, partial round of whole tiles becomes a full
@@ -358,6 +382,30 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
                                                           NT, 0);
     }
     const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
+    const Tin *A = static_cast<const Tin *>(g.A), *B = static_cast<const Tin *>(g.B);
+    Tin *C = static_cast<Tin *>(g.C);
+    if (g.bt.offA) {
+      // batch labels: whole tiles, as many entries per launch as the grid
+      // size allows
+      if constexpr (!batch_tile(TILE)) {
+        return hipErrorInvalidValue;
+      } else {
+        const int64_t per = int64_t(tilesM) * tilesN;
+        constexpr int64_t kMaxY = 65535;   // grid limit along y
+        if (per * NT > int64_t(UINT32_MAX) || !g.bt.offB || !g.bt.offC) return hipErrorInvalidValue;
+        for (int64_t e0 = 0; e0 < g.bt.count; e0 += kMaxY) {
+          GettBatch bt = g.bt;
+          bt.first = g.bt.first + e0;
+          bt.count = std::min(kMaxY, g.bt.count - e0);
+          hipLaunchKernelGGL((gett_batch_kernel<Tin, Tc, TILE, LA, LB, VA, VB>),
+                             dim3(unsigned(per), unsigned(bt.count)), dim3(NT), 0, s, A, B, C, g.t, g.M, g.N, g.K,
+                             g.alpha, g.beta, tilesM, tilesN, bt);
+          hipError_t e = hipGetLastError();
+          if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+      }
+    }
     if (g.persistent > 0) {
       if constexpr (!persistent_fits<Tin, Tc, TILE, LA, LB, VA, VB>()) {
         return hipErrorInvalidValue;
@@ -372,8 +420,6 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
     StreamK sk = g.sk;
     if (sk.blocks <= 0 || sk.tiles <= 0 || sk.tiles > tilesM * tilesN || !sk.ws) sk = StreamK{};
     const int dp = tilesM * tilesN - sk.tiles;
-    const Tin *A = static_cast<const Tin *>(g.A), *B = static_cast<const Tin *>(g.B);
-    Tin *C = static_cast<Tin *>(g.C);
     if (dp > 0) {
       hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(dp), dim3(NT), 0, s, A, B, C, g.t, g.M,
                          g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
@@ -437,16 +483,17 @@ hipError_t launch_tc(const GettLaunch &g, hipStream_t s) {
   }
 }
 
-// beta * C over the (m, n) index space of C
+// beta * C over the (b, m, n) index space of C
 template <typename T>
 __global__ __launch_bounds__(256) void scale_kernel(T *__restrict__ C, const int64_t *__restrict__ offCm,
                                                     const int64_t *__restrict__ offCn, int64_t M, int64_t N,
-                                                    double beta) {
-  const int64_t total = M * N;
+                                                    double beta, const int64_t *__restrict__ offCb, int64_t NB) {
+  const int64_t MN = M * N, total = NB * MN;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
        i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t m = i / N, n = i - m * N;
-    const int64_t a = offCm[m] + offCn[n];
+    const int64_t b = i / MN, r = i - b * MN;
+    const int64_t m = r / N, n = r - m * N;
+    const int64_t a = (offCb ? offCb[b] : 0) + offCm[m] + offCn[n];
     C[a] = beta == 0.0 ? T(0) : T(double(C[a]) * beta);
   }
 }
@@ -465,8 +512,9 @@ void gett_tile_shape(int tile, int *bm, int *bn, int *bk) {
   *bk = kTiles[tile].bk;
 }
 
-bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB) {
+bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB, bool batch) {
   if (tile < 0 || tile >= kNumTiles) return false;
+  if (batch && !batch_tile(tile)) return false;
   if (tile != 1 && (!vecA || !vecB)) return false;
   const bool same = (dtype == 0) == (compute == 0);
   if (!same && tile > 1) return false;
@@ -496,16 +544,17 @@ int gett_occupancy(const GettLaunch &g) {
 }
 
 hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,
-                        double beta, hipStream_t s) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  int64_t total = M * N;
+                        double beta, hipStream_t s, const int64_t *offCb, int64_t NB) {
+  if (M <= 0 || N <= 0 || NB <= 0) return hipSuccess;
+  if (!offCb && NB != 1) return hipErrorInvalidValue;
+  int64_t total = NB * M * N;
   int blocks = int(std::min<int64_t>((total + 255) / 256, 4096));
   if (dtype == 0)
     hipLaunchKernelGGL(scale_kernel<double>, dim3(blocks), dim3(256), 0, s, static_cast<double *>(C), offCm, offCn, M,
-                       N, beta);
+                       N, beta, offCb, NB);
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(C), offCm, offCn, M,
-                       N, beta);
+                       N, beta, offCb, NB);
   return hipGetLastError();
 }
 

@@ -23,6 +23,16 @@ struct StreamK {
   void *ws = nullptr;
 };
 
+// Batch labels: entries first .. first + count - 1 of the per-entry base
+// offsets (elements) of A, B and C; offA == nullptr means no batch labels.
+// A launch's grid is tiles x entries (at most 65535 entries per launch);
+// tiles 1 and 3.
+struct GettBatch {
+  const int64_t *offA = nullptr, *offB = nullptr, *offC = nullptr;
+  int64_t first = 0;
+  int64_t count = 1;
+};
+
 // dtype_in/out: 0 = double, 1 = float.  compute: 0 = FP64 MFMA, 1 = FP32 MFMA.
 struct GettLaunch {
   const void *A;
@@ -40,6 +50,7 @@ struct GettLaunch {
   int *occupancy = nullptr;   // when set: store the resident workgroups per CU, launch nothing
   StreamK sk;
   int persistent = 0;         // > 0: this many persistent workgroups walk the tiles (no stream-K)
+  GettBatch bt;               // batch labels: whole tiles only (no stream-K, not persistent)
 };
 
 hipError_t launch_gett(const GettLaunch &g, hipStream_t s);
@@ -50,8 +61,9 @@ int gett_tile_count();
 // bytes of one stream-K workspace slot (one partial output tile)
 size_t gett_sk_slot_bytes(int tile, int compute);
 void gett_tile_shape(int tile, int *bm, int *bn, int *bk);
-// whether a tile variant is compiled for this dtype/compute/vector combination
-bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB);
+// whether a tile variant is compiled for this dtype/compute/vector
+// combination (and with batch labels)
+bool gett_tile_valid(int tile, int dtype, int compute, bool vecA, bool vecB, bool batch = false);
 
 // GETT with FP32 operands split on the fly into three bfloat16 slices
 // (the six products b_p c_q with p + q <= 2 on BF16 MFMA, FP32 accumulation);
@@ -80,9 +92,11 @@ hipError_t launch_batch(const BatchDesc *descs, const BatchItem *items, int64_t 
 int batch_blocks_per_cu(int dtype, int mode);
 constexpr int kBatchTile = 64;
 
-// C[offCm[m] + offCn[n]] = beta * C (beta == 0 writes zeros without reading).
+// C[offCb[b] + offCm[m] + offCn[n]] = beta * C over NB batch entries
+// (offCb == nullptr: NB must be 1 and offCb[0] reads as 0); beta == 0 writes
+// zeros without reading.
 hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,
-                        double beta, hipStream_t s);
+                        double beta, hipStream_t s, const int64_t *offCb = nullptr, int64_t NB = 1);
 
 // N-dimensional permutation out = alpha * in (+ beta * out), dims given in
 // output order with both strides.

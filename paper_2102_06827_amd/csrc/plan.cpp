@@ -2,7 +2,9 @@
 //
 // Parsing and validation follow the label rules of Section 2: summation
 // indices appear in both inputs and not in the output; free indices appear in
-// one input and the output.  Label fusion is the index merging of the TTGT
+// one input and the output.  A label in all three tensors is a batch label:
+// it selects one slice of C, A and B, and each slice is an ordinary
+// contraction of the other labels.  Label fusion is the index merging of the TTGT
 // flattening (Section 2: consecutive indices merged into one matrix index);
 // here it is done only where the merged index is still one stride in every
 // tensor holding it.  The TTGT permutation is picked by the cost model of
@@ -58,10 +60,7 @@ Status parse_spec(const char *spec, Analysis &an) {
   for (char ch : an.labels) {
     int cnt = (an.spec_c.find(ch) != std::string::npos) + (an.spec_a.find(ch) != std::string::npos) +
               (an.spec_b.find(ch) != std::string::npos);
-    if (cnt == 3)
-      return Status::error(COMET_ERR_UNSUPPORTED,
-                           std::string("label '") + ch + "' is in C, A and B (batch labels are not supported)");
-    if (cnt != 2)
+    if (cnt < 2)
       return Status::error(COMET_ERR_INVALID_SPEC, std::string("label '") + ch + "' appears in only one tensor");
   }
   return Status{};
@@ -433,12 +432,17 @@ Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_
     tensor_span(e, an.strC, &an.sizeC);
   }
 
-  // classify; exchange A and B when C's smallest-stride dimension comes from A
+  auto in_all = [&](char ch) {
+    return an.spec_a.find(ch) != std::string::npos && an.spec_b.find(ch) != std::string::npos &&
+           an.spec_c.find(ch) != std::string::npos;
+  };
+  // classify; exchange A and B when C's smallest-stride matrix dimension
+  // comes from A
   {
     int64_t best = INT64_MAX;
     char unit = 0;
     for (size_t p = 0; p < an.spec_c.size(); ++p) {
-      if (ext_of(an.spec_c[p]) <= 1) continue;
+      if (ext_of(an.spec_c[p]) <= 1 || in_all(an.spec_c[p])) continue;
       if (an.strC[p] < best) {
         best = an.strC[p];
         unit = an.spec_c[p];
@@ -458,17 +462,17 @@ Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_
     d.sB = stride_in(lb, sb, ch);
     d.sC = stride_in(an.spec_c, an.strC, ch);
     bool inA = la.find(ch) != std::string::npos, inB = lb.find(ch) != std::string::npos;
-    d.cls = (inA && inB) ? CLS_K : inA ? CLS_M : CLS_N;
-    int64_t &tot = d.cls == CLS_M ? an.m : d.cls == CLS_N ? an.n : an.k;
+    d.cls = in_all(ch) ? CLS_X : (inA && inB) ? CLS_K : inA ? CLS_M : CLS_N;
+    int64_t &tot = d.cls == CLS_M ? an.m : d.cls == CLS_N ? an.n : d.cls == CLS_K ? an.k : an.nb;
     tot *= d.ext;
     if (d.ext == 1) continue;
-    (d.cls == CLS_M ? an.M : d.cls == CLS_N ? an.N : an.K).push_back(d);
+    (d.cls == CLS_M ? an.M : d.cls == CLS_N ? an.N : d.cls == CLS_K ? an.K : an.X).push_back(d);
   }
-  an.empty_out = an.m == 0 || an.n == 0;
+  an.empty_out = an.m == 0 || an.n == 0 || an.nb == 0;
   an.empty_sum = an.k == 0;
   const int64_t kTableCap = int64_t(1) << 28;
-  if (an.m > kTableCap || an.n > kTableCap || an.k > kTableCap)
-    return Status::error(COMET_ERR_UNSUPPORTED, "a flattened matrix dimension exceeds 2^28");
+  if (an.m > kTableCap || an.n > kTableCap || an.k > kTableCap || an.nb > kTableCap)
+    return Status::error(COMET_ERR_UNSUPPORTED, "a flattened matrix or batch dimension exceeds 2^28");
 
   // dimension order inside each class (outermost first, last fastest)
   bool a_m_contig = !an.M.empty() && (an.K.empty() || min_stride(an.M, 0) < min_stride(an.K, 0));
@@ -480,8 +484,16 @@ Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_
   fuse(an.M, true, false, true);
   fuse(an.N, false, true, true);
   fuse(an.K, true, true, false);
+  // batch entries in C's memory order
+  sort_by(an.X, 2, 0);
+  fuse(an.X, true, true, true);
 
   if (!an.empty_out) {
+    if (!an.X.empty()) {
+      build_table(an.X, 0, an.offAx);
+      build_table(an.X, 1, an.offBx);
+      build_table(an.X, 2, an.offCx);
+    }
     build_table(an.M, 0, an.offAm);
     build_table(an.M, 2, an.offCm);
     build_table(an.N, 1, an.offBn);
@@ -510,10 +522,12 @@ Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_
   comet_path_t p = path;
   if (p == COMET_PATH_AUTO) {
     const char *env = std::getenv("COMET_FORCE_PATH");
-    p = (env && std::strcmp(env, "ttgt") == 0 && native) ? COMET_PATH_TTGT : COMET_PATH_GETT;
+    p = (env && std::strcmp(env, "ttgt") == 0 && native && an.X.empty()) ? COMET_PATH_TTGT : COMET_PATH_GETT;
   }
   if (p == COMET_PATH_TTGT && !native)
     return Status::error(COMET_ERR_UNSUPPORTED, "the TTGT path runs the native FP64/FP32 products only");
+  if (p == COMET_PATH_TTGT && !an.X.empty())
+    return Status::error(COMET_ERR_UNSUPPORTED, "the TTGT path has no batch labels (use the GETT path)");
   an.path = p;
   if (an.path == COMET_PATH_TTGT) an.ttgt = choose_ttgt(an);
   return Status{};
@@ -537,7 +551,9 @@ std::string describe_json(const Analysis &an) {
   o << ",\"compute\":\"" << cnames[an.compute] << "\"";
   o << ",\"path\":\"" << (an.path == COMET_PATH_TTGT ? "ttgt" : "gett") << "\"";
   o << ",\"swapped\":" << (an.swapped ? "true" : "false");
-  o << ",\"m\":" << an.m << ",\"n\":" << an.n << ",\"k\":" << an.k;
+  o << ",\"m\":" << an.m << ",\"n\":" << an.n << ",\"k\":" << an.k << ",\"nb\":" << an.nb;
+  o << ",";
+  json_dims(o, "X", an.X);
   o << ",";
   json_dims(o, "M", an.M);
   o << ",";

@@ -14,8 +14,10 @@ namespace comet {
 
 // Label classes.  A contraction C = A * B is the matrix product of A viewed as
 // an M x K matrix and B viewed as K x N (the TTGT flattening of Section 2):
-// M = free labels of A, N = free labels of B, K = summation labels.
-enum LabelClass { CLS_M = 0, CLS_N = 1, CLS_K = 2 };
+// M = free labels of A, N = free labels of B, K = summation labels.  A label
+// in all three tensors (X, a batch label) indexes C, A and B alike and is not
+// summed: the contraction is one such matrix product per batch entry.
+enum LabelClass { CLS_M = 0, CLS_N = 1, CLS_K = 2, CLS_X = 3 };
 
 // A (possibly fused) dimension of the index space.  `labels` holds the
 // original labels it stands for, outermost first; strides are in elements and
@@ -69,12 +71,17 @@ struct Analysis {
   // after classification (and the A/B swap, if any)
   bool swapped = false;                   // A, B exchanged so C's unit label is in N
   std::vector<Dim> M, N, K;               // outermost first; fused, extent-1 dims dropped
+  std::vector<Dim> X;                     // batch labels, same conventions
   int64_t m = 1, n = 1, k = 1;            // flattened sizes
-  bool empty_out = false;                 // m == 0 or n == 0: nothing to do
+  int64_t nb = 1;                         // batch entries (product of the X extents)
+  bool empty_out = false;                 // m, n or nb == 0: nothing to do
   bool empty_sum = false;                 // k == 0: C = beta * C
 
   // offset tables (elements), one entry per flattened index
   std::vector<int64_t> offAm, offAk, offBk, offBn, offCm, offCn;
+  // per batch entry: base offset of its slice of A, B and C (empty without
+  // batch labels; A and B after the exchange, like the tables above)
+  std::vector<int64_t> offAx, offBx, offCx;
   // contiguous-run widths (1, 2, 4 or 8) of each operand along each class
   int runAm = 1, runAk = 1, runBk = 1, runBn = 1, runCm = 1, runCn = 1;
   OperandLayout layoutA = LAYOUT_K_CONTIG, layoutB = LAYOUT_K_CONTIG;

@@ -17,7 +17,7 @@ namespace comet {
 
 namespace {
 const char *kFormat = "comet-tune-2";
-const char *kKernelVersion = "k6";   // bump when kernels change in a way that invalidates timings
+const char *kKernelVersion = "k7";   // bump when kernels change in a way that invalidates timings
 
 int bucket(int64_t x) {
   int b = 0;
@@ -131,7 +131,7 @@ std::string tune_key(const Analysis &an, const std::string &arch) {
   k << arch << "/" << kKernelVersion << "/" << (an.dtype == COMET_F64 ? "f64" : "f32")
     << "/c" << int(an.compute) << "/L" << int(an.layoutA) << int(an.layoutB) << "/r" << an.runAm << an.runAk
     << an.runBk << an.runBn << an.runCn << "/s" << (an.swapped ? 1 : 0) << "/m" << bucket(an.m) << "n" << bucket(an.n)
-    << "k" << bucket(an.k);
+    << "k" << bucket(an.k) << "b" << bucket(an.nb);
   return k.str();
 }
 

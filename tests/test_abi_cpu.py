@@ -44,7 +44,8 @@ OK, SPEC, SHAPE, STRIDE, NULLP, UNSUP = 0, 1, 2, 3, 4, 5
     ("abij=acik*cbkj", [2] * 6, OK),
     ("abij=acik*cbk", [2] * 6, SPEC),         # j in C only
     ("abij=acik*cbkjj", [2] * 6, SPEC),       # repeated label
-    ("aij=acik*ackj", [2] * 5, UNSUP),        # a in all three tensors
+    ("aij=acik*ackj", [2] * 5, OK),           # a in all three tensors: a batch label
+    ("ijk=ijk*ijk", [2] * 3, OK),             # every label a batch label: elementwise product
     ("abij-acik*cbkj", [2] * 6, SPEC),
     ("abij=acik", [2] * 6, SPEC),
     ("ab1j=acik*cbkj", [2] * 6, SPEC),
@@ -159,12 +160,35 @@ def direct_addr(labels, strides, val):
     return sum(val[ch] * s for ch, s in zip(labels, strides))
 
 
+def test_batch_labels_classes():
+    spec = "bij=bik*bkj"
+    d = comet.analyze(spec, ext_list(spec, dict(b=7, i=5, j=6, k=4)))
+    assert [x["labels"] for x in d["X"]] == ["b"] and d["nb"] == 7
+    assert d["m"] * d["n"] == 30 and d["k"] == 4
+    assert d["sk_tiles"] == 0 and d["persist"] == 0
+    # two batch labels consecutive in all three tensors fuse into one
+    spec = "xyij=xyik*xykj"
+    d = comet.analyze(spec, ext_list(spec, dict(x=3, y=4, i=5, j=6, k=2)))
+    assert [x["labels"] for x in d["X"]] == ["xy"] and d["nb"] == 12
+    # C's unit label a batch label: the exchange looks at matrix labels only
+    spec = "ijb=ikb*kjb"
+    d = comet.analyze(spec, ext_list(spec, dict(b=3, i=5, j=6, k=2)))
+    assert d["swapped"] is False and [x["labels"] for x in d["N"]] == ["j"]
+    # an empty batch is an empty output
+    spec = "bij=bik*bkj"
+    d = comet.analyze(spec, ext_list(spec, dict(b=0, i=5, j=6, k=4)))
+    assert d["empty_out"] is True
+    # the TTGT lowering has no batch labels
+    assert comet.analyze_status(spec, ext_list(spec, dict(b=2, i=5, j=6, k=4)), path=2) == UNSUP
+
+
 @pytest.mark.parametrize("spec", ["abij=acik*cbkj", "abij=acik*bkcj", "abcijk=daij*bcdk", "ajbi=kcia*cjkb",
-                                  "abij=abcd*cdij", "abij=ijcd*cdab", "abij=ciak*bkjc", "abcd=aebf*dfce"])
+                                  "abij=abcd*cdij", "abij=ijcd*cdab", "abij=ciak*bkjc", "abcd=aebf*dfce",
+                                  "bij=bik*bkj", "ibj=kbi*jbk", "xaiy=xyk*kyia", "ijk=ijk*ijk", "b=bk*bk"])
 def test_offset_decomposition_matches_direct_addressing(spec):
     """Rebuild the separable offset tables from the planner's dims and check
-    that offA[m] + offA[k] (etc.) equals the tensor's own address of every
-    label tuple."""
+    that offA[x] + offA[m] + offA[k] (etc.) equals the tensor's own address of
+    every label tuple (x: batch labels)."""
     rng = np.random.default_rng(abs(hash(spec)) % 1000)
     c, a, b = comet.split_spec(spec)
     labels = []
@@ -209,23 +233,35 @@ def test_offset_decomposition_matches_direct_addressing(spec):
     offCn, _ = table(d["N"], "sC")
     offAk, _ = table(d["K"], "sA")
     offBk, _ = table(d["K"], "sB")
-    assert len(offAm) == d["m"] and len(offBn) == d["n"] and len(offAk) == d["k"]
-    for m in range(d["m"]):
-        vm = decode(d["M"], m)
-        for kk in range(d["k"]):
-            vk = decode(d["K"], kk)
-            v = dict(vm, **vk)
-            assert offAm[m] + offAk[kk] == direct_addr(la, sa, {ch: v.get(ch, 0) for ch in la})
+    offAx, _ = table(d["X"], "sA")
+    offBx, _ = table(d["X"], "sB")
+    offCx, _ = table(d["X"], "sC")
+    assert len(offAm) == d["m"] and len(offBn) == d["n"] and len(offAk) == d["k"] and len(offAx) == d["nb"]
+    # the label tuples visited cover every element of each tensor once
+    seen = {"A": set(), "B": set(), "C": set()}
+    for x in range(d["nb"]):
+        vx = decode(d["X"], x)
+        for m in range(d["m"]):
+            vm = dict(vx, **decode(d["M"], m))
+            for kk in range(d["k"]):
+                v = dict(vm, **decode(d["K"], kk))
+                addr = offAx[x] + offAm[m] + offAk[kk]
+                assert addr == direct_addr(la, sa, {ch: v.get(ch, 0) for ch in la})
+                seen["A"].add(addr)
+            for n in range(d["n"]):
+                v = dict(vm, **decode(d["N"], n))
+                addr = offCx[x] + offCm[m] + offCn[n]
+                assert addr == direct_addr(c, sC, v)
+                seen["C"].add(addr)
         for n in range(d["n"]):
-            vn = decode(d["N"], n)
-            v = dict(vm, **vn)
-            assert offCm[m] + offCn[n] == direct_addr(c, sC, v)
-    for n in range(d["n"]):
-        vn = decode(d["N"], n)
-        for kk in range(d["k"]):
-            vk = decode(d["K"], kk)
-            v = dict(vn, **vk)
-            assert offBk[kk] + offBn[n] == direct_addr(lb, sb, v)
+            vn = dict(vx, **decode(d["N"], n))
+            for kk in range(d["k"]):
+                v = dict(vn, **decode(d["K"], kk))
+                addr = offBx[x] + offBk[kk] + offBn[n]
+                assert addr == direct_addr(lb, sb, v)
+                seen["B"].add(addr)
+    for name, labs in (("A", la), ("B", lb), ("C", c)):
+        assert len(seen[name]) == int(np.prod([ext[ch] for ch in labs])), name
 
 
 def test_ttgt_cost_model_on_the_worked_example():
