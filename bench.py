@@ -23,6 +23,8 @@ The same line also carries, each timed with HIP events on the launch stream:
   batch      1024 independent 4D contractions of six patterns with per-label
              extents from {8,...,64}, forward + backward in one persistent
              launch replayed from a HIP graph (FP32 and BF16x3);
+  batch_labels  contractions with a label in C, A and B (batched products),
+             against torch.bmm where the layout allows;
   roofline   of the headline kernel; cpu_baseline: the oracle on the host.
 """
 from __future__ import annotations
@@ -557,6 +559,57 @@ def bench_batch(comet, reps, n=1024):
     return out
 
 
+# Batch labels (one label in C, A and B): batched matrix products with one
+# tiles x entries launch, FP64.
+BATCH_LABEL_CASES = [
+    ("bij=bik*bkj", dict(b=64, i=512, j=512, k=512)),      # a few large entries
+    ("bij=bik*bkj", dict(b=4096, i=64, j=64, k=64)),       # many small entries
+    ("ibj=kbi*jbk", dict(b=32, i=384, j=384, k=384)),      # batch label inside every tensor
+]
+
+
+def bench_batch_labels(comet, reps=5):
+    """Contractions with a batch label (FP64), against torch.bmm on the same
+    data where the layout is a plain batched product; sampled outputs are
+    checked against the oracle in the CPU leg."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    g = torch.Generator(device=dev)
+    g.manual_seed(19)
+    rng = np.random.default_rng(19)
+    for n, (spec, ext) in enumerate(BATCH_LABEL_CASES):
+        c, a, b = split_spec(spec)
+        A = torch.rand(shape(a, ext), dtype=torch.float64, device=dev, generator=g) * 2 - 1
+        B = torch.rand(shape(b, ext), dtype=torch.float64, device=dev, generator=g) * 2 - 1
+        C = comet.contract(spec, A, B)
+        torch.cuda.synchronize()
+        pts = np.stack([rng.integers(0, e, 128) for e in shape(c, ext)], axis=1)
+        got = C[tuple(torch.from_numpy(pts[:, d]).to(dev) for d in range(len(c)))].cpu().numpy()
+        key = "%s %s" % (spec, ",".join("%s=%d" % kv for kv in ext.items()))
+        check_points(["batch_labels", key, "relerr_vs_oracle"], spec, A.cpu().numpy(), B.cpu().numpy(), pts, got,
+                     tol=1e-12)
+        comet.contract(spec, A, B, C)
+        ms = timed(lambda: comet.contract(spec, A, B, C), reps, stream)
+        flops = 2.0 * float(np.prod(list(ext.values())))
+        d = comet.Plan(spec, A, B, C).describe()
+        rec = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+               "frac_mfma_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["f64"], 4),
+               "tile": d["tile"], "relerr_vs_oracle": None}
+        if spec == "bij=bik*bkj":
+            R = torch.bmm(A, B)
+            rec["max_abs_diff_vs_torch_bmm"] = float((R - C).abs().max().item())
+            t = timed(lambda: torch.bmm(A, B, out=R), reps, stream)
+            rec["torch_bmm_ms"] = round(t, 4)
+            rec["torch_bmm_gflops"] = round(flops / (t * 1e-3) / 1e9, 1)
+            del R
+        out[key] = rec
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -564,6 +617,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--modes", default="all", help="comma list of compute modes for the headline, or all")
     ap.add_argument("--only-headline", action="store_true", help="skip the other workloads")
+    ap.add_argument("--sections", default="all",
+                    help="comma list of the other workloads to run (backward, triples, config1, permute, "
+                         "ttgt_study, chain, batch, batch_labels), or all")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MB (HBM counter calibration)")
@@ -634,13 +690,22 @@ def main():
         "modes": modes,
     }
     if not args.only_headline:
-        line["backward"] = bench_backward(comet, A, B, C0, reps=5)
-        line["triples"] = bench_triples(comet, reps=5)
-        line["config1"] = bench_config1(comet)
-        line["permute"] = bench_permute(comet, reps=5)
-        line["ttgt_study"] = bench_ttgt_study(comet)
-        line["chain"] = bench_chain(comet)
-        line["batch"] = bench_batch(comet, reps=3)
+        sections = {
+            "backward": lambda: bench_backward(comet, A, B, C0, reps=5),
+            "triples": lambda: bench_triples(comet, reps=5),
+            "config1": lambda: bench_config1(comet),
+            "permute": lambda: bench_permute(comet, reps=5),
+            "ttgt_study": lambda: bench_ttgt_study(comet),
+            "chain": lambda: bench_chain(comet),
+            "batch": lambda: bench_batch(comet, reps=3),
+            "batch_labels": lambda: bench_batch_labels(comet),
+        }
+        chosen = list(sections) if args.sections == "all" else args.sections.split(",")
+        for name in chosen:
+            if name not in sections:
+                print("unknown section %r" % name, file=sys.stderr)
+                sys.exit(2)
+            line[name] = sections[name]()
     if not args.no_cpu:
         # the CPU leg: oracle references for every recorded check, and the
         # oracle's own throughput

@@ -245,8 +245,10 @@ comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dty
 /*
  * Multi-operand contraction chains (Section 5: ta.mult, ta.set; Section 6,
  * "Multi-Operand Expression").  spec "C=A1*A2*...*An", 2 <= n <= 8, every
- * label in exactly two of the tensors; extents one per distinct label, in
- * order of first appearance scanning C then A1..An.
+ * label in at least two of the tensors (a label in more than two is a batch
+ * label of the steps that meet it while another tensor still holds it);
+ * extents one per distinct label, in order of first appearance scanning C
+ * then A1..An.
  *
  * comet_chain_plan (host only, no device needed) chooses the grouping with
  * the fewest algorithmic operations (a search over every binary tree) and

@@ -61,13 +61,12 @@ Status chain_plan(const char *spec, const int64_t *extents, ChainPlan &plan) {
   for (const std::string &t : parts)
     for (char ch : t)
       if (std::find(plan.labels.begin(), plan.labels.end(), ch) == plan.labels.end()) plan.labels.push_back(ch);
+  // a label in more than two tensors becomes a batch label of the steps
+  // whose operands both hold it while a third tensor still needs it
   for (char ch : plan.labels) {
     int cnt = 0;
     for (const std::string &t : parts) cnt += t.find(ch) != std::string::npos;
-    if (cnt > 2)
-      return Status::error(COMET_ERR_UNSUPPORTED,
-                           std::string("label '") + ch + "' is in more than two tensors (not supported)");
-    if (cnt != 2) return Status::error(COMET_ERR_INVALID_SPEC, std::string("label '") + ch + "' appears once");
+    if (cnt < 2) return Status::error(COMET_ERR_INVALID_SPEC, std::string("label '") + ch + "' appears once");
   }
   if (!plan.labels.empty() && !extents) return Status::error(COMET_ERR_NULL_POINTER, "extents is NULL");
   for (size_t i = 0; i < plan.labels.size(); ++i) {

@@ -33,9 +33,9 @@ struct ChainPlan {
   double natural_flops = 0.0;            // left to right: ((A1 A2) A3) ...
 };
 
-// Parse "C=A1*A2*...*An" (2 <= n <= kChainMaxOperands; every label in exactly
-// two of the tensors) with one extent per distinct label, in order of first
-// appearance scanning C then the operands, and choose the order.
+// Parse "C=A1*A2*...*An" (2 <= n <= kChainMaxOperands; every label in at
+// least two of the tensors) with one extent per distinct label, in order of
+// first appearance scanning C then the operands, and choose the order.
 Status chain_plan(const char *spec, const int64_t *extents, ChainPlan &plan);
 
 std::string chain_json(const ChainPlan &plan);

@@ -39,6 +39,9 @@ CASES = [
     ("ai=cdmn*inad*mc", dict(a=12, i=10, c=3, d=11, m=9, n=7)),
     ("ij=ik*kl*lm*mj", dict(i=40, k=5, l=33, m=6, j=29)),
     ("abij=mnef*am*fn*ebij", dict(a=10, b=9, i=5, j=6, m=4, n=5, e=11, f=7)),
+    # labels in more than two tensors
+    ("bij=bik*bkl*blj", dict(b=5, i=30, k=4, l=50, j=3)),
+    ("aij=aik*kl*alj*ij", dict(a=7, i=9, k=11, l=13, j=5)),
 ]
 
 
