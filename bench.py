@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the schedule and kernel version recorded, null otherwise.
 HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512}, "kernel_version": "k5",
                     "bytes": 883231437}
-KERNEL_VERSION = "k5"
+KERNEL_VERSION = "k6"
 
 
 def headline_kernels(d):

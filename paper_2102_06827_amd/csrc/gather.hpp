@@ -357,47 +357,84 @@ __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &
   }
 }
 
-// C = alpha * acc + beta * C for the tile at (m0, n0), through the C tables,
-// in double for double storage or double accumulation, in float otherwise.
-template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
-__device__ __forceinline__ void gett_store(const WaveTile<Tc, BM, BN, WGM, WGN> &w, Tin *__restrict__ C,
-                                           const GettTables &t, int64_t M, int64_t N, double alpha, double beta,
-                                           int64_t m0, int64_t n0) {
-  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
-  typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
-  const Te al = Te(alpha), be = Te(beta);
-  const bool read_c = beta != 0.0;
-  glb_t<Tin> *const gC = to_glb(C);
-  const glb_t<const int64_t> *const offCm = to_glb(t.offCm);
-  const glb_t<const int64_t> *const offCn = to_glb(t.offCn);
-#pragma unroll
-  for (int j = 0; j < WT::FN; ++j) {
-    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
-    if (n >= N) continue;
-    const int64_t cn = offCn[n];
-#pragma unroll
-    for (int i = 0; i < WT::FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm0 + i * 16 + acc_row<Tc>(lane, r);
-        if (m >= M) continue;
-        const int64_t addr = offCm[m] + cn;
-        Te v = al * Te(w.acc[i][j][r]);
-        if (read_c) v = v + be * Te(gC[addr]);
-        gC[addr] = Tin(v);
-      }
-    }
-  }
-}
-
-// gett_store with the tile's C offsets read from LDS: cm[r] = offCm[m0 + r],
-// cn[c] = offCn[n0 + c] (entries past M or N are never read).
+// Epilogue of one tile from its C offsets in LDS: cm[r] = offCm[m0 + r],
+// cn[c] = offCn[n0 + c], entries past M or N holding the last row's or
+// column's offset (their writes are masked).  C[cm + cn] = alpha * acc +
+// beta * C for this thread's accumulator elements, in groups of four.  On
+// CDNA loads and stores share one in-order completion counter, so a load
+// placed after a store cannot be waited for without waiting for that store
+// too: the offsets come from LDS (a counter of their own), and with
+// beta != 0 the C values of the next group are requested before the current
+// group is stored, so that every wait is for loads issued ahead of the
+// stores still in flight.
 template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
 __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM, WGN> &w, Tin *__restrict__ C,
                                                   const lds_t<int64_t> *cm, const lds_t<int64_t> *cn, int64_t M,
                                                   int64_t N, double alpha, double beta, int64_t m0, int64_t n0) {
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
+  constexpr int G = WT::FN * WT::FM;   // groups of four elements: (j, i)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
+  const Te al = Te(alpha), be = Te(beta);
+  glb_t<Tin> *const gC = to_glb(C);
+  auto ml = [&](int i, int r) { return wm0 + i * 16 + acc_row<Tc>(lane, r); };
+  auto nl = [&](int j) { return wn0 + j * 16 + (lane & 15); };
+  auto addr = [&](int i, int r, int j) { return int64_t(cm[ml(i, r)]) + int64_t(cn[nl(j)]); };
+  auto inside = [&](int i, int r, int j) { return m0 + ml(i, r) < M && n0 + nl(j) < N; };
+  if (beta == 0.0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int j = g / WT::FM, i = g % WT::FM;
+      // the group's offsets first (in-bounds reads), then the masked stores
+      int64_t a[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = addr(i, r, j);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (inside(i, r, j)) gC[a[r]] = Tin(al * Te(w.acc[i][j][r]));
+    }
+    return;
+  }
+  // the look-ahead costs registers; tiles whose accumulators already take
+  // more than 64 VGPRs load and store one group at a time
+  constexpr bool ahead = WT::FM * WT::FN * 4 * int(sizeof(Tc)) <= 64 * 4;
+  Tin cv[2][4];
+  if (ahead) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cv[0][r] = gC[addr(0, r, 0)];
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int j = g / WT::FM, i = g % WT::FM;
+    __builtin_amdgcn_sched_barrier(0);
+    if (ahead && g + 1 < G) {
+      const int j1 = (g + 1) / WT::FM, i1 = (g + 1) % WT::FM;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cv[(g + 1) & 1][r] = gC[addr(i1, r, j1)];
+    }
+    if (!ahead) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cv[g & 1][r] = gC[addr(i, r, j)];
+    }
+    int64_t a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = addr(i, r, j);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (inside(i, r, j)) gC[a[r]] = Tin(al * Te(w.acc[i][j][r]) + be * Te(cv[g & 1][r]));
+  }
+}
+
+// The same result one element at a time (offsets from LDS, each C value
+// read just before its store).  The persistent kernel uses this form: there
+// the grouped form above, whose code sits inside the kernel's tile loop, made
+// the whole loop slower (measured on a K = 32 contraction).
+template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gett_store_staged_serial(const WaveTile<Tc, BM, BN, WGM, WGN> &w,
+                                                         Tin *__restrict__ C, const lds_t<int64_t> *cm,
+                                                         const lds_t<int64_t> *cn, int64_t M, int64_t N, double alpha,
+                                                         double beta, int64_t m0, int64_t n0) {
   typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
   typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -425,6 +462,31 @@ __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM
   }
 }
 
+// C = alpha * acc + beta * C for the tile at (m0, n0) through the C tables,
+// in double for double storage or double accumulation, in float otherwise.
+// The tile's C offsets are first staged in `smem` (the tile's LDS, free once
+// the main loop has passed its last barrier); the caller must pass a barrier
+// before it writes smem again.
+template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
+__device__ __forceinline__ void gett_store(const WaveTile<Tc, BM, BN, WGM, WGN> &w, Tin *__restrict__ C,
+                                           const GettTables &t, int64_t M, int64_t N, double alpha, double beta,
+                                           int64_t m0, int64_t n0, Tc *smem) {
+  constexpr int NT = 64 * WGM * WGN;
+  lds_t<int64_t> *const tab = to_lds(reinterpret_cast<int64_t *>(smem));
+  const glb_t<const int64_t> *const offCm = to_glb(t.offCm);
+  const glb_t<const int64_t> *const offCn = to_glb(t.offCn);
+  for (int x = threadIdx.x; x < BM + BN; x += NT) {
+    int64_t v;
+    if (x < BM)
+      v = offCm[m0 + x < M ? m0 + x : M - 1];
+    else
+      v = offCn[n0 + (x - BM) < N ? n0 + (x - BM) : N - 1];
+    tab[x] = v;
+  }
+  __syncthreads();
+  gett_store_staged<Tin, Tc, BM, BN, WGM, WGN>(w, C, tab, tab + BM, M, N, alpha, beta, m0, n0);
+}
+
 // C = alpha * v + beta * C for accumulator element (i, j) of this thread
 // only (the same outputs gett_store writes from w.acc[i][j]).
 template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
@@ -441,15 +503,19 @@ __device__ __forceinline__ void gett_store_fragment(const typename AccT<Tc>::typ
   const int64_t cn = to_glb(t.offCn)[n];
   const glb_t<const int64_t> *const offCm = to_glb(t.offCm);
   const Te al = Te(alpha), be = Te(beta);
+  // all offsets, then all C values, then the stores (see gett_epilogue)
+  int64_t addr[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int64_t m = m0 + wm0 + i * 16 + acc_row<Tc>(lane, r);
-    if (m >= M) continue;
-    const int64_t addr = offCm[m] + cn;
-    Te x = al * Te(v[r]);
-    if (beta != 0.0) x = x + be * Te(gC[addr]);
-    gC[addr] = Tin(x);
+    addr[r] = offCm[m < M ? m : M - 1] + cn;
   }
+  Te x[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) x[r] = beta != 0.0 ? be * Te(gC[addr[r]]) : Te(0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (m0 + wm0 + i * 16 + acc_row<Tc>(lane, r) < M) gC[addr[r]] = Tin(al * Te(v[r]) + x[r]);
 }
 
 // A partial sum of one tile in workspace: accumulator element (i, j) of
@@ -471,10 +537,12 @@ template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, i
 __device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C,
                                           const GettTables &t, int64_t M, int64_t N, int64_t K, double alpha,
                                           double beta, int64_t m0, int64_t n0, Tc *smem) {
+  static_assert(8 * (BM + BN) <= int(sizeof(Tc)) * gett_lds_elems<Tin, Tc, BM, BN, BK, 64 * WGM * WGN, LA, LB, VA, VB>(),
+                "the tile's C offsets fit in its LDS");
   WaveTile<Tc, BM, BN, WGM, WGN> w;
   gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(w, A, B, t, M, N, K, m0, n0, 0,
                                                                  (K + BK - 1) / BK, smem);
-  gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, m0, n0);
+  gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, m0, n0, smem);
 }
 
 

@@ -40,18 +40,19 @@ using namespace gather;
 // per SIMD to stay busy across the K-step barriers.
 struct TileShape {
   int bm, bn, bk, wgm, wgn, wpe;
+  int swpe;   // the same for the stream-K and persistent kernels
 };
 constexpr TileShape kTiles[] = {
-    {128, 128, 16, 2, 2, 1},   // 0: large problems
-    {64, 64, 16, 2, 2, 1},     // 1: small problems; also every element-load variant
-    {128, 128, 32, 2, 2, 1},   // 2: longer K step (fewer barriers per flop)
-    {128, 128, 16, 4, 2, 1},   // 3: 8 waves; two workgroups per CU
-    {256, 128, 16, 4, 2, 1},   // 4: 8 waves, 64 x 64 per wave
-    {128, 64, 16, 2, 2, 1},    // 5
-    {64, 128, 16, 2, 2, 1},    // 6
-    {96, 96, 16, 2, 2, 1},     // 7: FP64 only; 3072^2 outputs -> 4 tiles per CU
-    {128, 96, 32, 4, 2, 1},    // 8: FP64 only; 3072^2 outputs -> 3 tiles per CU
-    {192, 96, 32, 4, 2, 1},    // 9: FP64 only; 3072^2 outputs -> 2 tiles per CU
+    {128, 128, 16, 2, 2, 1, 1},   // 0: large problems
+    {64, 64, 16, 2, 2, 1, 3},     // 1: small problems; also every element-load variant
+    {128, 128, 32, 2, 2, 1, 1},   // 2: longer K step (fewer barriers per flop)
+    {128, 128, 16, 4, 2, 4, 1},   // 3: 8 waves; two workgroups per CU (128 VGPRs)
+    {256, 128, 16, 4, 2, 1, 1},   // 4: 8 waves, 64 x 64 per wave
+    {128, 64, 16, 2, 2, 1, 2},    // 5
+    {64, 128, 16, 2, 2, 1, 2},    // 6
+    {96, 96, 16, 2, 2, 1, 2},     // 7: FP64 only; 3072^2 outputs -> 4 tiles per CU
+    {128, 96, 32, 4, 2, 1, 1},    // 8: FP64 only; 3072^2 outputs -> 3 tiles per CU
+    {192, 96, 32, 4, 2, 1, 1},    // 9: FP64 only; 3072^2 outputs -> 2 tiles per CU
 };
 constexpr int kNumTiles = int(sizeof(kTiles) / sizeof(kTiles[0]));
 
@@ -119,7 +120,7 @@ constexpr bool batch_tile(int tile) { return tile == 1 || tile == 3; }
 // A separate kernel from the whole-tile one so that the latter keeps its
 // register budget (and its occupancy).
 template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
-__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett_sk_kernel(
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].swpe) void gett_sk_kernel(
     const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
     int64_t K, double alpha, double beta, int tilesM, int tilesN, StreamK sk) {
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
@@ -144,7 +145,8 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
     gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(w, A, B, t, M, N, K, int64_t(tm) * BM,
                                                                    int64_t(tn) * BN, ks, ke, smem);
     if (ks == 0 && ke == nk) {
-      gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, int64_t(tm) * BM, int64_t(tn) * BN);
+      gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, int64_t(tm) * BM, int64_t(tn) * BN, smem);
+      __syncthreads();   // the C offsets in smem are read before the next piece's loads overwrite them
     } else {
       const int slot = 2 * s + (tt == a / nk ? 0 : 1);
       gett_store_partial<Tc, BM, BN, WGM, WGN>(w, ws + slot * kSlot);
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett
 // two tiles ahead and its C offsets one tile ahead (each double-buffered by
 // tile parity), so that no table read sits on the critical path.
 template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
-__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_persistent_kernel(
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].swpe) void gett_persistent_kernel(
     const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
     int64_t K, double alpha, double beta, int tilesM, int tilesN) {
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
     if (last) {
       origin(j, &m0, &n0);
       const lds_t<int64_t> *ct = ctab + (j & 1) * (BM + BN);
-      gett_store_staged<Tin, Tc, BM, BN, WGM, WGN>(w, C, ct, ct + BM, M, N, alpha, beta, m0, n0);
+      gett_store_staged_serial<Tin, Tc, BM, BN, WGM, WGN>(w, C, ct, ct + BM, M, N, alpha, beta, m0, n0);
 #pragma unroll
       for (int i = 0; i < WT::FM; ++i)
 #pragma unroll
