@@ -98,28 +98,14 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
     lb.template store_split3<F3_LDK>(sB);
     __syncthreads();
   }
-  const float al = float(alpha), be = float(beta);
-  const bool read_c = beta != 0.0;
-  glb_t<float> *const gC = to_glb(C);
-  const glb_t<const int64_t> *const offCm = to_glb(t.offCm);
-  const glb_t<const int64_t> *const offCn = to_glb(t.offCn);
+  // the epilogue of the gather kernels (C offsets staged in LDS, which the
+  // loop above no longer reads)
+  WaveTile<float, TB, TB, 2, 2> w;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
-    if (n >= N) continue;
-    const int64_t cn = offCn[n];
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
-        if (m >= M) continue;
-        const int64_t addr = offCm[m] + cn;
-        float v = al * acc[i][j][r];
-        if (read_c) v = v + be * gC[addr];
-        gC[addr] = v;
-      }
-  }
+    for (int j = 0; j < 2; ++j) w.acc[i][j] = acc[i][j];
+  gett_store<float, float, TB, TB, 2, 2>(w, C, t, M, N, alpha, beta, m0, n0, reinterpret_cast<float *>(smem));
 }
 
 template <int LA, int LB, bool V>

@@ -281,6 +281,81 @@ constexpr int GNT = 64 * GWM * GWN;
 // then hit 64 distinct banks.
 __device__ __forceinline__ int sw(int r, int c) { return r * GBK + ((c ^ ((r >> 2) & 3)) << 3); }
 
+// Epilogue of the slice-pair products: C = alpha * 2^(eA[m] + eB[n]) * val +
+// beta * C for the thread's accumulator elements (row 4 * (lane / 16) + r of
+// each 16 x 16 block, the layout of the 16-bit and 8-bit MFMA outputs), val(i,
+// j, r) the element's unscaled sum.  The tile's C offsets and exponents are
+// first staged in LDS (`smem`: free once the main loop has passed its last
+// barrier), so that no global load of the epilogue follows a store: loads and
+// stores share one in-order completion counter on CDNA.  With beta != 0 the C
+// values of the next group of four elements are requested before the current
+// group is stored.
+template <typename Tout, int BM, int BN, int FM, int FN, int NTH, typename ValF>
+__device__ __forceinline__ void split_store(Tout *__restrict__ C, const int64_t *__restrict__ offCm,
+                                            const int64_t *__restrict__ offCn, const int *__restrict__ eA,
+                                            const int *__restrict__ eB, int64_t M, int64_t N, double alpha,
+                                            double beta, int64_t m0, int64_t n0, int wm0, int wn0, void *smem,
+                                            ValF val) {
+  typedef typename std::conditional<sizeof(Tout) == 8, double, float>::type Te;
+  lds_t<int64_t> *const toff = to_lds(static_cast<int64_t *>(smem));
+  lds_t<int> *const texp = to_lds(reinterpret_cast<int *>(static_cast<int64_t *>(smem) + BM + BN));
+  for (int x = threadIdx.x; x < BM + BN; x += NTH) {
+    if (x < BM) {
+      const int64_t m = m0 + x < M ? m0 + x : M - 1;
+      toff[x] = offCm[m];
+      texp[x] = eA[m];
+    } else {
+      const int64_t n = n0 + (x - BM) < N ? n0 + (x - BM) : N - 1;
+      toff[x] = offCn[n];
+      texp[x] = eB[n];
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  glb_t<Tout> *const gC = to_glb(C);
+  constexpr int G = FN * FM;
+  auto ml = [&](int i, int r) { return wm0 + i * 16 + 4 * (lane >> 4) + r; };
+  auto nl = [&](int j) { return wn0 + j * 16 + (lane & 15); };
+  auto inside = [&](int i, int r, int j) { return m0 + ml(i, r) < M && n0 + nl(j) < N; };
+  auto value = [&](int i, int j, int r) {
+    const int em = texp[ml(i, r)], en = texp[BM + nl(j)];
+    const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(val(i, j, r), em + en);
+    return Te(alpha * prod);
+  };
+  if (beta == 0.0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int j = g / FM, i = g % FM;
+      int64_t a[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = toff[ml(i, r)] + toff[BM + nl(j)];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (inside(i, r, j)) gC[a[r]] = Tout(value(i, j, r));
+    }
+    return;
+  }
+  Tout cv[2][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) cv[0][r] = gC[toff[ml(0, r)] + toff[BM + nl(0)]];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int j = g / FM, i = g % FM;
+    __builtin_amdgcn_sched_barrier(0);
+    if (g + 1 < G) {
+      const int j1 = (g + 1) / FM, i1 = (g + 1) % FM;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cv[(g + 1) & 1][r] = gC[toff[ml(i1, r)] + toff[BM + nl(j1)]];
+    }
+    int64_t a[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = toff[ml(i, r)] + toff[BM + nl(j)];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (inside(i, r, j)) gC[a[r]] = Tout(value(i, j, r) + Te(beta) * Te(cv[g & 1][r]));
+  }
+}
+
 template <typename ST, typename Tout, int MODE, int S>
 __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ As, const ST *__restrict__ Bs,
                                                           const int *__restrict__ eA, const int *__restrict__ eB,
@@ -421,29 +496,9 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
   fold();
 
   // epilogue: C = alpha * 2^(eA + eB) * acc + beta * C
-  typedef typename std::conditional<sizeof(Tout) == 8, double, float>::type Te;
-  const bool read_c = beta != 0.0;
-#pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
-    if (n >= N) continue;
-    const int64_t cn = offCn[n];
-    const int en = eB[n];
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
-        if (m >= M) continue;
-        const int em = eA[m];
-        const int64_t addr = offCm[m] + cn;
-        const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(acc64[i][j][r], em + en);
-        Te v = Te(alpha * prod);
-        if (read_c) v = v + Te(beta) * Te(C[addr]);
-        C[addr] = Tout(v);
-      }
-    }
-  }
+  static_assert((GBM + GBN) * 12 <= NBUF * STAGE * int(sizeof(ST)), "epilogue tables fit in LDS");
+  split_store<Tout, GBM, GBN, FM, FN, GNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem,
+                                          [&](int i, int j, int r) { return acc64[i][j][r]; });
 }
 
 // ------------------------------------------ large-tile slice-pair GEMM --
@@ -581,33 +636,15 @@ __global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restric
   }
 
   // epilogue: C = alpha * 2^(eA + eB) * sum_a scale(a) * acc[a] + beta * C
-  typedef typename std::conditional<sizeof(Tout) == 8, double, float>::type Te;
-  const bool read_c = beta != 0.0;
-  glb_t<Tout> *const gC = to_glb(C);
+  static_assert((XBM + XBN) * 12 <= 2 * STAGE * int(sizeof(ST)), "epilogue tables fit in LDS");
+  split_store<Tout, XBM, XBN, FM, FN, XNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem_,
+                                          [&](int i, int j, int r) {
+                                            double sum = 0.0;
 #pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
-    if (n >= N) continue;
-    const int64_t cn = offCn[n];
-    const int en = eB[n];
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
-        if (m >= M) continue;
-        const int em = eA[m];
-        double sum = 0.0;
-#pragma unroll
-        for (int a = 0; a < PP::NACC; ++a) sum += double(acc[a][i][j][r]) * PP::scale(a);
-        const int64_t addr = offCm[m] + cn;
-        const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(sum, em + en);
-        Te v = Te(alpha * prod);
-        if (read_c) v = v + Te(beta) * Te(gC[addr]);
-        gC[addr] = Tout(v);
-      }
-    }
-  }
+                                            for (int a = 0; a < PP::NACC; ++a)
+                                              sum += double(acc[a][i][j][r]) * PP::scale(a);
+                                            return sum;
+                                          });
 }
 
 // ------------------------------------------------------ INT8 slice-pair GEMM --
@@ -737,32 +774,15 @@ __global__ __launch_bounds__(GNT) void split_gemm_i8_kernel(const signed char *_
     }
   }
 
-  typedef typename std::conditional<sizeof(Tout) == 8, double, float>::type Te;
-  const bool read_c = beta != 0.0;
+  static_assert((GBM + GBN) * 12 <= NBUF * STAGE, "epilogue tables fit in LDS");
+  split_store<Tout, GBM, GBN, FM, FN, GNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem,
+                                          [&](int i, int j, int r) {
+                                            double sum = 0.0;
 #pragma unroll
-  for (int j = 0; j < FN; ++j) {
-    const int64_t n = n0 + wn0 + j * 16 + (lane & 15);
-    if (n >= N) continue;
-    const int64_t cn = offCn[n];
-    const int en = eB[n];
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm0 + i * 16 + 4 * (lane >> 4) + r;
-        if (m >= M) continue;
-        const int em = eA[m];
-        const int64_t addr = offCm[m] + cn;
-        double sum = 0.0;
-#pragma unroll
-        for (int d = S - 1; d >= 0; --d) sum += double(acc[d][i][j][r]) * ldexp(1.0, -7 * (d + 2));
-        const double prod = (em == kExpNone || en == kExpNone) ? 0.0 : ldexp(sum, em + en);
-        Te v = Te(alpha * prod);
-        if (read_c) v = v + Te(beta) * Te(C[addr]);
-        C[addr] = Tout(v);
-      }
-    }
-  }
+                                            for (int d = S - 1; d >= 0; --d)
+                                              sum += double(acc[d][i][j][r]) * ldexp(1.0, -7 * (d + 2));
+                                            return sum;
+                                          });
 }
 
 // ----------------------------------------------------------------- launch --
