@@ -146,27 +146,43 @@ __device__ __forceinline__ void row_offsets(int64_t *ro, const int64_t *__restri
   }
 }
 
-__global__ __launch_bounds__(256) void fill_int_kernel(int *__restrict__ p, int64_t n, int v) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = v;
-}
+// The two operands of one product, as the slicer kernels see them: rows R
+// (M or N) and summation K through the offset tables, tilesR slicer tiles of
+// rows, `part` the partial row maxima (ky ranges of the summation, pitch Rp),
+// `e` the final row exponents, `out` the slices (pitch Kp, Rp rows each).
+struct SliceOperand {
+  const void *base;
+  const int64_t *offR, *offK;
+  int64_t R;
+  int layout;
+  int tilesR;
+  int *part;
+  int *e;
+  void *out;
+  int64_t Rp;
+};
+struct SliceArgs {
+  SliceOperand op[2];
+  int64_t K, Kp;
+  int ky;
+};
 
-// e[r] = max over k of the binary exponent of the operand row r.  Block
-// (x, y) takes rows [64x, 64x + 64) and the y-th of gridDim.y equal ranges of
-// summation tiles; the maxima stay in registers over the range, so a row
-// receives one atomic update per block.
+// Partial row exponents: part[y][r] = max over the y-th of ky equal ranges of
+// summation tiles of the binary exponent of operand row r.  Block (x, y)
+// takes rows [64x', 64x' + 64) of operand 0 (x < tilesR of operand 0) or
+// operand 1, and summation range y; the maxima stay in registers over the
+// range, then in LDS, and one plain store per row and range leaves the block
+// (no initialisation and no global atomics).
 template <typename Tin, int LAYOUT>
-__global__ __launch_bounds__(PT) void split_exp_kernel(const Tin *__restrict__ base, const int64_t *__restrict__ offR,
-                                                       const int64_t *__restrict__ offK, int64_t R, int64_t K,
-                                                       int *__restrict__ e) {
-  __shared__ int emax[PR];
+__device__ __forceinline__ void exp_block(const SliceOperand &op, int rt, int64_t K, int ky, int *emax) {
   const int tid = threadIdx.x;
   if (tid < PR) emax[tid] = kExpNone;
-  const int64_t r0 = int64_t(blockIdx.x) * PR;
+  const Tin *__restrict__ base = static_cast<const Tin *>(op.base);
+  const int64_t r0 = int64_t(rt) * PR, R = op.R;
   const int64_t tilesK = (K + PK - 1) / PK;
-  const int64_t kt0 = tilesK * blockIdx.y / gridDim.y, kt1 = tilesK * (blockIdx.y + 1) / gridDim.y;
+  const int64_t kt0 = tilesK * blockIdx.y / ky, kt1 = tilesK * (blockIdx.y + 1) / ky;
   int64_t ro[PI];
-  row_offsets<LAYOUT>(ro, offR, r0, R);
+  row_offsets<LAYOUT>(ro, op.offR, r0, R);
   // LAYOUT 0: a thread's elements lie in PI rows; LAYOUT 1: in one row
   constexpr int NR = LAYOUT == 0 ? PI : 1;
   int mx[NR];
@@ -174,7 +190,7 @@ __global__ __launch_bounds__(PT) void split_exp_kernel(const Tin *__restrict__ b
   for (int q = 0; q < NR; ++q) mx[q] = kExpNone;
   for (int64_t kt = kt0; kt < kt1; ++kt) {
     double x[PI];
-    load_tile<Tin, LAYOUT>(x, base, ro, offK, r0, kt * PK, R, K);
+    load_tile<Tin, LAYOUT>(x, base, ro, op.offK, r0, kt * PK, R, K);
 #pragma unroll
     for (int q = 0; q < PI; ++q) {
       int ex = kExpNone;
@@ -190,30 +206,53 @@ __global__ __launch_bounds__(PT) void split_exp_kernel(const Tin *__restrict__ b
     if (mx[q] != kExpNone) atomicMax(&emax[rl], mx[q]);
   }
   __syncthreads();
-  if (tid < PR && r0 + tid < R && emax[tid] != kExpNone) atomicMax(&e[r0 + tid], emax[tid]);
+  if (tid < PR && r0 + tid < R) op.part[int64_t(blockIdx.y) * op.Rp + r0 + tid] = emax[tid];
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(PT) void split_exp_kernel(SliceArgs a) {
+  __shared__ int emax[PR];
+  const int w = int(blockIdx.x) < a.op[0].tilesR ? 0 : 1;
+  const int rt = int(blockIdx.x) - (w ? a.op[0].tilesR : 0);
+  if (a.op[w].layout == 0)
+    exp_block<Tin, 0>(a.op[w], rt, a.K, a.ky, emax);
+  else
+    exp_block<Tin, 1>(a.op[w], rt, a.K, a.ky, emax);
 }
 
 // Cut a PR x PK tile into S slices, written K-contiguous: out[p][r][k]
 // (pitch Kp, Rp rows per slice).  Thread t writes 16 consecutive k of row
 // t/4, so the four threads of a row write one 128-byte line per 16-bit slice.
+// The block first reduces its rows' partial exponents; blocks of the first
+// summation tile also store them as the rows' final exponents, which the
+// product's epilogue reads.
 template <typename Tin, typename ST, int LAYOUT, int MODE, int S>
-__global__ __launch_bounds__(PT) void split_pack_kernel(const Tin *__restrict__ base,
-                                                        const int64_t *__restrict__ offR,
-                                                        const int64_t *__restrict__ offK, int64_t R, int64_t K,
-                                                        int64_t tilesR, const int *__restrict__ e,
-                                                        ST *__restrict__ out, int64_t Rp, int64_t Kp) {
-  __shared__ double t[PR][PK + 1];
-  const int64_t r0 = (int64_t(blockIdx.x) % tilesR) * PR, k0 = (int64_t(blockIdx.x) / tilesR) * PK;
+__device__ __forceinline__ void pack_block(const SliceOperand &op, int64_t bid, int64_t K, int64_t Kp, int ky,
+                                           double (*t)[PK + 1], int *erow) {
+  const Tin *__restrict__ base = static_cast<const Tin *>(op.base);
+  ST *__restrict__ out = static_cast<ST *>(op.out);
+  const int64_t R = op.R, Rp = op.Rp;
+  const int64_t r0 = (bid % op.tilesR) * PR, k0 = (bid / op.tilesR) * PK;
+  const int tid = threadIdx.x;
+  if (tid < PR) {
+    int ex = kExpNone;
+    if (r0 + tid < R)
+      for (int y = 0; y < ky; ++y) {
+        const int v = op.part[int64_t(y) * Rp + r0 + tid];
+        ex = v > ex ? v : ex;
+      }
+    erow[tid] = ex;
+    if (k0 == 0 && r0 + tid < R) op.e[r0 + tid] = ex;
+  }
   {
     int64_t ro[PI];
-    row_offsets<LAYOUT>(ro, offR, r0, R);
-    gather_tile<Tin, LAYOUT>(t, base, ro, offK, r0, k0, R, K);
+    row_offsets<LAYOUT>(ro, op.offR, r0, R);
+    gather_tile<Tin, LAYOUT>(t, base, ro, op.offK, r0, k0, R, K);
   }
   __syncthreads();
-  const int tid = threadIdx.x;
   const int rl = tid / 4;
   const int64_t r = r0 + rl;
-  const int ex = r < R ? e[r] : kExpNone;
+  const int ex = erow[rl];
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     const int kc = (tid % 4) * 16 + half * 8;
@@ -254,6 +293,19 @@ __global__ __launch_bounds__(PT) void split_pack_kernel(const Tin *__restrict__ 
     for (int p = 0; p < S; ++p)
       *reinterpret_cast<typename Vec8<ST>::type *>(out + (int64_t(p) * Rp + r) * Kp + k0 + kc) = sl[p];
   }
+}
+
+template <typename Tin, typename ST, int MODE, int S>
+__global__ __launch_bounds__(PT) void split_pack_kernel(SliceArgs a) {
+  __shared__ double t[PR][PK + 1];
+  __shared__ int erow[PR];
+  const int64_t nA = int64_t(a.op[0].tilesR) * (a.Kp / PK);
+  const int w = int64_t(blockIdx.x) < nA ? 0 : 1;
+  const int64_t bid = int64_t(blockIdx.x) - (w ? nA : 0);
+  if (a.op[w].layout == 0)
+    pack_block<Tin, ST, 0, MODE, S>(a.op[w], bid, a.K, a.Kp, a.ky, t, erow);
+  else
+    pack_block<Tin, ST, 1, MODE, S>(a.op[w], bid, a.K, a.Kp, a.ky, t, erow);
 }
 
 // ------------------------------------------------------- slice-pair GEMM --
@@ -790,36 +842,6 @@ __global__ __launch_bounds__(GNT) void split_gemm_i8_kernel(const signed char *_
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 template <typename Tin, typename ST, int MODE, int S>
-hipError_t pack_operand(const void *base, const int64_t *offR, const int64_t *offK, int64_t R, int64_t K, int layout,
-                        const int *e, ST *out, int64_t Rp, int64_t Kp, hipStream_t s) {
-  const int64_t tilesR = Rp / PR, tilesK = Kp / PK;
-  const dim3 grid(unsigned(tilesR * tilesK));
-  const Tin *b = static_cast<const Tin *>(base);
-  if (layout == 0)
-    hipLaunchKernelGGL((split_pack_kernel<Tin, ST, 0, MODE, S>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e,
-                       out, Rp, Kp);
-  else
-    hipLaunchKernelGGL((split_pack_kernel<Tin, ST, 1, MODE, S>), grid, dim3(PT), 0, s, b, offR, offK, R, K, tilesR, e,
-                       out, Rp, Kp);
-  return hipGetLastError();
-}
-
-template <typename Tin>
-hipError_t exp_operand(const void *base, const int64_t *offR, const int64_t *offK, int64_t R, int64_t K, int layout,
-                       int *e, hipStream_t s) {
-  const int64_t tilesR = (R + PR - 1) / PR, tilesK = (K + PK - 1) / PK;
-  // split the summation range so that about 2048 blocks run
-  const int64_t ky = std::max<int64_t>(1, std::min<int64_t>(tilesK, (2048 + tilesR - 1) / tilesR));
-  const dim3 grid = dim3(unsigned(tilesR), unsigned(ky));
-  const Tin *b = static_cast<const Tin *>(base);
-  if (layout == 0)
-    hipLaunchKernelGGL((split_exp_kernel<Tin, 0>), grid, dim3(PT), 0, s, b, offR, offK, R, K, e);
-  else
-    hipLaunchKernelGGL((split_exp_kernel<Tin, 1>), grid, dim3(PT), 0, s, b, offR, offK, R, K, e);
-  return hipGetLastError();
-}
-
-template <typename Tin, typename ST, int MODE, int S>
 hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
                      const void *B, double beta, void *C, void *ws, hipStream_t s) {
   char *w = static_cast<char *>(ws);
@@ -827,18 +849,22 @@ hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &
   ST *Bs = reinterpret_cast<ST *>(w + sp.offB);
   int *eA = reinterpret_cast<int *>(w + sp.offEA);
   int *eB = reinterpret_cast<int *>(w + sp.offEB);
-  hipLaunchKernelGGL(fill_int_kernel, dim3(64), dim3(256), 0, s, eA, sp.Mp, kExpNone);
-  hipLaunchKernelGGL(fill_int_kernel, dim3(64), dim3(256), 0, s, eB, sp.Np, kExpNone);
+  // both operands in one exponent launch and one pack launch
+  SliceArgs a{};
+  a.op[0] = SliceOperand{A, t.offAm, t.offAk, an.m, an.layoutA, int(sp.Mp / PR), reinterpret_cast<int *>(w + sp.offPA),
+                         eA, As, sp.Mp};
+  a.op[1] = SliceOperand{B, t.offBn, t.offBk, an.n, an.layoutB, int(sp.Np / PR), reinterpret_cast<int *>(w + sp.offPB),
+                         eB, Bs, sp.Np};
+  a.K = an.k;
+  a.Kp = sp.Kp;
+  a.ky = sp.ky;
+  hipLaunchKernelGGL((split_exp_kernel<Tin>), dim3(unsigned(a.op[0].tilesR + a.op[1].tilesR), unsigned(sp.ky)),
+                     dim3(PT), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if ((err = exp_operand<Tin>(A, t.offAm, t.offAk, an.m, an.k, an.layoutA, eA, s)) != hipSuccess) return err;
-  if ((err = exp_operand<Tin>(B, t.offBn, t.offBk, an.n, an.k, an.layoutB, eB, s)) != hipSuccess) return err;
-  if ((err = pack_operand<Tin, ST, MODE, S>(A, t.offAm, t.offAk, an.m, an.k, an.layoutA, eA, As, sp.Mp, sp.Kp, s)) !=
-      hipSuccess)
-    return err;
-  if ((err = pack_operand<Tin, ST, MODE, S>(B, t.offBn, t.offBk, an.n, an.k, an.layoutB, eB, Bs, sp.Np, sp.Kp, s)) !=
-      hipSuccess)
-    return err;
+  const int64_t packs = (int64_t(a.op[0].tilesR) + a.op[1].tilesR) * (sp.Kp / PK);
+  hipLaunchKernelGGL((split_pack_kernel<Tin, ST, MODE, S>), dim3(unsigned(packs)), dim3(PT), 0, s, a);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
   const int tilesM = int(sp.Mp / GBM), tilesN = int(sp.Np / GBN);
   if constexpr (MODE == 3) {
     // exact int32 diagonal sums over at most IKC indices per launch; later
@@ -917,8 +943,16 @@ Status split_prepare(const Analysis &an, SplitPlan &sp) {
   sp.Np = round_up(an.n, sp.tile == 1 ? XBN : GBN);
   sp.Kp = round_up(an.k, PK);   // whole slicer tiles (a multiple of GBK and IBK)
   const int64_t tiles = sp.tile == 1 ? (sp.Mp / XBM) * (sp.Np / XBN) : (sp.Mp / GBM) * (sp.Np / GBN);
-  if (tiles > INT_MAX || (sp.Mp / PR) * (sp.Kp / PK) > INT_MAX || (sp.Np / PR) * (sp.Kp / PK) > INT_MAX)
+  // one pack launch covers both operands' tiles; its grid must stay below
+  // 2^32 work-items
+  if (tiles > INT_MAX || ((sp.Mp + sp.Np) / PR) * (sp.Kp / PK) > int64_t(INT_MAX) / PT)
     return Status::error(COMET_ERR_UNSUPPORTED, "problem too large for the split path");
+  // exponent pass: about 2048 blocks over both operands' row tiles and ky
+  // ranges of the summation
+  {
+    const int64_t rows = sp.Mp / PR + sp.Np / PR, tilesK = sp.Kp / PK;
+    sp.ky = int(std::max<int64_t>(1, std::min<int64_t>({(2048 + rows - 1) / rows, tilesK, int64_t(64)})));
+  }
   const size_t es = sp.mode == 3 ? 1 : 2;
   size_t off = 0;
   sp.offA = off;
@@ -929,6 +963,10 @@ Status split_prepare(const Analysis &an, SplitPlan &sp) {
   off = align256(off + size_t(sp.Mp) * 4);
   sp.offEB = off;
   off = align256(off + size_t(sp.Np) * 4);
+  sp.offPA = off;
+  off = align256(off + size_t(sp.ky) * sp.Mp * 4);
+  sp.offPB = off;
+  off = align256(off + size_t(sp.ky) * sp.Np * 4);
   sp.ws_bytes = off;
   return Status{};
 }

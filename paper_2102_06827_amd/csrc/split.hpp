@@ -14,6 +14,8 @@ struct SplitPlan {
   int S = 5;                // slices per operand
   int64_t Mp = 0, Np = 0, Kp = 0;   // padded matrix sizes of the packed operands
   size_t offA = 0, offB = 0, offEA = 0, offEB = 0;   // workspace byte offsets
+  size_t offPA = 0, offPB = 0;                        // partial row exponents, ky per row
+  int ky = 1;                                         // summation ranges of the exponent pass
   size_t ws_bytes = 0;
   int tile = 0;
 };
