@@ -162,6 +162,7 @@ comet_status_t upload_tables(comet_plan_s *p) {
 constexpr double kThroughputF64[] = {28.4, 33.2, 28.6, 41.0, 38.6, 33.6, 32.7, 33.5, 34.4, 34.3};
 constexpr double kThroughputF32[] = {74.5, 64.9, 73.4, 75.8, 79.3, 69.8, 70.1};
 constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
+constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
 constexpr double kSkBytesPerUs = 4.0e6;  // partial-sum traffic rate (HBM, both directions)
 constexpr double kSkLaunchUs = 4.0;      // the two extra launches
@@ -468,7 +469,16 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   bool split = an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
                an.compute == COMET_COMPUTE_SPLIT_FP16X2 || an.compute == COMET_COMPUTE_SPLIT_INT8;
   // FP32 storage in BF16x3: split on the fly inside the gather kernel
-  p->fused3 = an.compute == COMET_COMPUTE_SPLIT_BF16X3 && an.dtype == COMET_F32;
+  // (small products; large ones slice into the workspace first and run the
+  // slice-pair product, whose 192 x 192 tile does more MFMA work per LDS byte:
+  // on MI355X the fused kernel wins up to about 1024^3 and loses 2.4x at the
+  // 3072^3 CCSD-like contraction; COMET_FUSED3=0/1 overrides)
+  p->fused3 = an.compute == COMET_COMPUTE_SPLIT_BF16X3 && an.dtype == COMET_F32 &&
+              double(an.m) * double(an.n) * double(an.k) * double(an.nb) < kFused3MaxMNK;
+  if (an.compute == COMET_COMPUTE_SPLIT_BF16X3 && an.dtype == COMET_F32) {
+    const char *env = std::getenv("COMET_FUSED3");
+    if (env && *env) p->fused3 = std::atoi(env) != 0;
+  }
   if (split && !p->fused3 && !an.empty_out && !an.empty_sum) {
     Status s2 = split_prepare(an, p->split);
     if (!s2.ok()) return fail(s2);
@@ -815,21 +825,13 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
   add(sC, rc);
   k += "|" + std::to_string(dtype) + "|" + std::to_string(compute) + "|" + std::to_string(dev) + "|" +
        std::to_string(g_split_slices) + "|" + std::to_string(g_int8_slices);
-  const char *env = std::getenv("COMET_FORCE_PATH");
-  k += "|";
-  if (env) k += env;
-  const char *ord = std::getenv("COMET_TTGT_ORDER");
-  k += "|";
-  if (ord) k += ord;
-  const char *tl = std::getenv("COMET_GETT_TILE");
-  k += "|";
-  if (tl) k += tl;
-  const char *skv = std::getenv("COMET_GETT_SK");
-  k += "|";
-  if (skv) k += skv;
-  const char *pv = std::getenv("COMET_GETT_PERSIST");
-  k += "|";
-  if (pv) k += pv;
+  // every planner override in the environment
+  for (const char *name : {"COMET_FORCE_PATH", "COMET_TTGT_ORDER", "COMET_GETT_TILE", "COMET_GETT_SK",
+                           "COMET_GETT_PERSIST", "COMET_SPLIT_TILE", "COMET_FUSED3"}) {
+    const char *v = std::getenv(name);
+    k += "|";
+    if (v) k += v;
+  }
   k += "|t" + std::to_string(tune_cache().mode());
   return k;
 }
