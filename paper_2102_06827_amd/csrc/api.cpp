@@ -200,12 +200,14 @@ int persistent_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
   return gett_occupancy(g);
 }
 
-// Short summations: a workgroup per tile spends most of its life on the
-// latency of its first loads and on draining its pipeline (about three
-// K steps' worth on MI355X), so with at most kPersistMaxSteps steps per tile
-// and at least two tiles per resident workgroup the persistent kernel, which
-// overlaps one tile's epilogue and the next tile's loads, takes over.
-constexpr int kPersistMaxSteps = 8;
+// Short summations: the persistent kernel overlaps one tile's epilogue with
+// the next tile's loads.  It beat a workgroup per tile while the epilogue
+// serialized its loads behind its stores; with the staged epilogue the
+// whole-tile kernel (two workgroups per CU) is as fast or faster on every
+// short summation measured on MI355X (K = 16 to 128; the K = 32 triples
+// contraction 0.328 -> 0.275 ms in FP64), so the persistent schedule is only
+// taken when COMET_GETT_PERSIST asks for it.
+constexpr int kPersistMaxSteps = 0;
 
 void persist_choice(const Analysis &an, int cus, bool vecA, bool vecB, Schedule &sc) {
   const char *env = std::getenv("COMET_GETT_PERSIST");

@@ -500,8 +500,13 @@ def test_persistent_schedule(tile, grid, dtype, spec, ext, monkeypatch):
     check(spec, ext, dtype, seed=980 + tile, alpha=-0.75, beta=0.5)
 
 
-def test_persistent_chosen_for_short_sums():
+def test_persistent_only_on_request(monkeypatch):
+    """The whole-tile kernel is the default for short summations too; the
+    persistent schedule runs when COMET_GETT_PERSIST asks for it."""
     A = torch.zeros((32, 32, 16, 16), dtype=torch.float64, device="cuda")
     B = torch.zeros((32, 32, 32, 16), dtype=torch.float64, device="cuda")
     d = comet.Plan("abcijk=daij*bcdk", A, B).describe()
-    assert d["persist"] > 0 and d["sk_tiles"] == 0
+    assert d["persist"] == 0 and d["sk_tiles"] == 0
+    monkeypatch.setenv("COMET_GETT_PERSIST", "256")
+    d = comet.Plan("abcijk=daij*bcdk", A, B).describe()
+    assert d["persist"] == 256
