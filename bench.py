@@ -619,7 +619,7 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="skip the other workloads")
     ap.add_argument("--sections", default="all",
                     help="comma list of the other workloads to run (backward, triples, config1, permute, "
-                         "ttgt_study, chain, batch, batch_labels), or all")
+                         "ttgt_study, chain, batch, batch_labels), all or none")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MB (HBM counter calibration)")
@@ -700,7 +700,8 @@ def main():
             "batch": lambda: bench_batch(comet, reps=3),
             "batch_labels": lambda: bench_batch_labels(comet),
         }
-        chosen = list(sections) if args.sections == "all" else args.sections.split(",")
+        chosen = (list(sections) if args.sections == "all" else
+                  [] if args.sections == "none" else args.sections.split(","))
         for name in chosen:
             if name not in sections:
                 print("unknown section %r" % name, file=sys.stderr)
