@@ -921,6 +921,7 @@ comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len) {
     js.pop_back();
     js += ",\"resident\":" + std::to_string(res);
     if (plan->split.ws_bytes > 0) js += ",\"split_tile\":" + std::to_string(plan->split.tile);
+    js += std::string(",\"fused3\":") + (plan->fused3 ? "true" : "false");
     js += "}";
   }
   std::strncpy(buf, js.c_str(), len - 1);

@@ -185,6 +185,7 @@ def test_split_large_tile_forced(spec, ext, mode, storage, monkeypatch):
     """The 192 x 192 slice-pair kernel on ragged problems (operands padded to
     multiples of 192): same bars, integer inputs bit for bit."""
     monkeypatch.setenv("COMET_SPLIT_TILE", "1")
+    monkeypatch.setenv("COMET_FUSED3", "0")   # FP32 BF16x3 through the slicer too
     tdt = torch.float64 if storage == "f64" else torch.float32
     cast = np.float64 if storage == "f64" else np.float32
     print_case("split large tile", spec, mode, storage)
@@ -204,3 +205,39 @@ def test_split_large_tile_is_chosen_for_large_products():
     B = torch.zeros((V, O, V, O), dtype=torch.float64, device="cuda")
     d = comet.Plan("abij=acik*bkcj", A, B, compute="split_bf16x3").describe()
     assert d.get("split_tile") == 1
+
+
+@pytest.mark.parametrize("fused", ["1", "0"])
+@pytest.mark.parametrize("spec,ext", CASES)
+def test_fp32_bf16x3_fused_and_sliced_paths(spec, ext, fused, monkeypatch):
+    """FP32 storage in BF16x3: the fused kernel (operands split in the loader)
+    and the slicer + slice-pair product, each against the oracle."""
+    monkeypatch.setenv("COMET_FUSED3", fused)
+    print_case("fp32 bf16x3", spec, "fused" if fused == "1" else "sliced")
+    A, B, C0 = inputs(spec, ext, 840, beta=True)
+    A32, B32, C32 = A.astype(np.float32), B.astype(np.float32), C0.astype(np.float32)
+    Ad, Bd = torch_dev(A32, torch.float32), torch_dev(B32, torch.float32)
+    assert comet.Plan(spec, Ad, Bd, compute="split_bf16x3").describe()["fused3"] is (fused == "1")
+    got = run(spec, A32, B32, C32, 1.5, -1.0, torch.float32, "split_bf16x3")
+    assert oracle.relerr(got, oracle.contract(spec, A32, B32, C32, alpha=1.5, beta=-1.0)) <= 1e-5
+
+
+def test_fp32_bf16x3_path_follows_the_product_size():
+    small = torch.zeros((256, 256), dtype=torch.float32, device="cuda")
+    assert comet.Plan("ij=ik*kj", small, small, compute="split_bf16x3").describe()["fused3"] is True
+    big_a = torch.zeros((1400, 1400), dtype=torch.float32, device="cuda")
+    d = comet.Plan("ij=ik*kj", big_a, big_a, compute="split_bf16x3").describe()
+    assert d["fused3"] is False and "split_tile" in d
+
+
+def test_fp32_bf16x3_sliced_path_at_size_sampled():
+    """Above the size threshold (1400^3 multiply-adds) on sampled outputs."""
+    n = 1400
+    A = synth.uniform(850, (n, n)).astype(np.float32)
+    B = synth.uniform(851, (n, n)).astype(np.float32)
+    print_case("fp32 bf16x3 sliced 1400^3")
+    got = run("ij=ik*kj", A, B, None, 1.0, 0.0, torch.float32, "split_bf16x3")
+    rng = np.random.default_rng(852)
+    pts = np.stack([rng.integers(0, n, 2000), rng.integers(0, n, 2000)], axis=1)
+    ref = oracle.contract_points("ij=ik*kj", A, B, pts)
+    assert oracle.relerr(got[tuple(pts.T)], ref) <= 1e-5
