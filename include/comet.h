@@ -219,7 +219,8 @@ comet_status_t comet_analyze(const char *spec, const int64_t *extents,
  * with FP32 storage (operands split into three bfloat16 slices inside the
  * loader).  Problems with an empty summation or alpha == 0 are scaled by
  * beta before the launch.  A problem with batch labels contributes one
- * problem per batch entry to the work list.  The workspace holds the work
+ * problem per batch entry to the work list (at most 2^22 problems and batch
+ * entries in all, COMET_ERR_UNSUPPORTED beyond).  The workspace holds the work
  * counter (256 bytes).
  * comet_batch_create plans every problem and uploads the work list and
  * offset tables (not capturable); comet_batch_execute is capturable.

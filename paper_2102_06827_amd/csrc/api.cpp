@@ -1230,7 +1230,8 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
   std::vector<int64_t> first(n + 1, 0);
   for (int i = 0; i < n; ++i) first[i + 1] = first[i] + (an[i].empty_out ? 1 : an[i].nb);
   const int64_t nd = first[n];
-  if (nd > INT32_MAX) return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 batch entries");
+  constexpr int64_t kMaxEntries = int64_t(1) << 22;   // descriptors held on the host and the device
+  if (nd > kMaxEntries) return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^22 problems and batch entries");
   std::vector<BatchDesc> descs(static_cast<size_t>(nd));
   std::vector<size_t> tab_off(n, 0);
   size_t bytes = align256(sizeof(BatchDesc) * std::max<int64_t>(nd, 1));

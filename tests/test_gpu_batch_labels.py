@@ -185,6 +185,25 @@ def test_batch_api_with_batch_labels():
         assert oracle.relerr(to_np(pr["C"]), ref) <= 1e-12
 
 
+def test_batch_labels_backward():
+    """dA and dB of a contraction with batch labels are contractions with
+    batch labels too (the same kernels), against the oracle's gradient."""
+    spec, ext = "ixj=kxi*jxk", dict(i=30, x=4, j=26, k=21)
+    A, B, C0 = inputs(spec, ext, 371, beta=True)
+    W = synth.uniform(374, shape_of("ixj", ext))
+    print_case("batch labels backward")
+    Ad = torch_dev(A, torch.float64).requires_grad_(True)
+    Bd = torch_dev(B, torch.float64).requires_grad_(True)
+    Cd = torch_dev(C0, torch.float64).requires_grad_(True)
+    C = comet.contract_ad(spec, Ad, Bd, Cd, alpha=0.5, beta=2.0)
+    (C * torch_dev(W, torch.float64)).sum().backward()
+    torch.cuda.synchronize()
+    dA, dB, dC0 = oracle.grad(spec, A, B, W, alpha=0.5, beta=2.0)
+    assert oracle.relerr(to_np(Ad.grad), dA) <= 1e-12
+    assert oracle.relerr(to_np(Bd.grad), dB) <= 1e-12
+    assert np.array_equal(to_np(Cd.grad), dC0)
+
+
 # --------------------------------------------------------------------------
 # stepped index ranges [lo:hi:step] as views
 # --------------------------------------------------------------------------

@@ -453,7 +453,8 @@ def test_gradient_specs():
     assert oracle.grad_specs("abij=acik*bkcj") == ("acik=abij*bkcj", "bkcj=acik*abij")
 
 
-@pytest.mark.parametrize("spec", ["abij=acik*bkcj", "abcijk=daij*bcdk", "ajbi=kcia*cjkb"])
+@pytest.mark.parametrize("spec", ["abij=acik*bkcj", "abcijk=daij*bcdk", "ajbi=kcia*cjkb", "xij=xik*xkj",
+                                  "ixj=kxi*jxk"])
 def test_gradient_vs_central_finite_differences(spec):
     rng = random.Random(7)
     c, a, b = oracle.split_spec(spec)
