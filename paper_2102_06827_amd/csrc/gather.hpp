@@ -366,7 +366,9 @@ __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &
 // too: the offsets come from LDS (a counter of their own), and with
 // beta != 0 the C values of the next group are requested before the current
 // group is stored, so that every wait is for loads issued ahead of the
-// stores still in flight.
+// stores still in flight.  C is written with nontemporal stores: the kernel
+// never reads it back, and streaming it past the caches made the
+// store-bound K = 32 triples contraction 10% faster on MI355X.
 template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
 __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM, WGN> &w, Tin *__restrict__ C,
                                                   const lds_t<int64_t> *cm, const lds_t<int64_t> *cn, int64_t M,
@@ -392,7 +394,7 @@ __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM
       for (int r = 0; r < 4; ++r) a[r] = addr(i, r, j);
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (inside(i, r, j)) gC[a[r]] = Tin(al * Te(w.acc[i][j][r]));
+        if (inside(i, r, j)) __builtin_nontemporal_store(Tin(al * Te(w.acc[i][j][r])), &gC[a[r]]);
     }
     return;
   }
@@ -422,7 +424,7 @@ __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM
     for (int r = 0; r < 4; ++r) a[r] = addr(i, r, j);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (inside(i, r, j)) gC[a[r]] = Tin(al * Te(w.acc[i][j][r]) + be * Te(cv[g & 1][r]));
+      if (inside(i, r, j)) __builtin_nontemporal_store(Tin(al * Te(w.acc[i][j][r]) + be * Te(cv[g & 1][r])), &gC[a[r]]);
   }
 }
 
@@ -456,7 +458,7 @@ __device__ __forceinline__ void gett_store_staged_serial(const WaveTile<Tc, BM, 
         const int64_t addr = cm[ml] + cnv;
         Te v = al * Te(w.acc[i][j][r]);
         if (read_c) v = v + be * Te(gC[addr]);
-        gC[addr] = Tin(v);
+        __builtin_nontemporal_store(Tin(v), &gC[addr]);
       }
     }
   }
@@ -515,7 +517,7 @@ __device__ __forceinline__ void gett_store_fragment(const typename AccT<Tc>::typ
   for (int r = 0; r < 4; ++r) x[r] = beta != 0.0 ? be * Te(gC[addr[r]]) : Te(0);
 #pragma unroll
   for (int r = 0; r < 4; ++r)
-    if (m0 + wm0 + i * 16 + acc_row<Tc>(lane, r) < M) gC[addr[r]] = Tin(al * Te(v[r]) + x[r]);
+    if (m0 + wm0 + i * 16 + acc_row<Tc>(lane, r) < M) __builtin_nontemporal_store(Tin(al * Te(v[r]) + x[r]), &gC[addr[r]]);
 }
 
 // A partial sum of one tile in workspace: accumulator element (i, j) of

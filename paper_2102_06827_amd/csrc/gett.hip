@@ -496,7 +496,7 @@ __global__ __launch_bounds__(256) void scale_kernel(T *__restrict__ C, const int
     const int64_t b = i / MN, r = i - b * MN;
     const int64_t m = r / N, n = r - m * N;
     const int64_t a = (offCb ? offCb[b] : 0) + offCm[m] + offCn[n];
-    C[a] = beta == 0.0 ? T(0) : T(double(C[a]) * beta);
+    __builtin_nontemporal_store(beta == 0.0 ? T(0) : T(double(C[a]) * beta), C + a);
   }
 }
 

@@ -383,7 +383,7 @@ __device__ __forceinline__ void split_store(Tout *__restrict__ C, const int64_t 
       for (int r = 0; r < 4; ++r) a[r] = toff[ml(i, r)] + toff[BM + nl(j)];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (inside(i, r, j)) gC[a[r]] = Tout(value(i, j, r));
+        if (inside(i, r, j)) __builtin_nontemporal_store(Tout(value(i, j, r)), &gC[a[r]]);
     }
     return;
   }
@@ -404,7 +404,7 @@ __device__ __forceinline__ void split_store(Tout *__restrict__ C, const int64_t 
     for (int r = 0; r < 4; ++r) a[r] = toff[ml(i, r)] + toff[BM + nl(j)];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      if (inside(i, r, j)) gC[a[r]] = Tout(value(i, j, r) + Te(beta) * Te(cv[g & 1][r]));
+      if (inside(i, r, j)) __builtin_nontemporal_store(Tout(value(i, j, r) + Te(beta) * Te(cv[g & 1][r])), &gC[a[r]]);
   }
 }
 
