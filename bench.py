@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the schedule and kernel version recorded, null otherwise.
 HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512}, "kernel_version": "k6",
                     "bytes": 881097402}
-KERNEL_VERSION = "k6"
+KERNEL_VERSION = "k7"
 
 
 def headline_kernels(d):
