@@ -75,56 +75,102 @@ struct StreamArgs {
   double fill;            // value of the alpha term when alpha == 0 (nothing is read then)
 };
 
+// Each pass of a workgroup covers SB * SU consecutive vectors, that is the
+// rows [r0, r1] of its range: their input and output offsets are decomposed
+// once per row into LDS (not once per vector), then every thread takes its
+// SU vectors (stride SB).  The next pass's loads are issued before this
+// pass's stores, so that a wait for them is not also a wait for the stores
+// (loads and stores share one in-order completion counter on CDNA).
+constexpr int SROWS = SB * SU;   // rows a pass can touch (one vector per row)
+
 template <typename T, int W, typename I>
 __global__ __launch_bounds__(SB) void permute_stream(const T *__restrict__ in, T *__restrict__ out, StreamArgs a,
                                                      double alpha, double beta) {
   typedef typename std::conditional<sizeof(T) == 8, double, float>::type Te;
   typedef typename Vec16<T>::type vec_t;
-  const int64_t stride = int64_t(gridDim.x) * SB * SU;
-  for (int64_t q0 = int64_t(blockIdx.x) * SB * SU + threadIdx.x; q0 < a.total; q0 += stride) {
-    int64_t ai[SU], ao[SU];
-    bool ok[SU];
+  typedef typename std::conditional<W == 1, T, vec_t>::type val_t;
+  __shared__ int64_t row_in[SROWS + 1], row_out[SROWS + 1];
+  const int64_t per_pass = int64_t(SB) * SU;
+  const int64_t stride = int64_t(gridDim.x) * per_pass;
+  const I vpr = I(a.vpr);
+  const bool reads = alpha != 0.0;
+  int64_t q0 = int64_t(blockIdx.x) * per_pass;
+  if (q0 >= a.total) return;   // uniform: a workgroup without vectors
+  // offsets of this thread's vectors of the pass at q0 (rows from LDS)
+  auto offsets = [&](int64_t qb, int64_t *ai, int64_t *ao, bool *ok) {
+    const int64_t r0 = int64_t(I(qb) / vpr);
+    const int64_t qe = qb + per_pass < a.total ? qb + per_pass : a.total;
+    const int64_t nrows = int64_t(I(qe - 1) / vpr) - r0 + 1;
+    for (int64_t t = threadIdx.x; t < nrows; t += SB) {
+      int64_t bi, bo;
+      decompose<I>(a.rows, r0 + t, &bi, &bo);
+      row_in[t] = bi;
+      row_out[t] = bo;
+    }
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
-      const int64_t q = q0 + int64_t(u) * SB;
+      const int64_t q = qb + threadIdx.x + int64_t(u) * SB;
       ok[u] = q < a.total;
-      const I row = ok[u] ? I(q) / I(a.vpr) : I(0);
-      const int64_t c = ok[u] ? int64_t(I(q) - row * I(a.vpr)) * W : 0;
-      int64_t bi, bo;
-      decompose<I>(a.rows, int64_t(row), &bi, &bo);
-      ai[u] = bi + c * a.su_in;
-      ao[u] = bo + c * a.su_out;
+      const I qq = ok[u] ? I(q) : I(qb);
+      const I row = qq / vpr;
+      const int64_t c = int64_t(qq - row * vpr) * W;
+      ai[u] = row_in[int64_t(row) - r0] + c * a.su_in;
+      ao[u] = row_out[int64_t(row) - r0] + c * a.su_out;
     }
-    if constexpr (W > 1) {
-      vec_t x[SU];
+    __syncthreads();   // the table is rewritten by the next pass
+  };
+  auto load = [&](const int64_t *ai, const bool *ok, val_t *x) {
 #pragma unroll
-      for (int u = 0; u < SU; ++u)
-        if (ok[u]) x[u] = alpha != 0.0 ? *reinterpret_cast<const vec_t *>(in + ai[u]) : vec_t{};
+    for (int u = 0; u < SU; ++u) {
+      if (W > 1)
+        x[u] = (reads && ok[u]) ? *reinterpret_cast<const val_t *>(in + ai[u]) : val_t{};
+      else
+        x[u] = (reads && ok[u]) ? val_t(in[ai[u]]) : val_t{};
+    }
+  };
+  int64_t ai[SU], ao[SU];
+  bool ok[SU];
+  val_t x[SU];
+  offsets(q0, ai, ao, ok);
+  load(ai, ok, x);
+  for (; q0 < a.total; q0 += stride) {
+    // the next pass's vectors, requested before this pass is stored
+    int64_t ai1[SU], ao1[SU];
+    bool ok1[SU];
+    val_t x1[SU];
+    const bool more = q0 + stride < a.total;
+    if (more) {
+      offsets(q0 + stride, ai1, ao1, ok1);
+      load(ai1, ok1, x1);
+    }
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        if (!ok[u]) continue;
-        vec_t y;
-        vec_t *dst = reinterpret_cast<vec_t *>(out + ao[u]);
+    for (int u = 0; u < SU; ++u) {
+      if (!ok[u]) continue;
+      val_t *dst = reinterpret_cast<val_t *>(out + ao[u]);
+      val_t y;
+      if constexpr (W > 1) {
         const vec_t old = beta != 0.0 ? *dst : vec_t{};
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          Te v = alpha != 0.0 ? Te(alpha) * Te(x[u][k]) : Te(a.fill);
+          Te v = reads ? Te(alpha) * Te(x[u][k]) : Te(a.fill);
           if (beta != 0.0) v = v + Te(beta) * Te(old[k]);
           y[k] = T(v);
         }
-        __builtin_nontemporal_store(y, dst);   // streamed past the caches: 3% faster here
+      } else {
+        Te v = reads ? Te(alpha) * Te(x[u]) : Te(a.fill);
+        if (beta != 0.0) v = v + Te(beta) * Te(*dst);
+        y = T(v);
       }
-    } else {
-      T x[SU];
-#pragma unroll
-      for (int u = 0; u < SU; ++u)
-        if (ok[u]) x[u] = alpha != 0.0 ? in[ai[u]] : T(0);
+      __builtin_nontemporal_store(y, dst);   // streamed past the caches: 3% faster here
+    }
+    if (more) {
 #pragma unroll
       for (int u = 0; u < SU; ++u) {
-        if (!ok[u]) continue;
-        Te v = alpha != 0.0 ? Te(alpha) * Te(x[u]) : Te(a.fill);
-        if (beta != 0.0) v = v + Te(beta) * Te(out[ao[u]]);
-        __builtin_nontemporal_store(T(v), out + ao[u]);
+        ai[u] = ai1[u];
+        ao[u] = ao1[u];
+        ok[u] = ok1[u];
+        x[u] = x1[u];
       }
     }
   }
