@@ -195,8 +195,13 @@ comet_status_t comet_plan_execute(comet_plan_t plan, double alpha, const void *A
                                   double beta, void *C, void *workspace, size_t ws_bytes,
                                   void *stream);
 comet_status_t comet_plan_destroy(comet_plan_t plan);
-/* Writes a JSON description of the plan (path, label classes and fusion,
- * layouts, tile shape, TTGT permutations and cost) into buf; host only. */
+/* Writes a JSON description of the plan into buf (host only): path, the
+ * label classes after fusion ("M", "N", "K" and the batch labels "X", with
+ * extents and strides), flattened sizes m, n, k and batch entries nb,
+ * operand layouts and contiguous runs, tile shape, stream-K split
+ * (sk_tiles, sk_blocks), persistent workgroups, resident workgroups per CU,
+ * the split tile and whether FP32 BF16x3 runs fused, TTGT permutations and
+ * cost.  COMET_ERR_WORKSPACE if buf is too small (the text is truncated). */
 comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len);
 
 /*
