@@ -20,8 +20,10 @@
  *          three.  A batch label indexes C, A and B alike and is not summed
  *          (e.g. "bij=bik*bkj" is a batch of matrix products, "ij=ij*ij" the
  *          elementwise product); the operation grammar of Section 4 does not
- *          rule such labels out.  The TTGT path (COMET_PATH_TTGT) has no
- *          batch labels and returns COMET_ERR_UNSUPPORTED for them.  A label
+ *          rule such labels out.  The native FP64 / FP32 products run all
+ *          batch entries in one launch; the split modes run one contraction
+ *          per entry.  The TTGT path (COMET_PATH_TTGT) has no batch labels
+ *          and returns COMET_ERR_UNSUPPORTED for them.  A label
  *          in one tensor only, or repeated inside one tensor, returns
  *          COMET_ERR_INVALID_SPEC.
  * extents  one int64 per distinct label, in order of first appearance when
