@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # (gett_fixup_kernel).  HBM bytes of one group from FETCH_SIZE / WRITE_SIZE
 # counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
 # valid only for the schedule and kernel version recorded, null otherwise.
-HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512}, "kernel_version": "k7",
-                    "bytes": 880964934}
+HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 256}, "kernel_version": "k7",
+                    "bytes": 812120259}
 KERNEL_VERSION = "k7"
 
 

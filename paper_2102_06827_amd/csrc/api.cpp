@@ -186,6 +186,20 @@ struct Schedule {
   double us = 1e300;
 };
 
+// Workgroups of the stream-K kernel of `tile` resident per CU (0: none).
+int sk_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
+  GettLaunch g{};
+  g.dtype = an.dtype == COMET_F64 ? 0 : 1;
+  g.compute = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  g.layoutA = an.layoutA;
+  g.layoutB = an.layoutB;
+  g.vecA = vecA;
+  g.vecB = vecB;
+  g.tile = tile;
+  g.query_sk = 1;
+  return gett_occupancy(g);
+}
+
 // Workgroups of the persistent kernel of `tile` resident per CU (0: none).
 int persistent_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
   GettLaunch g{};
@@ -227,8 +241,10 @@ void persist_choice(const Analysis &an, int cus, bool vecA, bool vecB, Schedule 
 }
 
 // Modeled time of `tile`, whole tiles only and with the stream-K split;
-// returns the better of the two.
-Schedule model_tile(const Analysis &an, int tile, int resident, int cus) {
+// returns the better of the two.  resident: workgroups of the whole-tile
+// kernel per CU; sk_res: of the stream-K kernel, which runs after it and
+// gets at most one round of workgroups (a second round would only queue).
+Schedule model_tile(const Analysis &an, int tile, int resident, int sk_res, int cus) {
   Schedule out;
   out.tile = tile;
   const bool f64 = an.compute == COMET_COMPUTE_F64;
@@ -248,8 +264,8 @@ Schedule model_tile(const Analysis &an, int tile, int resident, int cus) {
     partial = rt * std::max(double(per_cu) / resident, 0.5);
   }
   out.us = double(full) * rt + partial;
-  if (rem > 0 && T <= INT32_MAX) {
-    const int64_t blocks = std::min<int64_t>(S, rem * nk / kSkMinSteps);
+  if (rem > 0 && T <= INT32_MAX && sk_res > 0) {
+    const int64_t blocks = std::min<int64_t>(int64_t(std::max(cus, 1)) * sk_res, rem * nk / kSkMinSteps);
     if (blocks >= 2) {
       // tiles' worth of steps per workgroup, at the speed of blocks / CUs
       // workgroups per CU (as for a partial round)
@@ -297,12 +313,13 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
   }
   Schedule best;
   if (forced_tile >= 0) {
-    best = model_tile(an, forced_tile, tile_resident(an, forced_tile, vecA, vecB), cus);
+    best = model_tile(an, forced_tile, tile_resident(an, forced_tile, vecA, vecB),
+                      sk_resident(an, forced_tile, vecA, vecB), cus);
     best.tile = forced_tile;
   } else {
     for (int t = 0; t < gett_tile_count(); ++t) {
       if (!gett_tile_valid(t, dt, cp, vecA, vecB, !an.X.empty())) continue;
-      Schedule sc = model_tile(an, t, tile_resident(an, t, vecA, vecB), cus);
+      Schedule sc = model_tile(an, t, tile_resident(an, t, vecA, vecB), sk_resident(an, t, vecA, vecB), cus);
       if (sc.us < best.us * 0.999) best = sc;
     }
   }

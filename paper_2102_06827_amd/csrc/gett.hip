@@ -371,6 +371,9 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
     constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn;
     constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
     if (g.occupancy) {
+      if (g.query_sk)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy,
+                                                            gett_sk_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
       if (g.persistent > 0) {
         if constexpr (!persistent_fits<Tin, Tc, TILE, LA, LB, VA, VB>()) {
           *g.occupancy = 0;

@@ -48,6 +48,7 @@ struct GettLaunch {
   int vecA, vecB;      // 16-byte vector loads allowed
   int tile;            // tile variant
   int *occupancy = nullptr;   // when set: store the resident workgroups per CU, launch nothing
+  int query_sk = 0;           // with occupancy: of the stream-K kernel instead
   StreamK sk;
   int persistent = 0;         // > 0: this many persistent workgroups walk the tiles (no stream-K)
   GettBatch bt;               // batch labels: whole tiles only (no stream-K, not persistent)
