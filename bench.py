@@ -13,8 +13,10 @@ The same line also carries, each timed with HIP events on the launch stream:
   backward   forward + dA + dB of the same contraction (FP64 and aligned split);
   triples    the 6D-output contraction C[a,b,c,i,j,k] = sum_d A[d,a,i,j] B[b,c,d,k]
              (virtual 32, occupied 16), bound by writing C to HBM;
-  config1    the all-16 contraction (latency-bound), with the oracle's
-             single-thread and all-core times;
+  config1    the all-16 contraction (latency-bound): per call through the
+             Python binding, and replayed from a HIP graph of plan executions
+             (device time without host work); with the oracle's single-thread
+             and all-core times;
   permute    the transpose kernel of the TTGT lowering on three shapes;
   ttgt_study every TTGT flattening of configs 2 and 3 timed, the planner's
              cost-model pick ranked among them, against GETT;
@@ -328,8 +330,26 @@ def bench_config1(comet, reps=50):
     check_full(["config1", "relerr_vs_oracle"], spec, A, B, C.cpu().numpy())
     ms = timed(lambda: comet.contract(spec, Ad, Bd, C), reps, torch.cuda.current_stream())
     flops = 2.0 * 16 ** 6
-    return {"ms": round(ms, 5), "gflops": round(flops / (ms * 1e-3) / 1e9, 1), "relerr_vs_oracle": None,
-            "oracle_ms_1thread": None, "oracle_ms_all_cores": None, "A": A, "B": B}
+    # the same contraction through a plan captured in a HIP graph: the device
+    # time per contraction without the per-call host work
+    plan = comet.Plan(spec, Ad, Bd, C, compute="f64")
+    ws = plan.workspace(Ad.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan(Ad, Bd, C, workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(10):
+            plan(Ad, Bd, C, workspace=ws)
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = timed(graph.replay, max(1, reps // 10), torch.cuda.current_stream()) / 10
+    return {"ms": round(ms, 5), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
+            "graph_ms": round(graph_ms, 5), "graph_gflops": round(flops / (graph_ms * 1e-3) / 1e9, 1),
+            "relerr_vs_oracle": None, "oracle_ms_1thread": None, "oracle_ms_all_cores": None, "A": A, "B": B}
 
 
 def bench_chain(comet, reps=5):

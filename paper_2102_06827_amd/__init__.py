@@ -179,23 +179,44 @@ def _dtype_code(*ts):
     return _DTYPE[dt]
 
 
+# Marshalled call arguments of comet_contract by (spec, shapes, strides):
+# repeated calls on same-shaped tensors skip the label bookkeeping.
+_ARGS_CACHE = {}
+_ARGS_CACHE_MAX = 256
+
+
+def _contract_args(spec, A, B, C):
+    key = (spec, tuple(A.shape), A.stride(), tuple(B.shape), B.stride(), None if C is None else (tuple(C.shape), C.stride()))
+    hit = _ARGS_CACHE.get(key)
+    if hit is not None:
+        return hit
+    ext, cshape = extents_of(spec, A.shape, B.shape)
+    if C is not None and tuple(C.shape) != cshape:
+        raise ValueError("C shape %s != %s" % (tuple(C.shape), cshape))
+    val = (spec.encode(), _i64(ext), cshape, _i64(A.stride()), _i64(B.stride()),
+           None if C is None else _i64(C.stride()))
+    if len(_ARGS_CACHE) >= _ARGS_CACHE_MAX:
+        _ARGS_CACHE.clear()
+    _ARGS_CACHE[key] = val
+    return val
+
+
 def contract(spec, A, B, C=None, alpha=1.0, beta=0.0, compute="default", stream=None):
     """C = alpha * contract(A, B) + beta * C  (C allocated when None).
 
     A, B (and C) are CUDA/HIP torch tensors of one dtype, any strides >= 0.
     """
-    ext, cshape = extents_of(spec, A.shape, B.shape)
+    spec_b, ext, cshape, sa, sb, sc = _contract_args(spec, A, B, C)
     if C is None:
-        C = torch.empty(cshape, dtype=A.dtype, device=A.device)
         if beta != 0.0:
             raise ValueError("beta != 0 needs C")
-    elif tuple(C.shape) != cshape:
-        raise ValueError("C shape %s != %s" % (tuple(C.shape), cshape))
+        C = torch.empty(cshape, dtype=A.dtype, device=A.device)
+        sc = _i64(C.stride())
     dt = _dtype_code(A, B, C)
-    rc = lib().comet_contract(spec.encode(), _i64(ext), dt, COMPUTE[compute], float(alpha),
-                              ctypes.c_void_p(A.data_ptr()), _i64(A.stride()),
-                              ctypes.c_void_p(B.data_ptr()), _i64(B.stride()), float(beta),
-                              ctypes.c_void_p(C.data_ptr()), _i64(C.stride()), _stream_handle(stream))
+    rc = lib().comet_contract(spec_b, ext, dt, COMPUTE[compute], float(alpha),
+                              ctypes.c_void_p(A.data_ptr()), sa,
+                              ctypes.c_void_p(B.data_ptr()), sb, float(beta),
+                              ctypes.c_void_p(C.data_ptr()), sc, _stream_handle(stream))
     _check(rc)
     return C
 

@@ -164,6 +164,7 @@ constexpr double kThroughputF32[] = {74.5, 64.9, 73.4, 75.8, 79.3, 69.8, 70.1};
 constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
 constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
+constexpr int kSkSmallSteps = 4;        // the same for latency-bound problems (tile 1)
 constexpr double kSkBytesPerUs = 4.0e6;  // partial-sum traffic rate (HBM, both directions)
 constexpr double kSkLaunchUs = 4.0;      // the two extra launches
 
@@ -321,6 +322,33 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
       if (!gett_tile_valid(t, dt, cp, vecA, vecB, !an.X.empty())) continue;
       Schedule sc = model_tile(an, t, tile_resident(an, t, vecA, vecB), sk_resident(an, t, vecA, vecB), cus);
       if (sc.us < best.us * 0.999) best = sc;
+    }
+    // Latency-bound problems: fewer 64 x 64 tiles than one round of tile-1
+    // workgroups.  The per-step latency of a lone workgroup dominates there,
+    // which the throughput model does not see (the all-16 contraction on
+    // MI355X: the model's tile 5 took 21.5 us, tile 1 with its summation cut
+    // into 4-step pieces 13.2 us); take tile 1 and spread the summation over
+    // the idle CUs.
+    if (an.X.empty() && vecA && vecB && gett_tile_valid(1, dt, cp, vecA, vecB)) {
+      int bm, bn, bk;
+      gett_tile_shape(1, &bm, &bn, &bk);
+      const int64_t T1 = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+      const int64_t nk = (an.k + bk - 1) / bk;
+      const int res1 = tile_resident(an, 1, vecA, vecB), skres1 = sk_resident(an, 1, vecA, vecB);
+      const int64_t blocks =
+          skres1 > 0 ? std::min<int64_t>(int64_t(std::max(cus, 1)) * skres1, T1 * nk / kSkSmallSteps) : 0;
+      // (with neither a split nor at most one tile per CU, the model's
+      // larger tiles measured faster: 2048^2 outputs, K = 256)
+      if (res1 > 0 && T1 <= int64_t(std::max(cus, 1)) * res1 && (blocks > T1 || T1 <= cus)) {
+        Schedule sc;
+        sc.tile = 1;
+        sc.us = 0.0;
+        if (blocks > T1) {
+          sc.sk_tiles = int(T1);
+          sc.sk_blocks = int(blocks);
+        }
+        best = sc;
+      }
     }
   }
   // the stream-K kernels exist for the vector-load variants
