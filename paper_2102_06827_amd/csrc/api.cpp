@@ -304,6 +304,34 @@ void sk_override(const Analysis &an, Schedule &sc) {
   sc.sk_blocks = sc.sk_tiles > 0 ? std::max(b, 1) : 0;
 }
 
+// Latency-bound problems: fewer 64 x 64 tiles than one round of tile-1
+// workgroups.  The per-step latency of a lone workgroup dominates there,
+// which the throughput model does not see (the all-16 contraction on MI355X:
+// the model's tile 5 took 21.5 us, tile 1 with its summation cut into 4-step
+// pieces 13.2 us); take tile 1 and spread the summation over the idle CUs.
+// With neither a split nor at most one tile per CU the model's larger tiles
+// measured faster (2048^2 outputs, K = 256), and *sc is left alone.
+void latency_schedule(const Analysis &an, int cus, bool vecA, bool vecB, Schedule *sc) {
+  const int dt = an.dtype == COMET_F64 ? 0 : 1, cp = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  if (!an.X.empty() || !vecA || !vecB || !gett_tile_valid(1, dt, cp, vecA, vecB)) return;
+  int bm, bn, bk;
+  gett_tile_shape(1, &bm, &bn, &bk);
+  const int64_t T1 = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+  const int64_t nk = (an.k + bk - 1) / bk;
+  const int64_t C = std::max(cus, 1);
+  const int res1 = tile_resident(an, 1, vecA, vecB), skres1 = sk_resident(an, 1, vecA, vecB);
+  const int64_t blocks = skres1 > 0 ? std::min<int64_t>(C * skres1, T1 * nk / kSkSmallSteps) : 0;
+  if (res1 <= 0 || T1 > C * res1 || !(blocks > T1 || T1 <= C)) return;
+  Schedule out;
+  out.tile = 1;
+  out.us = 0.0;
+  if (blocks > T1) {
+    out.sk_tiles = int(T1);
+    out.sk_blocks = int(blocks);
+  }
+  *sc = out;
+}
+
 // Tile and stream-K split of the gather kernel for an analyzed contraction.
 Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int forced_tile = -1) {
   const int dt = an.dtype == COMET_F64 ? 0 : 1, cp = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
@@ -317,39 +345,14 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
     best = model_tile(an, forced_tile, tile_resident(an, forced_tile, vecA, vecB),
                       sk_resident(an, forced_tile, vecA, vecB), cus);
     best.tile = forced_tile;
+    if (forced_tile == 1) latency_schedule(an, cus, vecA, vecB, &best);
   } else {
     for (int t = 0; t < gett_tile_count(); ++t) {
       if (!gett_tile_valid(t, dt, cp, vecA, vecB, !an.X.empty())) continue;
       Schedule sc = model_tile(an, t, tile_resident(an, t, vecA, vecB), sk_resident(an, t, vecA, vecB), cus);
       if (sc.us < best.us * 0.999) best = sc;
     }
-    // Latency-bound problems: fewer 64 x 64 tiles than one round of tile-1
-    // workgroups.  The per-step latency of a lone workgroup dominates there,
-    // which the throughput model does not see (the all-16 contraction on
-    // MI355X: the model's tile 5 took 21.5 us, tile 1 with its summation cut
-    // into 4-step pieces 13.2 us); take tile 1 and spread the summation over
-    // the idle CUs.
-    if (an.X.empty() && vecA && vecB && gett_tile_valid(1, dt, cp, vecA, vecB)) {
-      int bm, bn, bk;
-      gett_tile_shape(1, &bm, &bn, &bk);
-      const int64_t T1 = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
-      const int64_t nk = (an.k + bk - 1) / bk;
-      const int res1 = tile_resident(an, 1, vecA, vecB), skres1 = sk_resident(an, 1, vecA, vecB);
-      const int64_t blocks =
-          skres1 > 0 ? std::min<int64_t>(int64_t(std::max(cus, 1)) * skres1, T1 * nk / kSkSmallSteps) : 0;
-      // (with neither a split nor at most one tile per CU, the model's
-      // larger tiles measured faster: 2048^2 outputs, K = 256)
-      if (res1 > 0 && T1 <= int64_t(std::max(cus, 1)) * res1 && (blocks > T1 || T1 <= cus)) {
-        Schedule sc;
-        sc.tile = 1;
-        sc.us = 0.0;
-        if (blocks > T1) {
-          sc.sk_tiles = int(T1);
-          sc.sk_blocks = int(blocks);
-        }
-        best = sc;
-      }
-    }
+    latency_schedule(an, cus, vecA, vecB, &best);
   }
   // the stream-K kernels exist for the vector-load variants
   if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
