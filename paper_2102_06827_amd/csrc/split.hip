@@ -30,11 +30,13 @@
 // Rows are scaled by powers of two in every mode (exact), which keeps the
 // 16-bit slices in range; the epilogue multiplies by 2^(eA[m] + eB[n]).
 //
-// Kernels: an exponent pass (row maxima, HBM-bound), a pack pass (gather
-// through the offset tables into an LDS tile, so reads are coalesced along
-// the operand's unit-stride label, then write K-contiguous slices -- this is
-// also the transpose of TTGT), and the slice-pair matrix product on
-// v_mfma_f32_16x16x32_{bf16,f16}.
+// Kernels, one launch each for both operands: an exponent pass (partial row
+// maxima over ranges of the summation, HBM-bound) and a pack pass (reduce a
+// row's partial maxima, gather through the offset tables into an LDS tile so
+// reads are coalesced along the operand's unit-stride label, then write
+// K-contiguous slices -- this is also the transpose of TTGT); then the
+// slice-pair matrix product on v_mfma_f32_16x16x32_{bf16,f16} or
+// v_mfma_i32_16x16x64_i8.
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
