@@ -500,6 +500,20 @@ def test_persistent_schedule(tile, grid, dtype, spec, ext, monkeypatch):
     check(spec, ext, dtype, seed=980 + tile, alpha=-0.75, beta=0.5)
 
 
+def test_latency_bound_problems_spread_the_summation():
+    """Fewer 64 x 64 tiles than one round of workgroups (the all-16
+    contraction): tile 1 with its summation cut into stream-K pieces, and the
+    result equals the oracle's."""
+    spec, ext = CONFIG_SMALL[0]
+    A, B, _ = inputs(spec, ext, 990)
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    d = comet.Plan(spec, Ad, Bd).describe()
+    assert d["tile"] == 1 and d["sk_tiles"] == 16 and d["sk_blocks"] > d["sk_tiles"]
+    print_case("latency-bound schedule")
+    got = to_np(comet.contract(spec, Ad, Bd))
+    assert oracle.relerr(got, oracle.contract(spec, A, B)) <= 1e-12
+
+
 def test_persistent_only_on_request(monkeypatch):
     """The whole-tile kernel is the default for short summations too; the
     persistent schedule runs when COMET_GETT_PERSIST asks for it."""
