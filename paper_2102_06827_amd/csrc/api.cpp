@@ -159,8 +159,8 @@ comet_status_t upload_tables(comet_plan_s *p) {
 // stream-K alternative replaces the partial round by an equal split of its
 // tiles' summation over all S slots, plus the partial sums it writes and
 // reads back.  The autotuner replaces this model with timings.
-constexpr double kThroughputF64[] = {28.4, 33.2, 28.6, 41.0, 38.6, 33.6, 32.7, 33.5, 34.4, 34.3};
-constexpr double kThroughputF32[] = {74.5, 64.9, 73.4, 75.8, 79.3, 69.8, 70.1};
+constexpr double kThroughputF64[] = {28.7, 33.5, 30.9, 41.4, 39.5, 34.2, 33.4, 34.2, 35.0, 34.8};
+constexpr double kThroughputF32[] = {76.0, 70.6, 74.2, 77.0, 80.3, 69.2, 69.5};
 constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
 constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
