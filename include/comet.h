@@ -156,8 +156,10 @@ typedef struct {
 /*
  * comet_contract -- one contraction, C = alpha * contract(A, B) + beta * C
  * (Section 2 equations; ta.tc of Section 5).  Convenience call: plans on
- * first use (cached per spec, extents, strides, dtype, compute, device) and
- * uses a library-owned, stream-ordered workspace.  Returns
+ * first use (cached per spec, extents, strides, dtype, compute, device; at
+ * most 1024 plans per device, past which the call waits for the device and
+ * empties that device's cache) and uses a library-owned, stream-ordered
+ * workspace.  Returns
  * COMET_ERR_UNSUPPORTED if the stream is being captured (use the plan API
  * there).
  */

@@ -855,7 +855,11 @@ struct DeviceWorkspace {
   void *ptr = nullptr;
   size_t bytes = 0;
 };
-std::map<std::string, std::unique_ptr<comet_plan_s>> g_cache;
+// Plans of comet_contract, per device.  Each holds device tables, so the
+// cache is bounded: past kMaxCachedPlans distinct problems on one device it
+// waits for the device and starts over.
+constexpr size_t kMaxCachedPlans = 1024;
+std::map<int, std::map<std::string, std::unique_ptr<comet_plan_s>>> g_cache;
 std::map<int, DeviceWorkspace> g_ws;
 
 std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const int64_t *sA, size_t ra,
@@ -1005,15 +1009,21 @@ comet_status_t comet_contract(const char *spec, const int64_t *extents, comet_dt
   std::string key = cache_key(spec, extents, pre.labels.size(), strides_A, pre.spec_a.size(), strides_B,
                               pre.spec_b.size(), strides_C, pre.spec_c.size(), dtype, compute, dev);
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_cache.find(key);
+  auto &cache = g_cache[dev];
+  auto it = cache.find(key);
   comet_plan_s *p;
-  if (it == g_cache.end()) {
+  if (it == cache.end()) {
     std::unique_ptr<comet_plan_s> np;
     comet_status_t rc = build_plan(np, spec, extents, strides_A, strides_B, strides_C, dtype, compute,
                                    COMET_PATH_AUTO);
     if (rc != COMET_OK) return rc;
+    if (cache.size() >= kMaxCachedPlans) {
+      // kernels still in flight may read the tables of the cached plans
+      HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+      cache.clear();
+    }
     p = np.get();
-    g_cache[key] = std::move(np);
+    cache[key] = std::move(np);
   } else {
     p = it->second.get();
   }

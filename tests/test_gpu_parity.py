@@ -524,3 +524,23 @@ def test_persistent_only_on_request(monkeypatch):
     monkeypatch.setenv("COMET_GETT_PERSIST", "256")
     d = comet.Plan("abcijk=daij*bcdk", A, B).describe()
     assert d["persist"] == 256
+
+
+def test_contract_plan_cache_is_bounded():
+    """comet_contract keeps at most 1024 plans per device: the 1025th distinct
+    problem empties the cache, and every call before and after it (including
+    a problem planned again after the reset) gives the exact result."""
+    print_case("plan cache bound", "ij=ik*kj", "i = 1..1030")
+    k, j = 5, 3
+    B = synth.integers(31, (k, j))
+    Bd = torch_dev(B, torch.float64)
+    As = {}
+    for i in list(range(1, 1031)) + [1, 2, 1030]:
+        if i not in As:
+            As[i] = synth.integers(1000 + i, (i, k))
+        out = comet.contract("ij=ik*kj", torch_dev(As[i], torch.float64), Bd)
+        if i % 97 == 1 or i >= 1020 or i <= 2:
+            torch.cuda.synchronize()
+            ref = oracle.contract("ij=ik*kj", As[i], B)
+            assert np.array_equal(to_np(out), ref), "i = %d" % i
+    torch.cuda.synchronize()
