@@ -288,7 +288,7 @@ def bench_triples(comet, reps):
     nbytes = 8.0 * (A.size + B.size + C.numel())
     rng = np.random.default_rng(13)
     pts = np.stack([rng.integers(0, n, 256) for n in C.shape], axis=1)
-    flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+    flush = torch.ones(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
     out = {}
     for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2", "split_int8", "f64_ttgt"):
         if mode == "f64_ttgt":
@@ -302,7 +302,10 @@ def bench_triples(comet, reps):
                      C[tuple(torch.from_numpy(pts).to(dev).T)].cpu().numpy())
         tot = 0.0
         for _ in range(reps):
-            flush.fill_(1.0)     # evict the 256 MB last-level cache between runs
+            # evict the 256 MB last-level cache between runs by reading 512 MB:
+            # a write would leave it full of dirty lines whose write-back the
+            # timed run would pay for
+            flush.sum()
             tot += timed(run, 1, stream)
         ms = tot / reps
         out[mode] = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
@@ -404,7 +407,7 @@ def bench_permute(comet, reps):
     import torch
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    flush = torch.empty(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+    flush = torch.ones(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
     cases = [("aick=acik", dict(a=96, c=96, i=32, k=32)),
              ("abcijk=aijbck", dict(a=32, b=32, c=32, i=16, j=16, k=16)),
              ("ji=ij", dict(i=8192, j=8192))]
@@ -420,7 +423,7 @@ def bench_permute(comet, reps):
         exact = bool(torch.equal(y, x.permute(*[li.index(c) for c in lo])))
         tot = 0.0
         for _ in range(reps):
-            flush.fill_(1.0)
+            flush.sum()          # clean cold cache, as for the triples contraction
             tot += timed(lambda: comet.permute(spec, x, y), 1, stream)
         ms = tot / reps
         nbytes = 2.0 * x.numel() * 8
