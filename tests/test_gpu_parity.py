@@ -544,3 +544,35 @@ def test_contract_plan_cache_is_bounded():
             ref = oracle.contract("ij=ik*kj", As[i], B)
             assert np.array_equal(to_np(out), ref), "i = %d" % i
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("spec,dtype,compute", [
+    ("ij=ik*kj", "f32", "default"),
+    ("ji=ik*kj", "f32", "default"),
+    ("ij=ik*kj", "f64", "split_int8"),
+    ("ji=ik*kj", "f64", "split_bf16x3"),
+])
+def test_output_beyond_2_31_elements(spec, dtype, compute):
+    """C with 49152 x 49152 elements (2.4e9 > 2^31; 9.7 GB in FP32, 19.3 GB
+    in FP64): every output address needs 64 bits.  Integer inputs, exact in
+    every mode, so sampled outputs match the oracle bit for bit; all-ones
+    inputs give K everywhere, which checks that every element up to the last
+    one is written."""
+    n, k = 49152, 16
+    print_case("output beyond 2^31", spec, dtype, compute, n, k)
+    A = synth.integers(71, (n, k))
+    B = synth.integers(72, (k, n))
+    Ad, Bd = torch_dev(A, tdt(dtype)), torch_dev(B, tdt(dtype))
+    C = comet.contract(spec, Ad, Bd, compute=compute)
+    torch.cuda.synchronize()
+    assert C.numel() > (1 << 31)
+    pts = sample_points(tuple(C.shape), 4000, 9)
+    g = C[tuple(torch.from_numpy(pts).cuda().T)].cpu().numpy()
+    ref = oracle.contract_points(spec, A, B, pts)
+    assert np.array_equal(g, ref)
+    del C
+    C1 = comet.contract(spec, torch.ones_like(Ad), torch.ones_like(Bd), compute=compute)
+    torch.cuda.synchronize()
+    assert bool((C1 == float(k)).all())
+    del C1
+    torch.cuda.empty_cache()
