@@ -576,3 +576,32 @@ def test_output_beyond_2_31_elements(spec, dtype, compute):
     assert bool((C1 == float(k)).all())
     del C1
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_operands_beyond_2_31_elements(dtype):
+    """A and B with 64 x (2^25 + 8) elements each (2.1e9 > 2^31): operand
+    addresses need 64 bits, and the single 64 x 64 output tile sums 2^21 + 1
+    steps, the last one ragged.  A comb operand (1 where k mod 64 equals the
+    row, else 0) times all-ones gives, in closed form, K // 64 plus one for
+    the first K mod 64 rows -- exact in both precisions."""
+    m, k = 64, (1 << 25) + 8
+    t = tdt(dtype)
+    print_case("operands beyond 2^31", dtype, m, k)
+    kmod = torch.arange(k, device="cuda") % 64
+    idx = torch.arange(m, device="cuda")
+    want = torch.full((m,), float(k // 64), dtype=torch.float64, device="cuda") + (idx < k % 64).double()
+    A = (kmod[None, :] == idx[:, None]).to(t)
+    B = torch.ones((k, m), dtype=t, device="cuda")
+    assert A.numel() > (1 << 31)
+    C = comet.contract("ij=ik*kj", A, B)
+    torch.cuda.synchronize()
+    assert torch.equal(C.double(), want[:, None].expand(m, m))
+    del A, B, C
+    A = torch.ones((m, k), dtype=t, device="cuda")
+    B = (kmod[:, None] == idx[None, :]).to(t)
+    C = comet.contract("ij=ik*kj", A, B)
+    torch.cuda.synchronize()
+    assert torch.equal(C.double(), want[None, :].expand(m, m))
+    del A, B, C
+    torch.cuda.empty_cache()
