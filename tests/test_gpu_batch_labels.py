@@ -248,3 +248,15 @@ def test_stepped_views_with_batch_labels():
     Cd = comet.contract(spec, Ad, Bd)
     torch.cuda.synchronize()
     assert oracle.relerr(to_np(Cd), oracle.contract(spec, A, B)) <= 1e-12
+
+
+@pytest.mark.parametrize("spec,ext", [
+    ("bij=bik*bkj", dict(b=140001, i=3, j=2, k=5)),
+    ("ijk=ijk*ijk", dict(i=300, j=301, k=2)),
+])
+def test_batch_labels_beyond_one_launch(spec, ext):
+    """More batch entries than one launch's grid holds along y (65535): the
+    entries run in several launches, each from its own first entry; integer
+    inputs, bit-exact against the oracle."""
+    check(spec, ext, dtype="f64", seed=17, kind="integer")
+    check(spec, ext, dtype="f32", seed=18, kind="integer", beta=1.0)
