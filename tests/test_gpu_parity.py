@@ -605,3 +605,37 @@ def test_operands_beyond_2_31_elements(dtype):
     assert torch.equal(C.double(), want[None, :].expand(m, m))
     del A, B, C
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype,compute", [("f64", "default"), ("f32", "default"), ("f64", "split_int8"),
+                                           ("f64", "split_bf16x3"), ("f64", "ttgt")])
+def test_broadcast_operands(dtype, compute):
+    """Stride-0 (broadcast) operands: A constant along the summation label k,
+    B constant along the free label b.  The oracle gets the materialized
+    arrays."""
+    ext = dict(a=21, b=19, c=23, i=13, j=11, k=9)
+    spec = "abij=acik*bkcj"
+    print_case("broadcast operands", dtype, compute)
+    t = tdt(dtype)
+    a0 = synth.uniform(801, (21, 23, 13, 1))
+    b0 = synth.uniform(802, (1, 9, 23, 11))
+    c0 = synth.uniform(803, shape_of("abij", ext))
+    cast = np.float32 if dtype == "f32" else np.float64
+    A = np.ascontiguousarray(np.broadcast_to(a0, shape_of("acik", ext))).astype(cast)
+    B = np.ascontiguousarray(np.broadcast_to(b0, shape_of("bkcj", ext))).astype(cast)
+    C0 = c0.astype(cast)
+    Ad = torch_dev(a0, t).expand(*shape_of("acik", ext))
+    Bd = torch_dev(b0, t).expand(*shape_of("bkcj", ext))
+    assert Ad.stride()[3] == 0 and Bd.stride()[0] == 0
+    Cd = torch_dev(C0, t)
+    if compute == "ttgt":
+        plan = comet.Plan(spec, Ad, Bd, Cd, compute="f64", path="ttgt")
+        plan(Ad, Bd, Cd, alpha=0.5, beta=-1.0)
+        mode = "f64"
+    else:
+        comet.contract(spec, Ad, Bd, Cd, alpha=0.5, beta=-1.0, compute=compute)
+        mode = dtype if compute == "default" else compute
+    torch.cuda.synchronize()
+    ref = oracle.contract(spec, A, B, C0, alpha=0.5, beta=-1.0)
+    err = oracle.relerr(to_np(Cd), ref)
+    assert err <= dict(TOL, split_int8=1e-9)[mode], "relerr %.3e" % err
