@@ -241,3 +241,38 @@ def test_fp32_bf16x3_sliced_path_at_size_sampled():
     pts = np.stack([rng.integers(0, n, 2000), rng.integers(0, n, 2000)], axis=1)
     ref = oracle.contract_points("ij=ik*kj", A, B, pts)
     assert oracle.relerr(got[tuple(pts.T)], ref) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_split_degenerate(mode):
+    """The split modes on the degenerate problems: an empty summation
+    (C = beta * C), an empty output, a full contraction to a scalar, alpha = 0
+    with NaN in A (A and B unread), and extent-1 labels everywhere."""
+    print_case("split degenerate", mode)
+    f64 = torch.float64
+    C0 = synth.uniform(41, (5, 7))
+    C = torch_dev(C0, f64)
+    comet.contract("ij=ik*kj", torch.zeros((5, 0), dtype=f64, device="cuda"),
+                   torch.zeros((0, 7), dtype=f64, device="cuda"), C, beta=3.0, compute=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), 3.0 * C0)
+    C = comet.contract("ij=ik*kj", torch.zeros((0, 4), dtype=f64, device="cuda"),
+                       torch.ones((4, 3), dtype=f64, device="cuda"), compute=mode)
+    assert C.shape == (0, 3)
+    Ai = synth.integers(42, (37, 41))
+    Bi = synth.integers(43, (41, 37))
+    C = comet.contract("=ab*ba", torch_dev(Ai, f64), torch_dev(Bi, f64), compute=mode)
+    torch.cuda.synchronize()
+    assert float(C.item()) == float(np.sum(Ai * Bi.T))
+    A = torch.full((6, 4), float("nan"), dtype=f64, device="cuda")
+    B = torch_dev(synth.uniform(44, (4, 5)), f64)
+    C0 = synth.uniform(45, (6, 5))
+    C = torch_dev(C0, f64)
+    comet.contract("ij=ik*kj", A, B, C, alpha=0.0, beta=-2.0, compute=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), -2.0 * C0)
+    ext = dict(a=1, b=1, c=1, i=1, j=1, k=1)
+    A, B, _ = inputs("abij=acik*cbkj", ext, 46, kind="integer")
+    C = comet.contract("abij=acik*cbkj", torch_dev(A, f64), torch_dev(B, f64), compute=mode)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), oracle.contract("abij=acik*cbkj", A, B))
