@@ -313,7 +313,7 @@ void sk_override(const Analysis &an, Schedule &sc) {
 // measured faster (2048^2 outputs, K = 256), and *sc is left alone.
 void latency_schedule(const Analysis &an, int cus, bool vecA, bool vecB, Schedule *sc) {
   const int dt = an.dtype == COMET_F64 ? 0 : 1, cp = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
-  if (!an.X.empty() || !vecA || !vecB || !gett_tile_valid(1, dt, cp, vecA, vecB)) return;
+  if (!an.X.empty() || !gett_tile_valid(1, dt, cp, vecA, vecB)) return;
   int bm, bn, bk;
   gett_tile_shape(1, &bm, &bn, &bk);
   const int64_t T1 = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
@@ -352,12 +352,16 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
       Schedule sc = model_tile(an, t, tile_resident(an, t, vecA, vecB), sk_resident(an, t, vecA, vecB), cus);
       if (sc.us < best.us * 0.999) best = sc;
     }
+    // the throughput model describes the vector-load kernels: tile 1's
+    // element-load variant splits its summation only in the latency-bound
+    // case below (a ragged last round split by the model made the 3072^3
+    // "cmia=cdmn*inad" 2.8 -> 3.4 ms)
+    if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
     latency_schedule(an, cus, vecA, vecB, &best);
   }
-  // the stream-K kernels exist for the vector-load variants
-  if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
+  // every variant of a tile has its stream-K kernel (the element-load
+  // variants are those of tile 1)
   sk_override(an, best);
-  if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
   persist_choice(an, cus, vecA, vecB, best);
   return best;
 }

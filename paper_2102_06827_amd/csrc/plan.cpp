@@ -479,7 +479,21 @@ Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_
   bool b_n_contig = !an.N.empty() && (an.K.empty() || min_stride(an.N, 1) < min_stride(an.K, 1));
   if (a_m_contig) sort_by(an.M, 0, 2); else sort_by(an.M, 2, 0);
   if (b_n_contig) sort_by(an.N, 1, 2); else sort_by(an.N, 2, 1);
-  if (!a_m_contig && (b_n_contig || min_stride(an.K, 0) <= min_stride(an.K, 1))) sort_by(an.K, 0, 1);
+  // K follows the operand that reads along K; when both do, the one with the
+  // smaller stride there, and on a tie the larger operand (the other one's
+  // scattered reads then cost little: the GEMV-like "ia=dn*inad" reads its
+  // 75 MB operand in runs of 96 instead of one element per row)
+  bool k_by_a;
+  if (a_m_contig) {
+    k_by_a = false;
+  } else if (b_n_contig) {
+    k_by_a = true;
+  } else {
+    const int64_t ka = min_stride(an.K, 0), kb = min_stride(an.K, 1);
+    const int64_t size0 = an.swapped ? an.sizeB : an.sizeA, size1 = an.swapped ? an.sizeA : an.sizeB;
+    k_by_a = ka < kb || (ka == kb && size0 >= size1);
+  }
+  if (k_by_a) sort_by(an.K, 0, 1);
   else sort_by(an.K, 1, 0);
   fuse(an.M, true, false, true);
   fuse(an.N, false, true, true);

@@ -639,3 +639,35 @@ def test_broadcast_operands(dtype, compute):
     ref = oracle.contract(spec, A, B, C0, alpha=0.5, beta=-1.0)
     err = oracle.relerr(to_np(Cd), ref)
     assert err <= dict(TOL, split_int8=1e-9)[mode], "relerr %.3e" % err
+
+
+# operands whose unit-stride labels are different summation labels: only one
+# of them can read 16-byte vectors along the fused K order, so the plan takes
+# tile 1's element-load variant
+ELEMENT_LOAD_CASES = [
+    ("ia=ind*adn", dict(i=70, a=45, n=19, d=23)),
+    ("ia=dn*inad", dict(d=40, n=24, i=9, a=33)),     # one output row per i: GEMV-like
+]
+
+
+@pytest.mark.parametrize("sk", [None, "3,7", "2,200"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", ELEMENT_LOAD_CASES)
+def test_stream_k_element_load_variants(spec, ext, dtype, sk, monkeypatch):
+    """Stream-K splits of tile 1's element-load variants (planned, and forced
+    over tile boundaries and with more workgroups than steps) against the
+    oracle, bit-exact on integer inputs."""
+    if sk is not None:
+        monkeypatch.setenv("COMET_GETT_TILE", "1")
+        monkeypatch.setenv("COMET_GETT_SK", sk)
+    check(spec, ext, dtype, seed=960, kind="integer", alpha=1.0, beta=1.0)
+    check(spec, ext, dtype, seed=961, alpha=-0.5, beta=0.25)
+
+
+def test_gemv_like_contraction_is_split():
+    """A contraction with one output row and a long summation whose operands
+    cannot both read vectors is spread over the CUs by stream-K."""
+    A = torch.zeros((96, 32), dtype=torch.float64, device="cuda")
+    B = torch.zeros((32, 32, 96, 96), dtype=torch.float64, device="cuda")
+    d = comet.Plan("ia=dn*inad", A, B).describe()
+    assert d["tile"] == 1 and d["sk_tiles"] > 0 and d["sk_blocks"] > d["sk_tiles"]
