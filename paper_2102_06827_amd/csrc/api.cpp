@@ -162,6 +162,11 @@ comet_status_t upload_tables(comet_plan_s *p) {
 constexpr double kThroughputF64[] = {28.7, 33.5, 30.9, 41.4, 39.5, 34.2, 33.4, 34.2, 35.0, 34.8};
 constexpr double kThroughputF32[] = {76.0, 70.6, 74.2, 77.0, 80.3, 69.2, 69.5};
 constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
+// Products from which a contraction whose operands only tile 1's element-load
+// kernel can gather goes through TTGT instead (MI355X: "cmia=cdmn*inad" at
+// 3072^3 2.65 -> 1.00 ms in FP64 and 2.62 -> 0.58 ms in FP32, at 1024^3
+// 0.091 -> 0.067 ms)
+constexpr double kTTGTMinMNK = 0x1p30;
 constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
 constexpr int kSkSmallSteps = 4;        // the same for latency-bound problems (tile 1)
@@ -511,6 +516,20 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   };
   p->vecA_tables = tables_vec_ok(an.offAm, an.offAk, an.layoutA, an.runAm, an.runAk, VEC) && all_vec(an.offAx);
   p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC) && all_vec(an.offBx);
+  const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
+  if (path == COMET_PATH_AUTO && native && an.path == COMET_PATH_GETT && an.X.empty() && !an.empty_out &&
+      !an.empty_sum && !(p->vecA_tables && p->vecB_tables) &&
+      double(an.m) * double(an.n) * double(an.k) >= kTTGTMinMNK) {
+    // only tile 1's element-load kernel can gather these operands (their
+    // unit strides lie on different summation labels, or runs are ragged);
+    // on large products the permutes of TTGT cost less than that kernel
+    std::unique_ptr<comet_plan_s> tt;
+    if (build_plan(tt, spec, extents, sA, sB, sC, dtype, compute, COMET_PATH_TTGT, false) == COMET_OK && tt->gemm &&
+        tt->gemm->vecA_tables && tt->gemm->vecB_tables) {
+      out = std::move(tt);
+      return COMET_OK;
+    }
+  }
   apply_schedule(p.get(), cus);
   if (p->gemm) {
     apply_schedule(p->gemm.get(), cus);

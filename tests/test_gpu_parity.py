@@ -671,3 +671,27 @@ def test_gemv_like_contraction_is_split():
     B = torch.zeros((32, 32, 96, 96), dtype=torch.float64, device="cuda")
     d = comet.Plan("ia=dn*inad", A, B).describe()
     assert d["tile"] == 1 and d["sk_tiles"] > 0 and d["sk_blocks"] > d["sk_tiles"]
+
+
+def test_large_element_load_problem_goes_through_ttgt():
+    """Operands whose unit strides lie on different summation labels can only
+    be gathered by tile 1's element-load kernel; from 2^30 multiply-adds the
+    planner permutes them instead (TTGT).  Sampled outputs match the oracle."""
+    spec = "cmia=cdmn*inad"
+    ext = dict(c=64, m=16, i=16, a=64, d=64, n=16)
+    print_case("element-load problem via TTGT", spec, ext)
+    A = synth.uniform(971, shape_of("cdmn", ext))
+    B = synth.uniform(972, shape_of("inad", ext))
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    d = comet.Plan(spec, Ad, Bd).describe()
+    assert d["path"] == "ttgt"
+    C = comet.contract(spec, Ad, Bd)
+    torch.cuda.synchronize()
+    pts = sample_points(tuple(C.shape), 2000, 11)
+    g = C[tuple(torch.from_numpy(pts).cuda().T)].cpu().numpy()
+    assert oracle.relerr(g, oracle.contract_points(spec, A, B, pts)) <= 1e-12
+    # below the threshold the gather path stays
+    small = dict(c=32, m=16, i=16, a=32, d=32, n=16)
+    As = torch.zeros(shape_of("cdmn", small), dtype=torch.float64, device="cuda")
+    Bs = torch.zeros(shape_of("inad", small), dtype=torch.float64, device="cuda")
+    assert comet.Plan(spec, As, Bs).describe()["path"] == "gett"
