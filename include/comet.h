@@ -126,8 +126,12 @@ typedef enum {
 } comet_compute_t;
 
 /* Which lowering a plan uses.
- *   AUTO  the planner's choice (the fused gather path unless the autotune
- *         cache recorded TTGT as faster for this problem class).
+ *   AUTO  the planner's choice: the fused gather path, except TTGT where
+ *         the autotune cache recorded it as faster for this problem class,
+ *         and for native FP64 / FP32 products of 2^30 multiply-adds and more
+ *         (no batch labels) whose operands only the gather path's element
+ *         loads can read (their unit strides lie on different summation
+ *         labels) while the TTGT matrices can be read in vectors.
  *   GETT  operands are gathered through per-label offset tables straight into
  *         on-chip tiles; no transposed copies are made.
  *   TTGT  transpose-transpose-GEMM-transpose (Section 2; Section 6 "TTGT"):
