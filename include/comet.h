@@ -128,7 +128,7 @@ typedef enum {
 /* Which lowering a plan uses.
  *   AUTO  the planner's choice: the fused gather path, except TTGT where
  *         the autotune cache recorded it as faster for this problem class,
- *         and for native FP64 / FP32 products of 2^30 multiply-adds and more
+ *         and for native FP64 / FP32 products of 2^28 multiply-adds and more
  *         (no batch labels) whose operands only the gather path's element
  *         loads can read (their unit strides lie on different summation
  *         labels) while the TTGT matrices can be read in vectors.

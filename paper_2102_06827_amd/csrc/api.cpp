@@ -163,10 +163,11 @@ constexpr double kThroughputF64[] = {28.7, 33.5, 30.9, 41.4, 39.5, 34.2, 33.4, 3
 constexpr double kThroughputF32[] = {76.0, 70.6, 74.2, 77.0, 80.3, 69.2, 69.5};
 constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
 // Products from which a contraction whose operands only tile 1's element-load
-// kernel can gather goes through TTGT instead (MI355X: "cmia=cdmn*inad" at
-// 3072^3 2.65 -> 1.00 ms in FP64 and 2.62 -> 0.58 ms in FP32, at 1024^3
-// 0.091 -> 0.067 ms)
-constexpr double kTTGTMinMNK = 0x1p30;
+// kernel can gather goes through TTGT instead.  MI355X, "cmia=cdmn*inad",
+// gathered vs TTGT: 512^3 0.031 vs 0.034 ms (FP64), 768^3 0.063 vs 0.047,
+// 1024^3 0.21 vs 0.070, 3072^3 2.64 vs 1.00 (FP32: 0.025 vs 0.027, 0.054 vs
+// 0.039, 0.085 vs 0.050, 2.64 vs 0.59)
+constexpr double kTTGTMinMNK = 0x1p28;
 constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
 constexpr int kSkSmallSteps = 4;        // the same for latency-bound problems (tile 1)
@@ -327,6 +328,10 @@ void latency_schedule(const Analysis &an, int cus, bool vecA, bool vecB, Schedul
   const int res1 = tile_resident(an, 1, vecA, vecB), skres1 = sk_resident(an, 1, vecA, vecB);
   const int64_t blocks = skres1 > 0 ? std::min<int64_t>(C * skres1, T1 * nk / kSkSmallSteps) : 0;
   if (res1 <= 0 || T1 > C * res1 || !(blocks > T1 || T1 <= C)) return;
+  // tile 1's element-load variant: only with at least half of the CUs idle
+  // ("cmia=cdmn*inad", FP64: 64 tiles 0.039 -> 0.031 ms and 144 tiles
+  // 0.069 -> 0.064 ms split, but 256 tiles 0.094 -> 0.20 ms)
+  if (!(vecA && vecB) && 2 * T1 > C) return;
   Schedule out;
   out.tile = 1;
   out.us = 0.0;

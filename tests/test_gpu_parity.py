@@ -675,7 +675,7 @@ def test_gemv_like_contraction_is_split():
 
 def test_large_element_load_problem_goes_through_ttgt():
     """Operands whose unit strides lie on different summation labels can only
-    be gathered by tile 1's element-load kernel; from 2^30 multiply-adds the
+    be gathered by tile 1's element-load kernel; from 2^28 multiply-adds the
     planner permutes them instead (TTGT).  Sampled outputs match the oracle."""
     spec = "cmia=cdmn*inad"
     ext = dict(c=64, m=16, i=16, a=64, d=64, n=16)
