@@ -493,3 +493,50 @@ def test_gradient_adjoint_identity():
     assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
     rhs2 = float(np.sum(oracle.contract(sb, X, Y) * B))
     assert abs(lhs - rhs2) <= 1e-13 * abs(lhs)
+
+
+# ---- the error metric every GPU tolerance is measured with ----------------
+# relerr(x, ref) = ||x - ref||_F / ||ref||_F (the normwise relative error of
+# the result against the FP64 definition), with ||x - ref||_F alone when ref
+# is zero.  Hand-computed values, each chosen so that one plausible slip
+# changes the answer.
+
+def test_relerr_hand_computed_pythagorean_case():
+    # sqrt(3^2 + 4^2) / sqrt(0^2 + 4^2) = 5 / 4
+    assert oracle.relerr([3.0, 0.0], [0.0, 4.0]) == 1.25
+
+
+def test_relerr_takes_square_roots():
+    # sqrt(1 + 1) / sqrt(4) = 1/sqrt(2); without the roots it would read
+    # 2 / 4 = 0.5, with only the numerator's root sqrt(2) / 4
+    got = oracle.relerr([1.0, 1.0], [0.0, 2.0])
+    assert abs(got - 2.0 ** -0.5) < 1e-15
+
+
+def test_relerr_divides_by_the_reference_norm():
+    # |2 - 1| / |1| = 1, not |1 - 2| / |2| = 0.5: the denominator is ref's
+    assert oracle.relerr([2.0], [1.0]) == 1.0
+    assert oracle.relerr([1.0], [2.0]) == 0.5
+
+
+def test_relerr_zero_reference_is_absolute():
+    assert oracle.relerr([3.0, 4.0], [0.0, 0.0]) == 5.0
+    assert oracle.relerr([0.0, 0.0], [0.0, 0.0]) == 0.0
+
+
+def test_relerr_sums_every_element_of_a_multidimensional_array():
+    # 2 x 2 arrays: one wrong element among four; norms over all of them
+    x = np.array([[1.0, 2.0], [3.0, 5.0]])
+    ref = np.array([[1.0, 2.0], [3.0, 4.0]])
+    assert abs(oracle.relerr(x, ref) - 1.0 / np.sqrt(30.0)) < 1e-15
+    assert oracle.relerr(ref, ref) == 0.0
+
+
+def test_relerr_is_scale_invariant_and_survives_large_magnitudes():
+    # the squares of 1e200 overflow float64 but not the long double sums:
+    # the error of a relative perturbation 1e-10 must come back as 1e-10
+    ref = np.array([1e200, -1e200, 3e199])
+    x = ref * (1.0 + 1e-10)
+    got = oracle.relerr(x, ref)
+    assert abs(got - 1e-10) < 1e-14
+    assert abs(oracle.relerr(x * 1e-300, ref * 1e-300) - got) < 1e-14
