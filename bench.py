@@ -193,8 +193,28 @@ def cpu_baseline(oracle, A, B, C0, seconds_target=15.0):
     dt = time.perf_counter() - t0
     flops = FLOPS * slabs / V
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": "output slabs a < %d of %d (%.1f%% of the headline contraction, FP64, beta=1), %.1f s" %
                       (slabs, V, 100.0 * slabs / V, dt)}
+
+
+def cpu_model():
+    """The host CPU's model name as lscpu reports it (/proc/cpuinfo if lscpu is absent)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                return ln.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_modes(comet, A, B, C0, steps, warmup, want):

@@ -25,16 +25,20 @@ def grad_specs(spec):
 class ContractFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, spec, A, B, C0, alpha, beta, compute):
-        from . import contract
+        from . import contract, permute
         ctx.spec, ctx.alpha, ctx.beta, ctx.compute = spec, float(alpha), float(beta), compute
         ctx.has_c0 = C0 is not None
         ctx.save_for_backward(A, B)
-        C = C0.clone() if (C0 is not None and beta != 0.0) else None
+        C = None
+        if C0 is not None and beta != 0.0:
+            # a copy of C0 (the identity permutation), so the input stays untouched
+            c = grad_specs(spec)[0].split("=")[1].split("*")[0]
+            C = permute("%s=%s" % (c, c), C0)
         return contract(spec, A, B, C, alpha=alpha, beta=beta if C is not None else 0.0, compute=compute)
 
     @staticmethod
     def backward(ctx, dC):
-        from . import contract
+        from . import contract, permute
         A, B = ctx.saved_tensors
         dC = dC.contiguous()
         sa, sb = grad_specs(ctx.spec)
@@ -44,7 +48,10 @@ class ContractFn(torch.autograd.Function):
         if ctx.needs_input_grad[2]:
             dB = contract(sb, A, dC, alpha=ctx.alpha, compute=ctx.compute)
         if ctx.has_c0 and ctx.needs_input_grad[3]:
-            dC0 = dC * ctx.beta
+            # dC0 = beta * dC through the library's permute kernel (identity
+            # permutation with scale beta)
+            c = sa.split("=")[1].split("*")[0]
+            dC0 = permute("%s=%s" % (c, c), dC, alpha=ctx.beta)
         return None, dA, dB, dC0, None, None, None
 
 

@@ -162,17 +162,47 @@ comet_status_t upload_tables(comet_plan_s *p) {
 constexpr double kThroughputF64[] = {28.7, 33.5, 30.9, 41.4, 39.5, 34.2, 33.4, 34.2, 35.0, 34.8};
 constexpr double kThroughputF32[] = {76.0, 70.6, 74.2, 77.0, 80.3, 69.2, 69.5};
 constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
-// Products from which a contraction whose operands only tile 1's element-load
-// kernel can gather goes through TTGT instead.  MI355X, "cmia=cdmn*inad",
-// gathered vs TTGT: 512^3 0.031 vs 0.034 ms (FP64), 768^3 0.063 vs 0.047,
-// 1024^3 0.21 vs 0.070, 3072^3 2.64 vs 1.00 (FP32: 0.025 vs 0.027, 0.054 vs
-// 0.039, 0.085 vs 0.050, 2.64 vs 0.59)
-constexpr double kTTGTMinMNK = 0x1p28;
+// A contraction whose operands only tile 1's element-load kernel can gather
+// goes through TTGT when the time the vector-load GEMM saves exceeds what the
+// permutes cost.  Rates on MI355X ("cmia=cdmn*inad" at 3072^3: element-load
+// gather 2.64 ms in FP64 and 2.62 ms in FP32, the TTGT GEMM alone 1.00 and
+// 0.58 ms); permutes move their bytes at about 4.5 TB/s, and each of the up to
+// three extra launches costs about 3 us on the stream.  Measured crossover:
+// 512^3 0.031 (gather) vs 0.034 ms (TTGT) in FP64, 768^3 0.063 vs 0.047;
+// FP32 0.025 vs 0.027 and 0.054 vs 0.039.
+constexpr double kElemLoadFlops = 22.0e12;        // FLOP/s, FP64 and FP32
+constexpr double kVecGemmFlopsF64 = 58.0e12;
+constexpr double kVecGemmFlopsF32 = 100.0e12;
+constexpr double kPermuteBytesPerS = 4.5e12;
+constexpr double kPermuteLaunchS = 3.0e-6;
+constexpr size_t kTTGTMaxWorkspace = size_t(4) << 30;   // no automatic TTGT needing more
 constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
 constexpr int kSkSmallSteps = 4;        // the same for latency-bound problems (tile 1)
 constexpr double kSkBytesPerUs = 4.0e6;  // partial-sum traffic rate (HBM, both directions)
 constexpr double kSkLaunchUs = 4.0;      // the two extra launches
+
+// Estimated saving (seconds, may be negative) of TTGT plan `tt` over the
+// element-load gather of the same contraction `an`: the GEMM time saved
+// minus the permutes' traffic and launches.
+double ttgt_saving_s(const Analysis &an, const comet_plan_s &tt) {
+  const double flops = 2.0 * double(an.m) * double(an.n) * double(an.k);
+  const double vec = an.compute == COMET_COMPUTE_F64 ? kVecGemmFlopsF64 : kVecGemmFlopsF32;
+  const TTGTChoice &c = tt.an.ttgt;
+  const double es = double(elem_size(an.dtype));
+  auto count = [&](const std::string &labels) {
+    double n = 1.0;
+    for (char ch : labels)
+      n *= double(an.extents[std::find(an.labels.begin(), an.labels.end(), ch) - an.labels.begin()]);
+    return n;
+  };
+  double bytes = 0.0;
+  int launches = 0;
+  if (c.a_copy) bytes += 2.0 * es * count(an.spec_a), ++launches;
+  if (c.b_copy) bytes += 2.0 * es * count(an.spec_b), ++launches;
+  if (c.c_copy) bytes += 3.0 * es * count(an.spec_c), ++launches;   // GEMM write, then read + write
+  return flops / kElemLoadFlops - flops / vec - bytes / kPermuteBytesPerS - launches * kPermuteLaunchS;
+}
 
 int tile_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
   GettLaunch g{};
@@ -355,6 +385,9 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
     best = model_tile(an, forced_tile, tile_resident(an, forced_tile, vecA, vecB),
                       sk_resident(an, forced_tile, vecA, vecB), cus);
     best.tile = forced_tile;
+    // the element-load variant splits its summation only in the latency-bound
+    // case (see below), forced or not
+    if (!(vecA && vecB)) best.sk_tiles = best.sk_blocks = 0;
     if (forced_tile == 1) latency_schedule(an, cus, vecA, vecB, &best);
   } else {
     for (int t = 0; t < gett_tile_count(); ++t) {
@@ -522,15 +555,20 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   p->vecA_tables = tables_vec_ok(an.offAm, an.offAk, an.layoutA, an.runAm, an.runAk, VEC) && all_vec(an.offAx);
   p->vecB_tables = tables_vec_ok(an.offBn, an.offBk, an.layoutB, an.runBn, an.runBk, VEC) && all_vec(an.offBx);
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
-  if (path == COMET_PATH_AUTO && native && an.path == COMET_PATH_GETT && an.X.empty() && !an.empty_out &&
-      !an.empty_sum && !(p->vecA_tables && p->vecB_tables) &&
-      double(an.m) * double(an.n) * double(an.k) >= kTTGTMinMNK) {
-    // only tile 1's element-load kernel can gather these operands (their
-    // unit strides lie on different summation labels, or runs are ragged);
-    // on large products the permutes of TTGT cost less than that kernel
+  // Only tile 1's element-load kernel can gather these operands (their unit
+  // strides lie on different summation labels, or runs are ragged): when the
+  // estimate says the permutes of TTGT cost less than that kernel, take TTGT.
+  // This is the untuned default only: with the autotuner on it times both
+  // (or reads its cache), and a forced gather schedule keeps the gather path.
+  const bool tuning = tune && tune_cache().mode() != 0;
+  const bool gather_forced = std::getenv("COMET_GETT_TILE") || std::getenv("COMET_GETT_SK") ||
+                             std::getenv("COMET_GETT_PERSIST");
+  if (path == COMET_PATH_AUTO && native && !tuning && !gather_forced && an.path == COMET_PATH_GETT &&
+      an.X.empty() && !an.empty_out && !an.empty_sum && !(p->vecA_tables && p->vecB_tables)) {
     std::unique_ptr<comet_plan_s> tt;
     if (build_plan(tt, spec, extents, sA, sB, sC, dtype, compute, COMET_PATH_TTGT, false) == COMET_OK && tt->gemm &&
-        tt->gemm->vecA_tables && tt->gemm->vecB_tables) {
+        tt->gemm->vecA_tables && tt->gemm->vecB_tables && tt->ws_bytes <= kTTGTMaxWorkspace &&
+        ttgt_saving_s(an, *tt) > 0.0) {
       out = std::move(tt);
       return COMET_OK;
     }
@@ -879,16 +917,48 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
 
 // ---- convenience-call state: plan cache and per-device workspace ----------
 
+// A library-owned workspace of the convenience calls, one per (device,
+// stream): calls on one stream are ordered by the stream, so they may share
+// it; calls on two streams get two buffers.  `done` is recorded on the stream
+// after the last enqueued use, and a later user waits for it (on the device)
+// before touching the buffer, so a buffer whose stream handle is reused by a
+// new stream, or which is grown, is never overwritten or freed under kernels
+// still in flight.
 struct DeviceWorkspace {
   void *ptr = nullptr;
   size_t bytes = 0;
+  hipEvent_t done = nullptr;
 };
+typedef std::pair<int, hipStream_t> WsKey;
+
+// Make `w` at least `bytes` large and usable by stream s; call with the
+// lock that guards w held, and call ws_release after enqueuing the work.
+comet_status_t ws_acquire(DeviceWorkspace &w, size_t bytes, hipStream_t s) {
+  if (!w.done) HIP_TRY(hipEventCreateWithFlags(&w.done, hipEventDisableTiming), "hipEventCreate(workspace)");
+  if (bytes > w.bytes) {
+    // grow: the old buffer is freed only after its last use has completed
+    HIP_TRY(hipEventSynchronize(w.done), "hipEventSynchronize(workspace)");
+    if (w.ptr) HIP_TRY(hipFree(w.ptr), "hipFree(workspace)");
+    w.ptr = nullptr;
+    w.bytes = 0;
+    HIP_TRY(hipMalloc(&w.ptr, bytes), "hipMalloc(workspace)");
+    w.bytes = bytes;
+  } else {
+    HIP_TRY(hipStreamWaitEvent(s, w.done, 0), "hipStreamWaitEvent(workspace)");
+  }
+  return COMET_OK;
+}
+
+comet_status_t ws_release(DeviceWorkspace &w, hipStream_t s) {
+  HIP_TRY(hipEventRecord(w.done, s), "hipEventRecord(workspace)");
+  return COMET_OK;
+}
 // Plans of comet_contract, per device.  Each holds device tables, so the
 // cache is bounded: past kMaxCachedPlans distinct problems on one device it
 // waits for the device and starts over.
 constexpr size_t kMaxCachedPlans = 1024;
 std::map<int, std::map<std::string, std::unique_ptr<comet_plan_s>>> g_cache;
-std::map<int, DeviceWorkspace> g_ws;
+std::map<WsKey, DeviceWorkspace> g_ws;
 
 std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const int64_t *sA, size_t ra,
                       const int64_t *sB, size_t rb, const int64_t *sC, size_t rc, int dtype, int compute, int dev) {
@@ -1055,17 +1125,13 @@ comet_status_t comet_contract(const char *spec, const int64_t *extents, comet_dt
   } else {
     p = it->second.get();
   }
-  DeviceWorkspace &w = g_ws[dev];
-  if (p->ws_bytes > w.bytes) {
-    // grow: wait for every stream that may still use the old buffer
-    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
-    if (w.ptr) (void)hipFree(w.ptr);
-    w.ptr = nullptr;
-    w.bytes = 0;
-    HIP_TRY(hipMalloc(&w.ptr, p->ws_bytes), "hipMalloc(workspace)");
-    w.bytes = p->ws_bytes;
-  }
-  return execute(p, alpha, A, B, beta, C, w.ptr, w.bytes, s);
+  if (p->ws_bytes == 0) return execute(p, alpha, A, B, beta, C, nullptr, 0, s);
+  DeviceWorkspace &w = g_ws[WsKey(dev, s)];
+  comet_status_t rc = ws_acquire(w, p->ws_bytes, s);
+  if (rc != COMET_OK) return rc;
+  rc = execute(p, alpha, A, B, beta, C, w.ptr, w.bytes, s);
+  comet_status_t rr = ws_release(w, s);
+  return rc != COMET_OK ? rc : rr;
 }
 
 comet_status_t comet_permute(const char *spec, const int64_t *extents, comet_dtype_t dtype, double alpha,
@@ -1157,8 +1223,11 @@ comet_status_t comet_chain_plan(const char *spec, const int64_t *extents, char *
 }
 
 namespace {
-// per-device buffer for the intermediates of comet_contract_chain
-std::map<int, DeviceWorkspace> g_chain_ws;
+// per-(device, stream) buffers for the intermediates of comet_contract_chain,
+// and the lock held from the buffer's acquisition until every step of the
+// chain is enqueued (comet_contract takes g_mu itself, so this is another one)
+std::map<WsKey, DeviceWorkspace> g_chain_ws;
+std::mutex g_chain_mu;
 }  // namespace
 
 comet_status_t comet_contract_chain(const char *spec, const int64_t *extents, comet_dtype_t dtype,
@@ -1189,22 +1258,15 @@ comet_status_t comet_contract_chain(const char *spec, const int64_t *extents, co
     total += align256(std::max<size_t>(cnt, 1) * es);
   }
   char *inter = nullptr;
+  std::unique_lock<std::mutex> lk(g_chain_mu);
+  DeviceWorkspace *w = nullptr;
   if (total > 0) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_mu);
-    DeviceWorkspace &w = g_chain_ws[dev];
-    if (total > w.bytes) {
-      if (w.ptr) {
-        HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
-        HIP_TRY(hipFree(w.ptr), "hipFree(chain intermediates)");
-        w.ptr = nullptr;
-        w.bytes = 0;
-      }
-      HIP_TRY(hipMalloc(&w.ptr, total), "hipMalloc(chain intermediates)");
-      w.bytes = total;
-    }
-    inter = static_cast<char *>(w.ptr);
+    w = &g_chain_ws[WsKey(dev, s)];
+    comet_status_t rc = ws_acquire(*w, total, s);
+    if (rc != COMET_OK) return rc;
+    inter = static_cast<char *>(w->ptr);
   }
   const int ns = int(cp.steps.size());
   std::vector<const void *> ptr(size_t(n) + size_t(ns), nullptr);
@@ -1227,11 +1289,14 @@ comet_status_t comet_contract_chain(const char *spec, const int64_t *extents, co
     comet_status_t rc = comet_contract(stp.spec.c_str(), ext.data(), dtype, compute, last ? alpha : 1.0,
                                        ptr[stp.left], str[stp.left], ptr[stp.right], str[stp.right],
                                        last ? beta : 0.0, out, last ? strides_C : nullptr, stream);
-    if (rc != COMET_OK) return rc;
+    if (rc != COMET_OK) {
+      if (w) (void)ws_release(*w, s);
+      return rc;
+    }
     ptr[n + i] = out;
     str[n + i] = nullptr;
   }
-  return COMET_OK;
+  return w ? ws_release(*w, s) : COMET_OK;
 }
 
 comet_status_t comet_fill(int rank, const int64_t *extents, comet_dtype_t dtype, double value, void *out,
@@ -1330,7 +1395,12 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
     for (int64_t e = 0; e < a.nb; ++e) order.push_back(first[i] + e);
     total += a.nb * ((a.m + kBatchTile - 1) / kBatchTile) * ((a.n + kBatchTile - 1) / kBatchTile);
   }
-  if (total > INT32_MAX) return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 tiles");
+  // the device work counter is an int that every persistent workgroup
+  // increments once more after the list is drained: keep total + grid below
+  // 2^31 (the grid is at most one workgroup per CU slot, far below kMaxGrid)
+  constexpr int64_t kMaxGrid = int64_t(1) << 20;
+  if (total > int64_t(INT32_MAX) - kMaxGrid)
+    return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 - 2^20 output tiles");
   bytes += align256(sizeof(BatchItem) * std::max<int64_t>(total, 1));
   for (int i = 0; i < n; ++i) {
     tab_off[i] = bytes;

@@ -296,3 +296,22 @@ def test_autotune_configuration(tmp_path):
     assert L.comet_autotune(None, 0) == OK
     assert L.comet_autotune(None, 3) == UNSUP
     assert L.comet_autotune(None, -1) == UNSUP
+
+
+def test_batch_rejects_tile_counts_near_the_work_counter_range():
+    """The persistent batch kernel's work counter is a 32-bit int that every
+    workgroup increments once past the end of the list: a batch whose 64 x 64
+    output tiles come within 2^20 of 2^31 is refused on the host, before any
+    device call (the pointers below are never dereferenced)."""
+    import paper_2102_06827_amd as m
+    L = m.lib()
+    # ab = ak * kb with a = b = 2^22 + 64: (2^16 + 1)^2 tiles > 2^31 - 2^20
+    n = (1 << 22) + 64
+    spec = b"ab=ak*kb"
+    ext = (ctypes.c_int64 * 3)(n, n, 1)
+    arr = (m._Problem * 1)()
+    arr[0] = m._Problem(spec, ext, None, None, None, 1.0, 0.0, 16, 32, 48)
+    h = ctypes.c_void_p()
+    rc = L.comet_batch_create(ctypes.byref(h), 1, arr, 1, 0)
+    assert rc == UNSUP
+    assert b"2^31 - 2^20" in L.comet_last_error()
