@@ -225,24 +225,44 @@ comet_status_t comet_analyze(const char *spec, const int64_t *extents,
 
 /*
  * Batch API: n independent contractions in ONE persistent kernel launch.
- * Workgroups take (problem, tile) items from a device work list ordered by
- * decreasing cost, so many small, uneven problems fill the GPU together.
+ * Every problem gets a tile class (64 x 64, 128 x 64, 64 x 128 or 128 x 128
+ * outputs per workgroup; element-load problems and FP64 use the classes
+ * their kernels have): COMET_BATCH_CLASS=<class> forces one, the autotuner
+ * (comet_autotune on) times the classes per problem class (storage dtype,
+ * compute, operand layouts, power-of-two buckets of the flattened sizes) on
+ * a batch of copies of a representative problem and caches the winner, and
+ * otherwise a throughput model picks the class.  The work list is cut into
+ * one queue per XCD; whole problems go to queues by longest processing time
+ * first, heaviest first within a queue, each problem's tiles in groups of
+ * tile rows.  Workgroups take (problem, tile) items from their XCD's queue
+ * through a device counter and move on to the other queues once it is
+ * drained, so many small, uneven problems fill the GPU together.  A problem
+ * whose operands only the element-load kernel could gather (their unit
+ * strides on different summation labels) gets a dense copy of one operand,
+ * held by the batch and refreshed by every execute before the launch, in a
+ * label order both operands can be read from in 16-byte vectors
+ * (COMET_BATCH_COPY=0 keeps the element-load kernel instead).
  * All problems share dtype and compute; compute must be the storage type's
  * native MFMA (DEFAULT, or F64 / F32 matching the dtype), or SPLIT_BF16X3
  * with FP32 storage (operands split into three bfloat16 slices inside the
  * loader).  Problems with an empty summation or alpha == 0 are scaled by
  * beta before the launch.  A problem with batch labels contributes one
  * problem per batch entry to the work list (at most 2^22 problems and batch
- * entries in all, COMET_ERR_UNSUPPORTED beyond).  The workspace holds the work
- * counter (256 bytes).
+ * entries in all, COMET_ERR_UNSUPPORTED beyond; at most 2^31 - 2^20 output
+ * tiles).  The workspace holds the eight queue counters (256 bytes); its
+ * contents on entry do not matter.
  * comet_batch_create plans every problem and uploads the work list and
  * offset tables (not capturable); comet_batch_execute is capturable.
+ * comet_batch_describe writes JSON: output tiles, persistent grid, mode,
+ * problems per tile class, items per queue, how many classes came from the
+ * autotuner and how many operand copies run before the launch.
  */
 comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_problem_t *problems,
                                   comet_dtype_t dtype, comet_compute_t compute);
 comet_status_t comet_batch_workspace_size(comet_batch_t batch, size_t *bytes);
 comet_status_t comet_batch_execute(comet_batch_t batch, void *workspace, size_t ws_bytes,
                                    void *stream);
+comet_status_t comet_batch_describe(comet_batch_t batch, char *buf, size_t len);
 comet_status_t comet_batch_destroy(comet_batch_t batch);
 
 /*
@@ -299,10 +319,19 @@ comet_status_t comet_fill(int rank, const int64_t *extents, comet_dtype_t dtype,
                           const int64_t *strides, void *stream);
 
 /*
- * Autotuner.  mode 0: off (heuristic tiles); 1: use the cache at cache_path
- * and time candidates for problem classes it does not hold, appending them;
- * 2: re-time everything.  A corrupt cache file is ignored and rewritten.
- * cache_path NULL uses $COMET_TUNE_CACHE or ~/.cache/comet_tune.json.
+ * Autotuner (Section 6: tile sizes chosen for the memory hierarchy, here by
+ * timing on the device).  mode 0: off (heuristic tiles); 1: use the cache at
+ * cache_path and time candidates for problem classes it does not hold,
+ * appending them; 2: re-time everything.  What is timed: for a plan, every
+ * compiled gather tile (each with its stream-K split) and up to 32 TTGT
+ * flattenings of the native modes; for a split mode, the slice-pair product's
+ * tiles (the 128 x 64 and 192 x 192 products of the classic splits, and the
+ * fused and sliced BF16x3 paths on FP32 storage); for a batch, the tile
+ * classes per problem class.  Each candidate runs once to warm up, then five
+ * timed runs on nonzero operands; the fastest is recorded.  A corrupt cache
+ * file is ignored and rewritten.  cache_path NULL uses $COMET_TUNE_CACHE or
+ * ~/.cache/comet_tune.json.  Before the first call the mode is the one the
+ * environment variable COMET_AUTOTUNE names (off, on, force), off if unset.
  */
 comet_status_t comet_autotune(const char *cache_path, int mode);
 

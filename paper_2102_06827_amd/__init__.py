@@ -40,6 +40,7 @@ SYMBOLS = [
     "comet_contract", "comet_plan_create", "comet_plan_create_ex", "comet_plan_workspace_size",
     "comet_plan_execute", "comet_plan_destroy", "comet_plan_describe", "comet_analyze",
     "comet_batch_create", "comet_batch_workspace_size", "comet_batch_execute", "comet_batch_destroy",
+    "comet_batch_describe",
     "comet_permute", "comet_fill", "comet_chain_plan", "comet_contract_chain", "comet_autotune", "comet_set_split_slices", "comet_set_int8_slices", "comet_last_error",
     "comet_version",
 ]
@@ -99,6 +100,7 @@ def lib():
         L.comet_batch_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.comet_batch_execute.argtypes = [P, P, ctypes.c_size_t, P]
         L.comet_batch_destroy.argtypes = [P]
+        L.comet_batch_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         L.comet_permute.argtypes = [S, I64P, I, D, P, I64P, D, P, I64P, P]
         L.comet_fill.argtypes = [I, I64P, I, D, P, I64P, P]
         L.comet_chain_plan.argtypes = [S, I64P, ctypes.c_char_p, ctypes.c_size_t]
@@ -415,6 +417,11 @@ class Batch:
         wp = ctypes.c_void_p(ws.data_ptr()) if ws is not None else None
         wn = ws.numel() if ws is not None else 0
         _check(lib().comet_batch_execute(self._h, wp, wn, _stream_handle(stream)))
+
+    def describe(self):
+        buf = ctypes.create_string_buffer(1 << 12)
+        _check(lib().comet_batch_describe(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def __del__(self):
         try:

@@ -69,6 +69,12 @@ std::vector<int64_t> dense_strides(const std::vector<int64_t> &ext) {
 
 }  // namespace
 
+namespace comet {
+// Record an error for comet_last_error (used by the other translation units
+// of the C ABI).
+comet_status_t api_fail(comet_status_t code, const std::string &msg) { return fail(code, msg); }
+}  // namespace comet
+
 struct comet_plan_s {
   Analysis an;
   int device = 0;
@@ -108,11 +114,19 @@ struct comet_batch_s {
   const BatchDesc *descs = nullptr;
   const BatchItem *items = nullptr;
   int64_t total = 0;
+  BatchQueues queues{};            // the work list cut into one queue per XCD
+  std::vector<int> classes;        // descriptors per tile class
+  int tuned = 0;                   // descriptors whose class came from the autotuner
   int grid = 1;
   std::vector<ScaleJob> scales;    // empty summation or alpha == 0: C = beta * C
+  // element-load problems: one operand copied, before the launch, into a
+  // dense order that both operands can read in vectors (pbuf, owned here)
+  void *pbuf = nullptr;
+  std::vector<PermuteLaunch> perms;
 
   ~comet_batch_s() {
     if (dbuf) (void)hipFree(dbuf);
+    if (pbuf) (void)hipFree(pbuf);
   }
 };
 
@@ -167,14 +181,15 @@ constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
 // permutes cost.  Rates on MI355X ("cmia=cdmn*inad" at 3072^3: element-load
 // gather 2.64 ms in FP64 and 2.62 ms in FP32, the TTGT GEMM alone 1.00 and
 // 0.58 ms); permutes move their bytes at about 4.5 TB/s, and each of the up to
-// three extra launches costs about 3 us on the stream.  Measured crossover:
+// three extra launches costs about 5 us on small problems (its launch gap
+// and its ramp).  Measured crossover:
 // 512^3 0.031 (gather) vs 0.034 ms (TTGT) in FP64, 768^3 0.063 vs 0.047;
 // FP32 0.025 vs 0.027 and 0.054 vs 0.039.
 constexpr double kElemLoadFlops = 22.0e12;        // FLOP/s, FP64 and FP32
 constexpr double kVecGemmFlopsF64 = 58.0e12;
 constexpr double kVecGemmFlopsF32 = 100.0e12;
 constexpr double kPermuteBytesPerS = 4.5e12;
-constexpr double kPermuteLaunchS = 3.0e-6;
+constexpr double kPermuteLaunchS = 5.0e-6;
 constexpr size_t kTTGTMaxWorkspace = size_t(4) << 30;   // no automatic TTGT needing more
 constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
@@ -428,6 +443,7 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
                           const TTGTChoice *forced_ttgt = nullptr);
 comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
                              const int64_t *sA, const int64_t *sB, const int64_t *sC);
+hipError_t fill_value(void *p, int64_t n, int dt, double value, hipStream_t s);
 comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
                         hipStream_t s, void *ws);
 comet_status_t execute(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
@@ -770,7 +786,10 @@ std::string arch_id(int device) {
   return a;
 }
 
-// Time fn on stream s: one warm-up, then the best of three runs (microseconds).
+// Time fn on stream s: one warm-up, then the best of kTimedReps runs
+// (microseconds).
+constexpr int kTimedReps = 5;
+
 template <typename F>
 double time_us(F fn, hipStream_t s, bool *ok) {
   hipEvent_t e0, e1;
@@ -782,7 +801,7 @@ double time_us(F fn, hipStream_t s, bool *ok) {
   }
   double best = 1e30;
   bool good = fn() == COMET_OK;
-  for (int r = 0; good && r < 3; ++r) {
+  for (int r = 0; good && r < kTimedReps; ++r) {
     (void)hipEventRecord(e0, s);
     good = fn() == COMET_OK;
     (void)hipEventRecord(e1, s);
@@ -796,6 +815,70 @@ double time_us(F fn, hipStream_t s, bool *ok) {
   return best;
 }
 
+// The classic splits (BF16x3, FP16x2): time the slice-pair product's
+// 128 x 64 and 192 x 192 tiles and, for FP32 storage in BF16x3, the fused
+// kernel; record the fastest (entry tile 0, 1, or 2 for fused) per problem
+// class and apply it.  Called with the cache lock held.
+comet_status_t autotune_split(comet_plan_s *p, TuneCache &tc) {
+  Analysis &an = p->an;
+  const std::string key = tune_key(an, arch_id(p->device));
+  const bool can_fuse = an.compute == COMET_COMPUTE_SPLIT_BF16X3 && an.dtype == COMET_F32;
+  auto apply = [&](int choice) -> comet_status_t {
+    p->fused3 = choice == 2 && can_fuse;
+    if (p->fused3) {
+      p->split = SplitPlan();
+      p->ws_bytes = 0;
+      return COMET_OK;
+    }
+    Status st = split_prepare(an, p->split, choice < 0 ? -1 : choice == 1 ? 1 : 0);
+    if (!st.ok()) return fail(st);
+    p->ws_bytes = p->split.ws_bytes;
+    return COMET_OK;
+  };
+  TuneEntry best;
+  if (tc.mode() == 1 && tc.lookup(key, &best) && best.tile >= 0 && best.tile <= 2) return apply(best.tile);
+  const size_t es = elem_size(an.dtype);
+  const int dt = an.dtype == COMET_F64 ? 0 : 1;
+  void *bufA = nullptr, *bufB = nullptr, *bufC = nullptr, *ws = nullptr;
+  size_t wsb = 0;
+  hipStream_t s = nullptr;
+  bool ok = hipStreamCreate(&s) == hipSuccess && hipMalloc(&bufA, std::max<int64_t>(an.sizeA, 1) * es) == hipSuccess &&
+            hipMalloc(&bufB, std::max<int64_t>(an.sizeB, 1) * es) == hipSuccess &&
+            hipMalloc(&bufC, std::max<int64_t>(an.sizeC, 1) * es) == hipSuccess;
+  best = TuneEntry{-1, COMET_PATH_GETT, 1e30};
+  if (ok) {
+    (void)fill_value(bufA, std::max<int64_t>(an.sizeA, 1), dt, 0.5, s);
+    (void)fill_value(bufB, std::max<int64_t>(an.sizeB, 1), dt, -0.25, s);
+    for (int choice = 0; choice <= (can_fuse ? 2 : 1); ++choice) {
+      if (apply(choice) != COMET_OK) continue;
+      if (p->ws_bytes > wsb) {
+        if (ws) (void)hipFree(ws);
+        ws = nullptr;
+        wsb = 0;
+        if (hipMalloc(&ws, p->ws_bytes) != hipSuccess) continue;
+        wsb = p->ws_bytes;
+      }
+      bool good;
+      const comet_plan_s *pp = p;
+      const double us = time_us([&]() { return execute(pp, 1.0, bufA, bufB, 0.0, bufC, ws, wsb, s); }, s, &good);
+      if (good && us < best.us) best = TuneEntry{choice, COMET_PATH_GETT, us};
+    }
+    (void)hipStreamSynchronize(s);
+  }
+  if (bufA) (void)hipFree(bufA);
+  if (bufB) (void)hipFree(bufB);
+  if (bufC) (void)hipFree(bufC);
+  if (ws) (void)hipFree(ws);
+  if (s) (void)hipStreamDestroy(s);
+  if (best.tile < 0) {
+    // tuning not possible: the size rule's choice
+    p->fused3 = can_fuse && double(an.m) * double(an.n) * double(an.k) * double(an.nb) < kFused3MaxMNK;
+    return apply(p->fused3 ? 2 : -1);
+  }
+  tc.store(key, best);
+  return apply(best.tile);
+}
+
 comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
                              const int64_t *sA, const int64_t *sB, const int64_t *sC) {
   Analysis &an = p->an;
@@ -804,6 +887,10 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) cus = 256;
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
+  const bool classic = an.compute == COMET_COMPUTE_SPLIT_BF16X3 || an.compute == COMET_COMPUTE_SPLIT_FP16X2;
+  if (tc.mode() != 0 && classic && !an.empty_out && !an.empty_sum && an.X.empty() && !std::getenv("COMET_SPLIT_TILE") &&
+      !std::getenv("COMET_FUSED3"))
+    return autotune_split(p.get(), tc);
   if (tc.mode() == 0 || !native || an.empty_out || an.empty_sum) return COMET_OK;
   if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH") || std::getenv("COMET_GETT_SK") ||
       std::getenv("COMET_GETT_PERSIST"))
@@ -826,8 +913,10 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
               hipMalloc(&bufC, std::max<int64_t>(an.sizeC, 1) * es) == hipSuccess &&
               (wsb == 0 || hipMalloc(&ws, wsb) == hipSuccess);
     if (ok) {
-      (void)hipMemsetAsync(bufA, 0, std::max<int64_t>(an.sizeA, 1) * es, s);
-      (void)hipMemsetAsync(bufB, 0, std::max<int64_t>(an.sizeB, 1) * es, s);
+      // nonzero operands (the time of a product does not depend on the values,
+      // but zeros could take shortcuts in future kernels)
+      (void)fill_value(bufA, std::max<int64_t>(an.sizeA, 1), an.dtype == COMET_F64 ? 0 : 1, 0.5, s);
+      (void)fill_value(bufB, std::max<int64_t>(an.sizeB, 1), an.dtype == COMET_F64 ? 0 : 1, -0.25, s);
       best.us = 1e30;
       void *skws = nullptr;
       size_t skws_bytes = 0;
@@ -911,6 +1000,278 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
   if (best.tile >= 0 && best.tile < gett_tile_count()) {
     apply_schedule(p.get(), cus, best.tile);
     p->ws_bytes = p->sk_bytes;
+  }
+  return COMET_OK;
+}
+
+// ---- batch: dense copies for element-load problems --------------------------
+
+// A problem whose operands only the element-load kernel can gather (their
+// unit strides lie on different summation labels, or runs are ragged) gets a
+// dense copy of one operand X (the smaller first) in a label order that makes
+// both operands readable in vectors: X's free labels in their order, then
+// the summation labels in the order of the other operand's strides (so both
+// share the unit-stride summation label), or the summation labels first.
+// The copy's analysis replaces the problem's; `which` is 0 for A, 1 for B.
+struct BatchCopy {
+  int which = -1;
+  std::string order;            // labels of the copy, outermost first
+  std::vector<int64_t> ext;     // their extents
+  int64_t count = 0;            // elements
+};
+
+bool batch_copy_choice(const comet_problem_t &pr, const Analysis &a, comet_dtype_t dtype, comet_compute_t compute,
+                       int VEC, Analysis &out, BatchCopy &cp) {
+  if (!a.X.empty() || a.empty_out || a.empty_sum) return false;
+  const std::string &la = a.spec_a, &lb = a.spec_b, &lc = a.spec_c;
+  auto ext_of = [&](char ch) {
+    return a.extents[std::find(a.labels.begin(), a.labels.end(), ch) - a.labels.begin()];
+  };
+  auto strides_of = [&](const std::string &l, const int64_t *given) {
+    std::vector<int64_t> e;
+    for (char ch : l) e.push_back(ext_of(ch));
+    return given ? std::vector<int64_t>(given, given + l.size()) : dense_strides(e);
+  };
+  const std::vector<int64_t> sa = strides_of(la, pr.strides_A), sb = strides_of(lb, pr.strides_B);
+  const std::vector<int64_t> sc = strides_of(lc, pr.strides_C);
+  auto count = [&](const std::string &l) {
+    int64_t n = 1;
+    for (char ch : l) n *= ext_of(ch);
+    return n;
+  };
+  const int first = count(la) <= count(lb) ? 0 : 1;
+  for (int t = 0; t < 2; ++t) {
+    const int which = t == 0 ? first : 1 - first;
+    const std::string &lx = which == 0 ? la : lb, &ly = which == 0 ? lb : la;
+    const std::vector<int64_t> &sx = which == 0 ? sa : sb, &sy = which == 0 ? sb : sa;
+    // X's free labels by X's strides, summation labels by Y's, outermost first
+    std::vector<std::pair<int64_t, char>> fx, ky;
+    for (size_t q = 0; q < lx.size(); ++q)
+      if (lc.find(lx[q]) != std::string::npos) fx.push_back({-sx[q], lx[q]});
+    for (size_t q = 0; q < ly.size(); ++q)
+      if (lx.find(ly[q]) != std::string::npos && lc.find(ly[q]) == std::string::npos) ky.push_back({-sy[q], ly[q]});
+    std::stable_sort(fx.begin(), fx.end());
+    std::stable_sort(ky.begin(), ky.end());
+    std::string f, k;
+    for (auto &v : fx) f += v.second;
+    for (auto &v : ky) k += v.second;
+    for (const std::string &order : {f + k, k + f}) {
+      std::vector<int64_t> e;
+      for (char ch : order) e.push_back(ext_of(ch));
+      const std::vector<int64_t> d = dense_strides(e);
+      std::vector<int64_t> sxn(lx.size());
+      for (size_t q = 0; q < lx.size(); ++q) sxn[q] = d[order.find(lx[q])];
+      Analysis na;
+      const Status st = analyze(pr.spec, pr.extents, which == 0 ? sxn.data() : sa.data(),
+                                which == 1 ? sxn.data() : sb.data(), sc.data(), dtype, compute, COMET_PATH_GETT,
+                                g_split_slices, na, g_int8_slices);
+      if (!st.ok()) continue;
+      if (tables_vec_ok(na.offAm, na.offAk, na.layoutA, na.runAm, na.runAk, VEC) &&
+          tables_vec_ok(na.offBn, na.offBk, na.layoutB, na.runBn, na.runBk, VEC)) {
+        out = na;
+        cp.which = which;
+        cp.order = order;
+        cp.ext = e;
+        cp.count = count(lx);
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+// ---- batch tile classes -------------------------------------------------------
+
+// Output elements per unit time of each batch tile class relative to the
+// 64 x 64 class, for the native and the fused BF16x3 kernels (the untuned
+// choice; the autotuner replaces it with timings).
+constexpr double kBatchRateNative[kBatchClasses] = {1.0, 1.12, 1.12, 1.25};
+constexpr double kBatchRateFused[kBatchClasses] = {1.0, 1.3, 1.3, 1.7};
+
+// Modeled time of a descriptor in class `cls`: its padded output area times
+// its summation length over the class's rate.
+double batch_class_cost(const BatchDesc &d, int cls, int mode) {
+  int bm, bn;
+  batch_class_shape(cls, &bm, &bn);
+  const double area = double((d.M + bm - 1) / bm) * bm * double((d.N + bn - 1) / bn) * bn;
+  return area * double(d.K) / (mode == 1 ? kBatchRateFused[cls] : kBatchRateNative[cls]);
+}
+
+int batch_model_class(const BatchDesc &d, int dt, int mode) {
+  const bool vec = d.variant < 4;
+  int best = 0;
+  double bc = batch_class_cost(d, 0, mode);
+  for (int c = 1; c < kBatchClasses; ++c) {
+    if (!batch_class_valid(c, dt, mode, vec)) continue;
+    const double x = batch_class_cost(d, c, mode);
+    if (x < bc * 0.999) {
+      best = c;
+      bc = x;
+    }
+  }
+  return best;
+}
+
+comet_status_t batch_tune_classes(const std::vector<Analysis> &an, const std::vector<int64_t> &first,
+                                  const std::vector<char> &live, std::vector<BatchDesc> &descs, int dt, int mode);
+
+// The tile class of every live descriptor: COMET_BATCH_CLASS forces one
+// (where it exists for the descriptor), else the autotuner's timings when it
+// is on, else the model.
+comet_status_t batch_choose_classes(const std::vector<Analysis> &an, const std::vector<int64_t> &first,
+                                    const std::vector<char> &live, std::vector<BatchDesc> &descs, int dt,
+                                    int mode) {
+  const char *env = std::getenv("COMET_BATCH_CLASS");
+  const int forced = (env && *env) ? std::atoi(env) : -1;
+  for (size_t j = 0; j < descs.size(); ++j) {
+    BatchDesc &d = descs[j];
+    if (!live[j]) continue;
+    if (forced >= 0)
+      d.cls = batch_class_valid(forced, dt, mode, d.variant < 4) ? forced : 0;
+    else
+      d.cls = batch_model_class(d, dt, mode);
+  }
+  if (forced < 0 && tune_cache().mode() != 0) return batch_tune_classes(an, first, live, descs, dt, mode);
+  return COMET_OK;
+}
+
+// Fill n elements of dtype dt at p with `value` (the fill form of the
+// permute kernel), so that timed runs see nonzero operands.
+hipError_t fill_value(void *p, int64_t n, int dt, double value, hipStream_t s) {
+  PermuteLaunch pl{};
+  pl.ndim = 1;
+  pl.ext[0] = n;
+  pl.s_in[0] = pl.s_out[0] = 1;
+  pl.in = pl.out = p;
+  pl.alpha = pl.beta = 0.0;
+  pl.dtype = dt;
+  pl.fill = value;
+  return launch_permute(pl, s);
+}
+
+// Time every tile class that exists for the live descriptors' problem
+// classes the cache does not hold (or all, in mode 2) and record the fastest.
+// A class is timed on a batch of R copies of the problem's first live
+// descriptor (operands filled with nonzero values, alpha 1, beta 0, every
+// copy writing the same output), R chosen so that the copies' tiles fill
+// several rounds of the persistent grid: the per-problem time then measures
+// the class's throughput inside a full GPU, as in the batch, not the latency
+// of one problem alone.  One warm-up, then the best of kTuneReps runs.
+comet_status_t batch_tune_classes(const std::vector<Analysis> &an, const std::vector<int64_t> &first,
+                                  const std::vector<char> &live, std::vector<BatchDesc> &descs, int dt, int mode) {
+  TuneCache &tc = tune_cache();
+  std::lock_guard<std::mutex> lk(tc.mutex());
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device), "hipGetDevice");
+  const std::string arch = arch_id(device);
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
+  const int64_t slots = int64_t(cus) * batch_blocks_per_cu(dt, mode);
+  std::map<std::string, int> decided;
+  // the problem each descriptor belongs to
+  std::vector<int> owner(descs.size(), 0);
+  for (size_t i = 0; i + 1 < first.size(); ++i)
+    for (int64_t j = first[i]; j < first[i + 1]; ++j) owner[size_t(j)] = int(i);
+  const size_t es = dt == 0 ? 8 : 4;
+  for (size_t j = 0; j < descs.size(); ++j) {
+    if (!live[j]) continue;
+    BatchDesc &d = descs[j];
+    const std::string key = batch_tune_key(dt, mode, d.variant, d.M, d.N, d.K, arch);
+    auto hit = decided.find(key);
+    if (hit != decided.end()) {
+      d.cls = hit->second;
+      continue;
+    }
+    TuneEntry e;
+    if (tc.mode() == 1 && tc.lookup(key, &e) && batch_class_valid(e.tile, dt, mode, d.variant < 4)) {
+      decided[key] = d.cls = e.tile;
+      continue;
+    }
+    // time the classes on copies of this descriptor's problem
+    const Analysis &a = an[size_t(owner[j])];
+    void *buf = nullptr;
+    hipStream_t s = nullptr;
+    size_t offs[6], tb = 0;
+    const std::vector<int64_t> *tabs[6] = {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn};
+    for (int t = 0; t < 6; ++t) {
+      offs[t] = tb;
+      tb += align256(std::max<size_t>(tabs[t]->size(), 1) * sizeof(int64_t));
+    }
+    const int64_t nA = std::max<int64_t>(a.swapped ? a.sizeB : a.sizeA, 1);
+    const int64_t nB = std::max<int64_t>(a.swapped ? a.sizeA : a.sizeB, 1);
+    const int64_t nC = std::max<int64_t>(a.sizeC, 1);
+    const size_t oA = tb, oB = oA + align256(nA * es), oC = oB + align256(nB * es), oD = oC + align256(nC * es);
+    const size_t oI = oD + align256(sizeof(BatchDesc));
+    // items: at most enough copies for 4 rounds of the grid, at most 2^22 items
+    int64_t max_items = 0;
+    for (int c = 0; c < kBatchClasses; ++c) {
+      if (!batch_class_valid(c, dt, mode, d.variant < 4)) continue;
+      int bm, bn;
+      batch_class_shape(c, &bm, &bn);
+      const int64_t tiles = ((d.M + bm - 1) / bm) * ((d.N + bn - 1) / bn);
+      const int64_t R = std::max<int64_t>(1, (4 * slots + tiles - 1) / tiles);
+      max_items = std::max(max_items, std::min<int64_t>(R * tiles, std::max<int64_t>(tiles, int64_t(1) << 22)));
+    }
+    const size_t total_bytes = oI + align256(sizeof(BatchItem) * size_t(max_items)) + 256;
+    bool ok = hipStreamCreate(&s) == hipSuccess && hipMalloc(&buf, total_bytes) == hipSuccess;
+    int best = d.cls;
+    double best_us = 1e30;
+    if (ok) {
+      char *b = static_cast<char *>(buf);
+      std::vector<char> host(oA, 0);
+      for (int t = 0; t < 6; ++t)
+        if (!tabs[t]->empty()) std::memcpy(host.data() + offs[t], tabs[t]->data(), tabs[t]->size() * sizeof(int64_t));
+      ok = hipMemcpy(b, host.data(), oA, hipMemcpyHostToDevice) == hipSuccess &&
+           fill_value(b + oA, nA, dt, 0.5, s) == hipSuccess && fill_value(b + oB, nB, dt, -0.25, s) == hipSuccess;
+      BatchDesc td = d;
+      td.A = b + oA;
+      td.B = b + oB;
+      td.C = b + oC;
+      td.alpha = 1.0;
+      td.beta = 0.0;
+      auto T = [&](int t) { return reinterpret_cast<const int64_t *>(b + offs[t]); };
+      td.t = GettTables{T(0), T(1), T(2), T(3), T(4), T(5)};
+      for (int c = 0; ok && c < kBatchClasses; ++c) {
+        if (!batch_class_valid(c, dt, mode, d.variant < 4)) continue;
+        int bm, bn;
+        batch_class_shape(c, &bm, &bn);
+        td.cls = c;
+        td.tilesN = int((d.N + bn - 1) / bn);
+        const int64_t tiles = ((d.M + bm - 1) / bm) * td.tilesN;
+        const int64_t R = std::max<int64_t>(1, std::min<int64_t>((4 * slots + tiles - 1) / tiles,
+                                                                 max_items / std::max<int64_t>(tiles, 1)));
+        std::vector<BatchItem> items(size_t(R * tiles));
+        BatchQueues q{};
+        for (int qi = 0; qi <= kBatchQueues; ++qi) q.off[qi] = (R * tiles) * qi / kBatchQueues;
+        for (int64_t r = 0; r < R; ++r)
+          for (int64_t t = 0; t < tiles; ++t) items[size_t(r * tiles + t)] = BatchItem{0, int(t)};
+        if (hipMemcpy(b + oD, &td, sizeof(td), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b + oI, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
+          ok = false;
+          break;
+        }
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(R * tiles, slots)));
+        int *cnt = reinterpret_cast<int *>(b + total_bytes - 256);
+        bool good;
+        const double us = time_us(
+            [&]() {
+              return launch_batch(reinterpret_cast<const BatchDesc *>(b + oD), reinterpret_cast<const BatchItem *>(b + oI),
+                                  q, cnt, dt, mode, grid, s) == hipSuccess
+                         ? COMET_OK
+                         : COMET_ERR_HIP;
+            },
+            s, &good);
+        if (good && us / double(R) < best_us) {
+          best_us = us / double(R);
+          best = c;
+        }
+      }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (buf) (void)hipFree(buf);
+    if (s) (void)hipStreamDestroy(s);
+    if (ok && best_us < 1e30) tc.store(key, TuneEntry{best, COMET_PATH_GETT, best_us});
+    decided[key] = d.cls = best;
   }
   return COMET_OK;
 }
@@ -1352,7 +1713,6 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
   if (n > 0 && !problems) return fail(COMET_ERR_NULL_POINTER, "problems is NULL");
   std::unique_ptr<comet_batch_s> b(new comet_batch_s());
   b->dtype = dtype;
-  const int VEC = dtype == COMET_F64 ? 2 : 4;
   std::vector<Analysis> an(n);
   for (int i = 0; i < n; ++i) {
     const comet_problem_t &pr = problems[i];
@@ -1375,6 +1735,30 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
     if (reads && (pr.C == pr.A || pr.C == pr.B))
       return fail(COMET_ERR_UNSUPPORTED, "problem " + std::to_string(i) + ": C aliases an input");
   }
+  // dense copies of one operand of each element-load problem (COMET_BATCH_COPY=0
+  // keeps the element-load kernel for them)
+  const int VEC = dtype == COMET_F64 ? 2 : 4;
+  std::vector<BatchCopy> copies(n);
+  std::vector<size_t> copy_off(n, 0);
+  size_t copy_bytes = 0;
+  {
+    const char *env = std::getenv("COMET_BATCH_COPY");
+    const bool allow = !(env && *env && std::atoi(env) == 0);
+    for (int i = 0; allow && i < n; ++i) {
+      const Analysis &a = an[i];
+      const comet_problem_t &pr = problems[i];
+      if (a.empty_out || a.empty_sum || pr.alpha == 0.0) continue;
+      if (tables_vec_ok(a.offAm, a.offAk, a.layoutA, a.runAm, a.runAk, VEC) &&
+          tables_vec_ok(a.offBn, a.offBk, a.layoutB, a.runBn, a.runBk, VEC))
+        continue;
+      Analysis na;
+      if (batch_copy_choice(pr, a, dtype, compute, VEC, na, copies[i])) {
+        an[i] = na;
+        copy_off[i] = copy_bytes;
+        copy_bytes += align256(size_t(copies[i].count) * elem_size(dtype));
+      }
+    }
+  }
   // one descriptor per batch entry of each problem (a problem without batch
   // labels has one); device buffer: descriptors, work items, then every
   // problem's six tables and its C batch table
@@ -1385,35 +1769,115 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
   if (nd > kMaxEntries) return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^22 problems and batch entries");
   std::vector<BatchDesc> descs(static_cast<size_t>(nd));
   std::vector<size_t> tab_off(n, 0);
-  size_t bytes = align256(sizeof(BatchDesc) * std::max<int64_t>(nd, 1));
-  const size_t items_off = bytes;
-  int64_t total = 0;
-  std::vector<int64_t> order;
+  std::vector<char> live(size_t(nd), 0);   // descriptors with work (some output and a nonzero product)
   for (int i = 0; i < n; ++i) {
     const Analysis &a = an[i];
     if (a.empty_out || a.empty_sum || problems[i].alpha == 0.0) continue;
-    for (int64_t e = 0; e < a.nb; ++e) order.push_back(first[i] + e);
-    total += a.nb * ((a.m + kBatchTile - 1) / kBatchTile) * ((a.n + kBatchTile - 1) / kBatchTile);
+    for (int64_t e = 0; e < a.nb; ++e) live[size_t(first[i] + e)] = 1;
   }
-  // the device work counter is an int that every persistent workgroup
-  // increments once more after the list is drained: keep total + grid below
-  // 2^31 (the grid is at most one workgroup per CU slot, far below kMaxGrid)
-  constexpr int64_t kMaxGrid = int64_t(1) << 20;
-  if (total > int64_t(INT32_MAX) - kMaxGrid)
-    return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 - 2^20 output tiles");
-  bytes += align256(sizeof(BatchItem) * std::max<int64_t>(total, 1));
+  size_t bytes = align256(sizeof(BatchDesc) * std::max<int64_t>(nd, 1));
   for (int i = 0; i < n; ++i) {
     tab_off[i] = bytes;
     const Analysis &a = an[i];
     for (const std::vector<int64_t> *v : {&a.offAm, &a.offAk, &a.offBk, &a.offBn, &a.offCm, &a.offCn, &a.offCx})
       bytes += align256(std::max<size_t>(v->size(), 1) * sizeof(int64_t));
   }
+  const size_t es = elem_size(dtype);
+  const int dt = dtype == COMET_F64 ? 0 : 1;
+  // descriptors (table pointers are filled in once the buffer exists)
+  std::vector<std::vector<char>> host_tabs(n);
+  for (int i = 0; i < n; ++i) {
+    const Analysis &a = an[i];
+    const comet_problem_t &pr = problems[i];
+    const double alpha = dtype == COMET_F32 ? double(float(pr.alpha)) : pr.alpha;
+    const double beta = dtype == COMET_F32 ? double(float(pr.beta)) : pr.beta;
+    // a copied operand: its pointer is set once the copy buffer exists (256-byte aligned)
+    const void *oA = copies[i].which == 0 ? reinterpret_cast<const void *>(uintptr_t(256)) : pr.A;
+    const void *oB = copies[i].which == 1 ? reinterpret_cast<const void *>(uintptr_t(256)) : pr.B;
+    const void *pa = a.swapped ? oB : oA, *pb = a.swapped ? oA : oB;
+    const bool vec_tables = tables_vec_ok(a.offAm, a.offAk, a.layoutA, a.runAm, a.runAk, VEC) &&
+                            tables_vec_ok(a.offBn, a.offBk, a.layoutB, a.runBn, a.runBk, VEC);
+    for (int64_t e = 0; e < (a.empty_out ? 1 : a.nb); ++e) {
+      BatchDesc &d = descs[size_t(first[i] + e)];
+      const bool bx = !a.offAx.empty() && !a.empty_out;
+      d.A = pa ? static_cast<const char *>(pa) + (bx ? a.offAx[e] * es : 0) : nullptr;
+      d.B = pb ? static_cast<const char *>(pb) + (bx ? a.offBx[e] * es : 0) : nullptr;
+      d.C = pr.C ? static_cast<char *>(pr.C) + (bx ? a.offCx[e] * es : 0) : nullptr;
+      d.M = a.m;
+      d.N = a.n;
+      d.K = a.k;
+      d.alpha = alpha;
+      d.beta = beta;
+      const bool vec = vec_tables && reinterpret_cast<uintptr_t>(d.A) % 16 == 0 &&
+                       reinterpret_cast<uintptr_t>(d.B) % 16 == 0;
+      d.variant = a.layoutA * 2 + a.layoutB + (vec ? 0 : 4);
+      d.cls = 0;
+    }
+  }
+  // tile class of every live descriptor: the autotuner's, else the model's
+  comet_status_t crc = batch_choose_classes(an, first, live, descs, dt, b->mode);
+  if (crc != COMET_OK) return crc;
+  {
+    const char *env = std::getenv("COMET_BATCH_CLASS");
+    if (!(env && *env) && tune_cache().mode() != 0)
+      for (size_t j = 0; j < live.size(); ++j) b->tuned += live[j] ? 1 : 0;
+  }
+  int64_t total = 0;
+  for (int64_t j = 0; j < nd; ++j) {
+    BatchDesc &d = descs[size_t(j)];
+    int bm, bn;
+    batch_class_shape(d.cls, &bm, &bn);
+    d.tilesN = int((d.N + bn - 1) / bn);
+    if (live[size_t(j)]) total += ((d.M + bm - 1) / bm) * d.tilesN;
+  }
+  // the device work counters are ints that every persistent workgroup
+  // increments once more after a queue is drained: keep total + grid below
+  // 2^31 (the grid is at most one workgroup per CU slot, far below kMaxGrid)
+  constexpr int64_t kMaxGrid = int64_t(1) << 20;
+  if (total > int64_t(INT32_MAX) - kMaxGrid)
+    return fail(COMET_ERR_UNSUPPORTED, "batch has more than 2^31 - 2^20 output tiles");
+  const size_t items_off = bytes;
+  bytes += align256(sizeof(BatchItem) * std::max<int64_t>(total, 1));
   HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
   HIP_TRY(hipMalloc(&b->dbuf, bytes), "hipMalloc(batch)");
+  if (copy_bytes > 0) {
+    HIP_TRY(hipMalloc(&b->pbuf, copy_bytes), "hipMalloc(batch copies)");
+    for (int i = 0; i < n; ++i) {
+      const BatchCopy &cp = copies[i];
+      if (cp.which < 0) continue;
+      char *dst = static_cast<char *>(b->pbuf) + copy_off[i];
+      const Analysis &a = an[i];
+      const bool dst_is_A = (cp.which == 0) != a.swapped;   // after the A/B exchange
+      BatchDesc &d = descs[size_t(first[i])];
+      if (dst_is_A)
+        d.A = dst;
+      else
+        d.B = dst;
+      // the copy: out[order] = in[original labels, caller strides]
+      const comet_problem_t &pr = problems[i];
+      const std::string &lx = cp.which == 0 ? a.spec_a : a.spec_b;
+      const int64_t *given = cp.which == 0 ? pr.strides_A : pr.strides_B;
+      std::vector<int64_t> ex;
+      for (char ch : lx) ex.push_back(cp.ext[cp.order.find(ch)]);
+      const std::vector<int64_t> sin = given ? std::vector<int64_t>(given, given + lx.size()) : dense_strides(ex);
+      const PermuteDesc pd = make_permute(cp.order, dense_strides(cp.ext), lx, sin, cp.ext);
+      PermuteLaunch pl{};
+      pl.ndim = int(pd.ext.size());
+      for (int q = 0; q < pl.ndim; ++q) {
+        pl.ext[q] = pd.ext[q];
+        pl.s_in[q] = pd.s_in[q];
+        pl.s_out[q] = pd.s_out[q];
+      }
+      pl.in = cp.which == 0 ? pr.A : pr.B;
+      pl.out = dst;
+      pl.alpha = 1.0;
+      pl.beta = 0.0;
+      pl.dtype = dtype == COMET_F64 ? 0 : 1;
+      b->perms.push_back(pl);
+    }
+  }
   std::vector<char> host(bytes, 0);
   char *dev = static_cast<char *>(b->dbuf);
-  const size_t es = elem_size(dtype);
-  std::vector<int64_t> kof(size_t(nd), 0);   // summation length of each descriptor
   for (int i = 0; i < n; ++i) {
     const Analysis &a = an[i];
     const comet_problem_t &pr = problems[i];
@@ -1425,49 +1889,65 @@ comet_status_t comet_batch_create(comet_batch_t *batch, int n, const comet_probl
       ptr[k++] = reinterpret_cast<const int64_t *>(dev + off);
       off += align256(std::max<size_t>(v->size(), 1) * sizeof(int64_t));
     }
-    const double alpha = dtype == COMET_F32 ? double(float(pr.alpha)) : pr.alpha;
-    const double beta = dtype == COMET_F32 ? double(float(pr.beta)) : pr.beta;
-    const void *pa = a.swapped ? pr.B : pr.A, *pb = a.swapped ? pr.A : pr.B;
-    const bool vec_tables = tables_vec_ok(a.offAm, a.offAk, a.layoutA, a.runAm, a.runAk, VEC) &&
-                            tables_vec_ok(a.offBn, a.offBk, a.layoutB, a.runBn, a.runBk, VEC);
-    for (int64_t e = 0; e < (a.empty_out ? 1 : a.nb); ++e) {
-      BatchDesc &d = descs[size_t(first[i] + e)];
-      const bool bx = !a.offAx.empty() && !a.empty_out;
-      d.A = pa ? static_cast<const char *>(pa) + (bx ? a.offAx[e] * es : 0) : nullptr;
-      d.B = pb ? static_cast<const char *>(pb) + (bx ? a.offBx[e] * es : 0) : nullptr;
-      d.C = pr.C ? static_cast<char *>(pr.C) + (bx ? a.offCx[e] * es : 0) : nullptr;
-      d.t = GettTables{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5]};
-      d.M = a.m;
-      d.N = a.n;
-      d.K = a.k;
-      d.alpha = alpha;
-      d.beta = beta;
-      const bool vec = vec_tables && reinterpret_cast<uintptr_t>(d.A) % 16 == 0 &&
-                       reinterpret_cast<uintptr_t>(d.B) % 16 == 0;
-      d.variant = a.layoutA * 2 + a.layoutB + (vec ? 0 : 4);
-      d.tilesN = int((a.n + kBatchTile - 1) / kBatchTile);
-      kof[size_t(first[i] + e)] = a.k;
-    }
-    if (!a.empty_out && (a.empty_sum || pr.alpha == 0.0))
+    for (int64_t e = 0; e < (a.empty_out ? 1 : a.nb); ++e)
+      descs[size_t(first[i] + e)].t = GettTables{ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5]};
+    if (!a.empty_out && (a.empty_sum || pr.alpha == 0.0)) {
+      const double beta = dtype == COMET_F32 ? double(float(pr.beta)) : pr.beta;
       b->scales.push_back({pr.C, ptr[4], ptr[5], a.m, a.n, beta, a.offCx.empty() ? nullptr : ptr[6], a.nb});
+    }
   }
-  // longest summation first, so the heaviest tiles start early
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return kof[size_t(x)] > kof[size_t(y)]; });
-  BatchItem *items = reinterpret_cast<BatchItem *>(host.data() + items_off);
-  int64_t w = 0;
-  for (int64_t j : order) {
+  // queues: whole descriptors to the least-loaded queue, heaviest first
+  // (longest processing time first); in each queue the heaviest first, and
+  // a descriptor's tiles in groups of kGroup tile rows, so that the
+  // workgroups working at one time share operand rows and columns
+  std::vector<int64_t> order;
+  std::vector<double> cost(size_t(nd), 0.0);
+  for (int64_t j = 0; j < nd; ++j) {
+    if (!live[size_t(j)]) continue;
+    order.push_back(j);
     const BatchDesc &d = descs[size_t(j)];
-    const int64_t tiles = ((d.M + kBatchTile - 1) / kBatchTile) * d.tilesN;
-    for (int64_t t = 0; t < tiles; ++t) items[w++] = BatchItem{int(j), int(t)};
+    int bm, bn;
+    batch_class_shape(d.cls, &bm, &bn);
+    cost[size_t(j)] = double((d.M + bm - 1) / bm) * double(d.tilesN) * bm * bn * double(d.K);
   }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[size_t(x)] > cost[size_t(y)]; });
+  std::vector<std::vector<int64_t>> qlist(kBatchQueues);
+  std::vector<double> load(kBatchQueues, 0.0);
+  for (int64_t j : order) {
+    const int qmin = int(std::min_element(load.begin(), load.end()) - load.begin());
+    qlist[size_t(qmin)].push_back(j);
+    load[size_t(qmin)] += cost[size_t(j)];
+  }
+  BatchItem *items = reinterpret_cast<BatchItem *>(host.data() + items_off);
+  constexpr int kGroup = 4;
+  int64_t w = 0;
+  for (int qi = 0; qi < kBatchQueues; ++qi) {
+    b->queues.off[qi] = w;
+    for (int64_t j : qlist[size_t(qi)]) {
+      const BatchDesc &d = descs[size_t(j)];
+      int bm, bn;
+      batch_class_shape(d.cls, &bm, &bn);
+      const int64_t tm_ = (d.M + bm - 1) / bm, tn_ = d.tilesN;
+      for (int64_t id = 0; id < tm_ * tn_; ++id) {
+        const int64_t per = kGroup * tn_, group = id / per, first_row = group * kGroup;
+        const int64_t gsize = std::min<int64_t>(kGroup, tm_ - first_row);
+        const int64_t in = id - group * per;
+        const int64_t tm = first_row + in % gsize, tn = in / gsize;
+        items[w++] = BatchItem{int(j), int(tm * tn_ + tn)};
+      }
+    }
+  }
+  b->queues.off[kBatchQueues] = w;
   if (nd > 0 && n > 0) std::memcpy(host.data(), descs.data(), sizeof(BatchDesc) * size_t(nd));
   HIP_TRY(hipMemcpy(b->dbuf, host.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy(batch)");
   b->descs = reinterpret_cast<const BatchDesc *>(dev);
   b->items = reinterpret_cast<const BatchItem *>(dev + items_off);
   b->total = total;
+  b->classes.assign(kBatchClasses, 0);
+  for (int64_t j : order) b->classes[size_t(descs[size_t(j)].cls)] += 1;
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, b->device), "hipGetDeviceProperties");
-  const int64_t resident = int64_t(prop.multiProcessorCount) * batch_blocks_per_cu(dtype == COMET_F64 ? 0 : 1, b->mode);
+  const int64_t resident = int64_t(prop.multiProcessorCount) * batch_blocks_per_cu(dt, b->mode);
   b->grid = int(std::max<int64_t>(1, std::min<int64_t>(total, resident)));
   *batch = b.release();
   return COMET_OK;
@@ -1487,9 +1967,25 @@ comet_status_t comet_batch_execute(comet_batch_t batch, void *workspace, size_t 
     HIP_TRY(launch_scale(sc.C, batch->dtype == COMET_F64 ? 0 : 1, sc.offCm, sc.offCn, sc.m, sc.n, sc.beta, s,
                          sc.offCb, sc.nb),
             "batch scale");
-  HIP_TRY(launch_batch(batch->descs, batch->items, batch->total, static_cast<int *>(workspace),
+  for (const PermuteLaunch &pl : batch->perms) HIP_TRY(launch_permute(pl, s), "batch operand copy");
+  HIP_TRY(launch_batch(batch->descs, batch->items, batch->queues, static_cast<int *>(workspace),
                        batch->dtype == COMET_F64 ? 0 : 1, batch->mode, batch->grid, s),
           "batch launch");
+  return COMET_OK;
+}
+
+comet_status_t comet_batch_describe(comet_batch_t batch, char *buf, size_t len) {
+  if (!batch || !buf || !len) return fail(COMET_ERR_NULL_POINTER, "NULL argument");
+  std::string js = "{\"tiles\":" + std::to_string(batch->total) + ",\"grid\":" + std::to_string(batch->grid) +
+                   ",\"mode\":" + std::to_string(batch->mode) + ",\"classes\":[";
+  for (size_t c = 0; c < batch->classes.size(); ++c) js += (c ? "," : "") + std::to_string(batch->classes[c]);
+  js += "],\"queues\":[";
+  for (int q = 0; q < kBatchQueues; ++q)
+    js += (q ? "," : "") + std::to_string(batch->queues.off[q + 1] - batch->queues.off[q]);
+  js += "],\"tuned\":" + std::to_string(batch->tuned) + ",\"copies\":" + std::to_string(batch->perms.size()) + "}";
+  std::strncpy(buf, js.c_str(), len - 1);
+  buf[len - 1] = 0;
+  if (js.size() + 1 > len) return fail(COMET_ERR_WORKSPACE, "describe buffer too small");
   return COMET_OK;
 }
 

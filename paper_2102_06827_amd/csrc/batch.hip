@@ -1,20 +1,27 @@
 // batch.hip -- many independent contractions in one persistent launch, and
 // the fused BF16x3 gather product.
 //
-// Persistent launch: the host lists every (problem, 64 x 64 output tile)
-// pair, problems with the longest summation first (longest-processing-time
-// order), and starts as many workgroups as stay resident on the GPU.  Each
-// workgroup repeatedly takes the next item from a device counter and runs the
-// gather tile routine for that problem's layout variant, until the list is
-// exhausted -- every workgroup reaches that exit.  Uneven, small problems
-// thus fill the machine together instead of one under-filled launch each.
-// The counter is reset by a one-thread kernel in the same stream, so the
-// whole batch is capturable into a HIP graph.
+// Persistent launch: the host lists every (problem, output tile) pair, each
+// problem with the tile class the autotuner (or, untuned, a throughput
+// model) chose for it, and starts as many workgroups as stay resident on the
+// GPU.  The list is cut into one queue per XCD: the host hands whole problems
+// to queues by longest-processing-time first, so that the workgroups of one
+// XCD work on the same problems and find their operand panels in that XCD's
+// L2, and within a queue the heaviest problems come first and each problem's
+// tiles are walked in groups of tile rows.  Each workgroup takes the next
+// item of its XCD's queue from a device counter, runs the gather tile routine
+// for that problem's class and layout variant, and once its queue is drained
+// moves on to the next queue -- every workgroup reaches the exit after at
+// most one failed take per queue.  Uneven, small problems thus fill the
+// machine together instead of one under-filled launch each.  The counters
+// are reset by a one-workgroup kernel in the same stream, so the whole batch
+// is capturable into a HIP graph.
 //
 // Fused BF16x3: FP32 operands are split in the loader, x = b0 + b1 + b2 with
 // b0 = bf16(x) and b1, b2 the bf16 of the remainders (exact for FP32 x), and
 // the six products b_p c_q with p + q <= 2 run on v_mfma_f32_16x16x32_bf16
 // with FP32 accumulation -- no slice workspace and no extra pass.
+#include <climits>
 #include <type_traits>
 
 #include "gather.hpp"
@@ -27,28 +34,32 @@ using namespace gather;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int TB = kBatchTile;    // 64 x 64 output tiles
-constexpr int NT = 256;           // 4 waves, 2 x 2, each 32 x 32
+constexpr int TB = 64;            // the stand-alone fused kernel's 64 x 64 output tiles
+constexpr int NT = 256;           // 4 waves, 2 x 2
 constexpr int F3_BK = 32;         // one 16x16x32 MFMA step
 constexpr int F3_LDK = F3_BK + 8;  // LDS pitch in bf16 (80 bytes: conflict-free 16-byte reads)
-constexpr int F3_LDS = 2 * 3 * TB * F3_LDK;   // A and B, three slices (bf16 elements)
+template <int BM, int BN>
+constexpr int f3_lds() { return 3 * (BM + BN) * F3_LDK; }   // A and B, three slices (bf16 elements)
 
-template <int LA, int LB, bool V>
+// One BM x BN output tile of the fused BF16x3 product; 2 x 2 waves, each
+// (BM / 2) x (BN / 2) made of 16 x 16 blocks.
+template <int BM, int BN, int LA, int LB, bool V>
 __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const float *__restrict__ B,
                                             float *__restrict__ C, const GettTables &t, int64_t M, int64_t N,
                                             int64_t K, double alpha, double beta, int64_t m0, int64_t n0,
                                             __bf16 *smem) {
-  typedef Loader<float, float, TB, F3_BK, LA, V, NT> LoadA;
-  typedef Loader<float, float, TB, F3_BK, LB, V, NT> LoadB;
+  typedef Loader<float, float, BM, F3_BK, LA, V, NT> LoadA;
+  typedef Loader<float, float, BN, F3_BK, LB, V, NT> LoadB;
+  constexpr int FM = BM / 32, FN = BN / 32;
   lds_t<__bf16> *const sA = to_lds(smem);
-  lds_t<__bf16> *const sB = sA + 3 * TB * F3_LDK;
+  lds_t<__bf16> *const sB = sA + 3 * BM * F3_LDK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
-  f4_t acc[2][2];
+  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  f4_t acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
   LoadA la;
   LoadB lb;
   la.init(tid, m0, M, t.offAm);
@@ -68,27 +79,27 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
     lb.load(B, (step + 1) * F3_BK, K);
     la.fetch_k(t.offAk, (step + 2) * F3_BK, K);
     lb.fetch_k(t.offBk, (step + 2) * F3_BK, K);
-    bf16x8 bF[3][2];
+    bf16x8 bF[3][FN];
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < FN; ++j)
         bF[q][j] = *reinterpret_cast<const lds_t<bf16x8> *>(
-            &sB[(q * TB + wn0 + j * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
+            &sB[(q * BN + wn0 + j * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-      bf16x8 aF[2];
+      bf16x8 aF[FM];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
         aF[i] = *reinterpret_cast<const lds_t<bf16x8> *>(
-            &sA[(p * TB + wm0 + i * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
+            &sA[(p * BM + wm0 + i * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         if (p + q <= 2) {
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < FN; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aF[i], bF[q][j], acc[i][j], 0, 0, 0);
         }
       }
@@ -100,86 +111,139 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
   }
   // the epilogue of the gather kernels (C offsets staged in LDS, which the
   // loop above no longer reads)
-  WaveTile<float, TB, TB, 2, 2> w;
+  WaveTile<float, BM, BN, 2, 2> w;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) w.acc[i][j] = acc[i][j];
-  gett_store<float, float, TB, TB, 2, 2>(w, C, t, M, N, alpha, beta, m0, n0, reinterpret_cast<float *>(smem));
+    for (int j = 0; j < FN; ++j) w.acc[i][j] = acc[i][j];
+  gett_store<float, float, BM, BN, 2, 2>(w, C, t, M, N, alpha, beta, m0, n0, reinterpret_cast<float *>(smem));
 }
 
 template <int LA, int LB, bool V>
 __global__ __launch_bounds__(NT) void fused3_kernel(const float *__restrict__ A, const float *__restrict__ B,
                                                     float *__restrict__ C, GettTables t, int64_t M, int64_t N,
                                                     int64_t K, double alpha, double beta, int tilesM, int tilesN) {
-  __shared__ __attribute__((aligned(16))) __bf16 smem[F3_LDS];
+  __shared__ __attribute__((aligned(16))) __bf16 smem[f3_lds<TB, TB>()];
   int tm, tn;
   tile_coords(blockIdx.x, tilesM, tilesN, &tm, &tn);
-  fused3_tile<LA, LB, V>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * TB, int64_t(tn) * TB, smem);
+  fused3_tile<TB, TB, LA, LB, V>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * TB, int64_t(tn) * TB, smem);
 }
 
 // ---------------------------------------------------------------- batch ----
 
+// tile classes: BM x BN, 2 x 2 waves
+struct ClassShape {
+  int bm, bn;
+};
+constexpr ClassShape kClass[kBatchClasses] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
+
+// which classes exist: element loads in class 0 only, and the larger
+// classes for native FP32 only.  Every class of one kernel shares its
+// register allocation, which the largest class sets: FP32 fits all four in
+// 256 registers (two workgroups per CU) without spilling, while the FP64
+// and fused BF16x3 kernels spill with any class beyond 64 x 64.
+constexpr bool class_ok(int cls, int dtype, int mode, bool vec) {
+  return cls == 0 || (vec && dtype == 1 && mode == 0);
+}
+
+template <typename T, int LA, int LB, bool V, int CLS>
+constexpr int native_lds_one() {
+  return int(sizeof(T)) * gett_lds_elems<T, T, kClass[CLS].bm, kClass[CLS].bn, 16, NT, LA, LB, V, V>();
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+template <typename T, int CLS>
+constexpr int native_lds_cls() {
+  return cmax(cmax(native_lds_one<T, 0, 0, true, CLS>(), native_lds_one<T, 0, 1, true, CLS>()),
+              cmax(native_lds_one<T, 1, 0, true, CLS>(), native_lds_one<T, 1, 1, true, CLS>()));
+}
 template <typename T>
 constexpr int native_lds_bytes() {
-  // the largest of the eight layout/vector variants of the 64 x 64 tile
-  return int(sizeof(T)) * gett_lds_elems<T, T, TB, TB, 16, NT, 0, 0, true, true>();
+  // the largest layout/vector variant of every class the dtype has
+  return sizeof(T) == 4 ? cmax(cmax(native_lds_cls<T, 0>(), native_lds_cls<T, 1>()),
+                               cmax(native_lds_cls<T, 2>(), native_lds_cls<T, 3>()))
+                        : native_lds_cls<T, 0>();
+}
+constexpr int fused_lds_bytes() { return int(sizeof(__bf16)) * f3_lds<64, 64>(); }
+
+template <typename T, int MODE, int CLS, int LA, int LB, bool V>
+__device__ __forceinline__ void run_item(const BatchDesc &d, int tile, char *smem) {
+  constexpr int BM = kClass[CLS].bm, BN = kClass[CLS].bn;
+  const int64_t m0 = int64_t(tile / d.tilesN) * BM, n0 = int64_t(tile % d.tilesN) * BN;
+  if constexpr (MODE == 0) {
+    gett_tile<T, T, BM, BN, 16, 2, 2, LA, LB, V, V>(static_cast<const T *>(d.A), static_cast<const T *>(d.B),
+                                                    static_cast<T *>(d.C), d.t, d.M, d.N, d.K, d.alpha, d.beta, m0,
+                                                    n0, reinterpret_cast<T *>(smem));
+  } else {
+    fused3_tile<BM, BN, LA, LB, V>(static_cast<const float *>(d.A), static_cast<const float *>(d.B),
+                                   static_cast<float *>(d.C), d.t, d.M, d.N, d.K, d.alpha, d.beta, m0, n0,
+                                   reinterpret_cast<__bf16 *>(smem));
+  }
 }
 
-template <typename T, int LA, int LB, bool V>
-__device__ __forceinline__ void native_item(const BatchDesc &d, int64_t m0, int64_t n0, char *smem) {
-  gett_tile<T, T, TB, TB, 16, 2, 2, LA, LB, V, V>(static_cast<const T *>(d.A), static_cast<const T *>(d.B),
-                                                  static_cast<T *>(d.C), d.t, d.M, d.N, d.K, d.alpha, d.beta, m0,
-                                                  n0, reinterpret_cast<T *>(smem));
-}
-
-template <int LA, int LB, bool V>
-__device__ __forceinline__ void fused_item(const BatchDesc &d, int64_t m0, int64_t n0, char *smem) {
-  fused3_tile<LA, LB, V>(static_cast<const float *>(d.A), static_cast<const float *>(d.B), static_cast<float *>(d.C),
-                         d.t, d.M, d.N, d.K, d.alpha, d.beta, m0, n0, reinterpret_cast<__bf16 *>(smem));
-}
-
-template <typename T, int MODE, int LA, int LB, bool V>
-__device__ __forceinline__ void run_item(const BatchDesc &d, int64_t m0, int64_t n0, char *smem) {
-  if constexpr (MODE == 0)
-    native_item<T, LA, LB, V>(d, m0, n0, smem);
-  else
-    fused_item<LA, LB, V>(d, m0, n0, smem);
+// the four layout variants of one class with vector loads
+template <typename T, int MODE, int CLS>
+__device__ __forceinline__ void run_vec(const BatchDesc &d, int tile, char *smem) {
+  switch (d.variant) {
+    case 0: run_item<T, MODE, CLS, 0, 0, true>(d, tile, smem); break;
+    case 1: run_item<T, MODE, CLS, 0, 1, true>(d, tile, smem); break;
+    case 2: run_item<T, MODE, CLS, 1, 0, true>(d, tile, smem); break;
+    default: run_item<T, MODE, CLS, 1, 1, true>(d, tile, smem); break;
+  }
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(NT) void batch_kernel(const BatchDesc *__restrict__ descs,
-                                                   const BatchItem *__restrict__ items, int64_t total,
-                                                   int *__restrict__ counter) {
-  constexpr int LDS = MODE == 0 ? native_lds_bytes<T>() : int(sizeof(__bf16)) * F3_LDS;
+__device__ __forceinline__ void run_any(const BatchDesc &d, int tile, char *smem) {
+  constexpr int dt = sizeof(T) == 8 ? 0 : 1;
+  if (d.variant >= 4) {
+    switch (d.variant) {
+      case 4: run_item<T, MODE, 0, 0, 0, false>(d, tile, smem); break;
+      case 5: run_item<T, MODE, 0, 0, 1, false>(d, tile, smem); break;
+      case 6: run_item<T, MODE, 0, 1, 0, false>(d, tile, smem); break;
+      default: run_item<T, MODE, 0, 1, 1, false>(d, tile, smem); break;
+    }
+    return;
+  }
+  switch (d.cls) {
+    case 1: if constexpr (class_ok(1, dt, MODE, true)) { run_vec<T, MODE, 1>(d, tile, smem); return; } break;
+    case 2: if constexpr (class_ok(2, dt, MODE, true)) { run_vec<T, MODE, 2>(d, tile, smem); return; } break;
+    case 3: if constexpr (class_ok(3, dt, MODE, true)) { run_vec<T, MODE, 3>(d, tile, smem); return; } break;
+    default: break;
+  }
+  run_vec<T, MODE, 0>(d, tile, smem);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT, 2) void batch_kernel(const BatchDesc *__restrict__ descs,
+                                                   const BatchItem *__restrict__ items, BatchQueues q,
+                                                   int *__restrict__ counters) {
+  constexpr int LDS = MODE == 0 ? native_lds_bytes<T>() : fused_lds_bytes();
   __shared__ __attribute__((aligned(16))) char smem[LDS];
   __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+  // the XCD this workgroup runs on (workgroups are dealt to the XCDs in turn)
+  int queue = int(blockIdx.x % kBatchQueues);
+  for (int drained = 0; drained < kBatchQueues;) {
+    const int64_t len = q.off[queue + 1] - q.off[queue];
+    if (threadIdx.x == 0) s_item = len > 0 ? atomicAdd(&counters[queue], 1) : INT_MAX;
     __syncthreads();
     // the item index is the same in every lane: say so, so that the item and
     // its descriptor are read with scalar loads into scalar registers
     const int64_t item = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
-    if (item >= total) break;   // every workgroup ends here once the list is drained
-    const BatchItem w = items[item];
-    const BatchDesc d = descs[__builtin_amdgcn_readfirstlane(w.problem)];
-    const int64_t m0 = int64_t(w.tile / d.tilesN) * TB, n0 = int64_t(w.tile % d.tilesN) * TB;
-    switch (d.variant) {
-      case 0: run_item<T, MODE, 0, 0, true>(d, m0, n0, smem); break;
-      case 1: run_item<T, MODE, 0, 1, true>(d, m0, n0, smem); break;
-      case 2: run_item<T, MODE, 1, 0, true>(d, m0, n0, smem); break;
-      case 3: run_item<T, MODE, 1, 1, true>(d, m0, n0, smem); break;
-      case 4: run_item<T, MODE, 0, 0, false>(d, m0, n0, smem); break;
-      case 5: run_item<T, MODE, 0, 1, false>(d, m0, n0, smem); break;
-      case 6: run_item<T, MODE, 1, 0, false>(d, m0, n0, smem); break;
-      default: run_item<T, MODE, 1, 1, false>(d, m0, n0, smem); break;
+    if (item >= len) {   // this queue is drained (its counter only grows): the next one
+      queue = (queue + 1) % kBatchQueues;
+      ++drained;
+      continue;
     }
+    const BatchItem w = items[q.off[queue] + item];
+    const BatchDesc d = descs[__builtin_amdgcn_readfirstlane(w.problem)];
+    run_any<T, MODE>(d, w.tile, smem);
     __syncthreads();   // the next item's loads may not overwrite LDS still being read
   }
 }
 
-__global__ void reset_counter_kernel(int *counter) { *counter = 0; }
+__global__ void reset_counters_kernel(int *counters) {
+  if (threadIdx.x < kBatchQueues) counters[threadIdx.x] = 0;
+}
 
 template <int LA, int LB>
 hipError_t fused_l(const GettLaunch &g, hipStream_t s, dim3 grid, int tilesM, int tilesN) {
@@ -209,6 +273,16 @@ hipError_t launch_fused_bf16x3(const GettLaunch &g, hipStream_t s) {
   }
 }
 
+void batch_class_shape(int cls, int *bm, int *bn) {
+  const int c = (cls >= 0 && cls < kBatchClasses) ? cls : 0;
+  *bm = kClass[c].bm;
+  *bn = kClass[c].bn;
+}
+
+bool batch_class_valid(int cls, int dtype, int mode, bool vec) {
+  return cls >= 0 && cls < kBatchClasses && class_ok(cls, dtype, mode, vec);
+}
+
 int batch_blocks_per_cu(int dtype, int mode) {
   int n = 0;
   hipError_t e;
@@ -221,17 +295,17 @@ int batch_blocks_per_cu(int dtype, int mode) {
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-hipError_t launch_batch(const BatchDesc *descs, const BatchItem *items, int64_t total, int *counter, int dtype,
-                        int mode, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-  if (total <= 0) return hipGetLastError();
+hipError_t launch_batch(const BatchDesc *descs, const BatchItem *items, const BatchQueues &q, int *counters,
+                        int dtype, int mode, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, counters);
+  if (q.off[kBatchQueues] <= 0) return hipGetLastError();
   if (mode == 1) {
     if (dtype != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((batch_kernel<float, 1>), dim3(grid), dim3(NT), 0, s, descs, items, total, counter);
+    hipLaunchKernelGGL((batch_kernel<float, 1>), dim3(grid), dim3(NT), 0, s, descs, items, q, counters);
   } else if (dtype == 0) {
-    hipLaunchKernelGGL((batch_kernel<double, 0>), dim3(grid), dim3(NT), 0, s, descs, items, total, counter);
+    hipLaunchKernelGGL((batch_kernel<double, 0>), dim3(grid), dim3(NT), 0, s, descs, items, q, counters);
   } else {
-    hipLaunchKernelGGL((batch_kernel<float, 0>), dim3(grid), dim3(NT), 0, s, descs, items, total, counter);
+    hipLaunchKernelGGL((batch_kernel<float, 0>), dim3(grid), dim3(NT), 0, s, descs, items, q, counters);
   }
   return hipGetLastError();
 }

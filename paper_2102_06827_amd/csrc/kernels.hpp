@@ -80,18 +80,33 @@ struct BatchDesc {
   int64_t M, N, K;
   double alpha, beta;
   int variant;         // layoutA * 2 + layoutB, + 4 for element (non-vector) loads
-  int tilesN;          // 64 x 64 tiles along N
+  int cls;             // tile class (batch_class_shape); element loads: class 0 only
+  int tilesN;          // output tiles of the class along N
 };
 struct BatchItem {
   int problem;
-  int tile;
+  int tile;            // tm * tilesN + tn in the problem's class
 };
-// mode 0: native MFMA of the storage type; 1: fused BF16x3 (FP32 storage)
-hipError_t launch_batch(const BatchDesc *descs, const BatchItem *items, int64_t total, int *counter, int dtype,
-                        int mode, int grid, hipStream_t s);
+// The work list is cut into kBatchQueues queues, queue q holding items
+// off[q] .. off[q + 1] - 1; the workgroups on XCD x (x = workgroup id mod 8)
+// start with queue x and move on to the next queue once one is drained.
+constexpr int kBatchQueues = 8;
+struct BatchQueues {
+  int64_t off[kBatchQueues + 1];
+};
+// Tile classes of the batched kernel (4 waves each, 2 x 2): 0: 64 x 64,
+// 1: 128 x 64, 2: 64 x 128, 3: 128 x 128.
+constexpr int kBatchClasses = 4;
+void batch_class_shape(int cls, int *bm, int *bn);
+// whether tile class `cls` is compiled for storage dtype (0 = FP64, 1 = FP32),
+// mode (0: native MFMA, 1: fused BF16x3) and vector or element loads
+bool batch_class_valid(int cls, int dtype, int mode, bool vec);
+// mode 0: native MFMA of the storage type; 1: fused BF16x3 (FP32 storage).
+// counters: kBatchQueues ints (reset inside the launch sequence).
+hipError_t launch_batch(const BatchDesc *descs, const BatchItem *items, const BatchQueues &q, int *counters,
+                        int dtype, int mode, int grid, hipStream_t s);
 // persistent workgroups per CU for the batched kernel
 int batch_blocks_per_cu(int dtype, int mode);
-constexpr int kBatchTile = 64;
 
 // C[offCb[b] + offCm[m] + offCn[n]] = beta * C over NB batch entries
 // (offCb == nullptr: NB must be 1 and offCb[0] reads as 0); beta == 0 writes

@@ -921,7 +921,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-Status split_prepare(const Analysis &an, SplitPlan &sp) {
+Status split_prepare(const Analysis &an, SplitPlan &sp, int force_tile) {
   sp = SplitPlan();
   sp.mode = an.compute == COMET_COMPUTE_SPLIT_BF16     ? 0
             : an.compute == COMET_COMPUTE_SPLIT_BF16X3 ? 1
@@ -940,6 +940,7 @@ Status split_prepare(const Analysis &an, SplitPlan &sp) {
     sp.tile = (an.m >= 1536 && an.n >= 1536 && waste <= 1.1) ? 1 : 0;
     const char *env = std::getenv("COMET_SPLIT_TILE");
     if (env && *env) sp.tile = std::atoi(env) == 1 ? 1 : 0;
+    if (force_tile >= 0) sp.tile = force_tile == 1 ? 1 : 0;
   }
   sp.Mp = round_up(an.m, sp.tile == 1 ? XBM : GBM);
   sp.Np = round_up(an.n, sp.tile == 1 ? XBN : GBN);

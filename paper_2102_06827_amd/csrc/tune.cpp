@@ -17,7 +17,7 @@ namespace comet {
 
 namespace {
 const char *kFormat = "comet-tune-2";
-const char *kKernelVersion = "k7";   // bump when kernels change in a way that invalidates timings
+const char *kKernelVersion = "k8";   // bump when kernels change in a way that invalidates timings
 
 int bucket(int64_t x) {
   int b = 0;
@@ -74,8 +74,21 @@ bool parse(const std::string &text, std::map<std::string, TuneEntry> &out) {
 }
 }  // namespace
 
+// The cache starts in the mode COMET_AUTOTUNE names ("off", "on" = time
+// missing classes and reuse the cache, "force" = time every class again), at
+// COMET_TUNE_CACHE or ~/.cache/comet_tune.json; comet_autotune() changes it.
 TuneCache &tune_cache() {
   static TuneCache c;
+  static bool init = [] {
+    const char *env = std::getenv("COMET_AUTOTUNE");
+    if (env && *env) {
+      const std::string v(env);
+      const int mode = (v == "on" || v == "1") ? 1 : (v == "force" || v == "2") ? 2 : 0;
+      if (mode) c.configure(std::string(), mode);
+    }
+    return true;
+  }();
+  (void)init;
   return c;
 }
 
@@ -133,6 +146,14 @@ std::string tune_key(const Analysis &an, const std::string &arch) {
     << an.runBk << an.runBn << an.runCn << "/s" << (an.swapped ? 1 : 0) << "/m" << bucket(an.m) << "n" << bucket(an.n)
     << "k" << bucket(an.k) << "b" << bucket(an.nb);
   return k.str();
+}
+
+std::string batch_tune_key(int dtype, int mode, int variant, int64_t m, int64_t n, int64_t k,
+                           const std::string &arch) {
+  std::ostringstream o;
+  o << "batch/" << arch << "/" << kKernelVersion << "/" << (dtype == 0 ? "f64" : "f32") << "/x" << mode << "/v"
+    << variant << "/m" << bucket(m) << "n" << bucket(n) << "k" << bucket(k);
+  return o.str();
 }
 
 }  // namespace comet

@@ -45,4 +45,11 @@ TuneCache &tune_cache();
 // the flattened sizes bucketed by powers of two.
 std::string tune_key(const Analysis &an, const std::string &arch);
 
+// Problem class of one batched problem: `arch`, the kernel version, storage
+// dtype (0 FP64, 1 FP32), batch mode (0 native, 1 fused BF16x3), layout
+// variant and the flattened sizes bucketed by powers of two.  The cache
+// entry's `tile` holds the batch tile class.
+std::string batch_tune_key(int dtype, int mode, int variant, int64_t m, int64_t n, int64_t k,
+                           const std::string &arch);
+
 }  // namespace comet

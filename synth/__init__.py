@@ -128,6 +128,17 @@ def uniform_torch(seed: int, shape, dtype=None, device="cpu", lo: float = -1.0, 
     return x if dtype is None else x.to(dtype)
 
 
+def integers_torch(seed: int, shape, dtype=None, device="cpu", lo: int = -3, hi: int = 3):
+    """The values of integers() drawn with torch on any device."""
+    import torch
+    n = 1
+    for s in shape:
+        n *= int(s)
+    z = (splitmix64_torch(seed, n, device) >> 32) & ((1 << 32) - 1)
+    x = (z % (hi - lo + 1) + lo).to(torch.float64).reshape(tuple(shape))
+    return x if dtype is None else x.to(dtype)
+
+
 # the six contraction patterns of the batched workload: 4D = 4D x 4D, output
 # labels a, b, i, j split two and two between A and B, two summation labels
 BATCH_PATTERNS = [
@@ -152,3 +163,23 @@ def batch_problems(n: int, seed: int, extents=(8, 16, 24, 32, 40, 48, 56, 64)):
         ext = {ch: int(extents[int(w[1 + q] % np.uint64(len(extents)))]) for q, ch in enumerate(labels)}
         out.append((spec, ext))
     return out
+
+
+def batch_check_sample(problems, n_sample: int = 128, seed: int = 5005, heaviest: int = 20,
+                       small_flops: float = 2.0 ** 24):
+    """Indices of the batched problems checked in full against the oracle: a
+    seeded sample of n_sample problems, every problem of at most small_flops
+    forward FLOPs (2 x the product of its extents) and the `heaviest` largest
+    ones, sorted."""
+    flops = []
+    for _, ext in problems:
+        p = 1
+        for v in ext.values():
+            p *= int(v)
+        flops.append(2.0 * p)
+    n = len(problems)
+    chosen = [int(i) for i in np.argsort(splitmix64(seed, n), kind="stable")[:n_sample]]   # seeded permutation
+    out = set(chosen)
+    out |= {i for i in range(n) if flops[i] <= small_flops}
+    out |= set(int(i) for i in np.argsort(np.array(flops), kind="stable")[::-1][:heaviest])
+    return sorted(out)

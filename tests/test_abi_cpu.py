@@ -298,14 +298,16 @@ def test_autotune_configuration(tmp_path):
     assert L.comet_autotune(None, -1) == UNSUP
 
 
-def test_batch_rejects_tile_counts_near_the_work_counter_range():
+def test_batch_rejects_tile_counts_near_the_work_counter_range(monkeypatch):
     """The persistent batch kernel's work counter is a 32-bit int that every
     workgroup increments once past the end of the list: a batch whose 64 x 64
     output tiles come within 2^20 of 2^31 is refused on the host, before any
     device call (the pointers below are never dereferenced)."""
     import paper_2102_06827_amd as m
     L = m.lib()
-    # ab = ak * kb with a = b = 2^22 + 64: (2^16 + 1)^2 tiles > 2^31 - 2^20
+    # ab = ak * kb with a = b = 2^22 + 64 in the 64 x 64 class: (2^16 + 1)^2
+    # tiles > 2^31 - 2^20
+    monkeypatch.setenv("COMET_BATCH_CLASS", "0")
     n = (1 << 22) + 64
     spec = b"ab=ak*kb"
     ext = (ctypes.c_int64 * 3)(n, n, 1)

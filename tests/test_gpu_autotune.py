@@ -88,3 +88,80 @@ def test_autotune_searches_ttgt_flattenings(cache, monkeypatch):
     if entry["path"] == 2:
         a, b, c = entry["ttgt"].split("|")
         assert sorted(a) == sorted("aebf") and sorted(b) == sorted("dfce") and sorted(c) == sorted("abcd")
+
+
+@pytest.mark.parametrize("dtype,choices", [(torch.float64, (0, 1)), (torch.float32, (0, 1, 2))])
+def test_autotune_split_product_tile(cache, dtype, choices):
+    """The classic BF16x3 split: the slice-pair tiles (and, on FP32 storage,
+    the fused kernel) are timed, the winner is recorded and used, and the
+    tuned plan is exact on integer inputs."""
+    spec = "abij=acik*bkcj"
+    ext = dict(a=40, b=36, c=24, i=12, j=16, k=20)
+    A = synth.integers(11, shape_of("acik", ext))
+    B = synth.integers(12, shape_of("bkcj", ext))
+    Ad, Bd = torch_dev(A, dtype), torch_dev(B, dtype)
+    print_case("autotune split", dtype)
+    comet.autotune(str(cache), 2)
+    plan = comet.Plan(spec, Ad, Bd, compute="split_bf16x3")
+    C = plan(Ad, Bd)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), oracle.contract(spec, A, B))
+    (key, entry), = json.loads(cache.read_text())["entries"].items()
+    assert entry["tile"] in choices and entry["us"] > 0 and "/c4/" in key
+    d = plan.describe()
+    assert d["fused3"] == (entry["tile"] == 2)
+    if entry["tile"] != 2:
+        assert d["split_tile"] == entry["tile"]
+
+
+def test_autotune_batch_classes(cache):
+    """The batch's tile classes come from timings per problem class: every
+    problem is counted as tuned, the cache holds batch entries with valid
+    classes, a second batch reuses them without timing, and results are
+    exact on integer inputs."""
+    rng = np.random.default_rng(2)
+    host, dev = [], []
+    for t in range(10):
+        spec = ["abij=acik*bkcj", "abij=abcd*cdij"][t % 2]
+        c, a, b = oracle.split_spec(spec)
+        ext = {ch: int(rng.choice([8, 24, 64])) for ch in set(a + b)}
+        A = synth.integers(20 + t, shape_of(a, ext)).astype(np.float32)
+        B = synth.integers(40 + t, shape_of(b, ext)).astype(np.float32)
+        host.append((spec, A, B))
+        C = torch.zeros(shape_of(c, ext), dtype=torch.float32, device="cuda")
+        dev.append(dict(spec=spec, A=torch_dev(A, torch.float32), B=torch_dev(B, torch.float32), C=C))
+    print_case("autotune batch")
+    comet.autotune(str(cache), 1)
+    bt = comet.Batch(dev, dtype=torch.float32)
+    d = bt.describe()
+    assert d["tuned"] == len(dev)
+    entries = json.loads(cache.read_text())["entries"]
+    batch_entries = {k: v for k, v in entries.items() if k.startswith("batch/")}
+    assert batch_entries and all(0 <= v["tile"] <= 3 and v["us"] > 0 for v in batch_entries.values())
+    mtime = cache.stat().st_mtime_ns
+    bt2 = comet.Batch(dev, dtype=torch.float32)
+    assert bt2.describe()["classes"] == d["classes"] and cache.stat().st_mtime_ns == mtime
+    bt()
+    torch.cuda.synchronize()
+    for (spec, A, B), x in zip(host, dev):
+        assert np.array_equal(to_np(x["C"]), oracle.contract(spec, A, B)), spec
+
+
+def test_autotune_environment_switch(tmp_path):
+    """COMET_AUTOTUNE=on turns the autotuner on from the environment (a fresh
+    process), with the cache at COMET_TUNE_CACHE."""
+    import os
+    import subprocess
+    import sys
+    path = tmp_path / "env_tune.json"
+    code = ("import torch, paper_2102_06827_amd as c; "
+            "A = torch.ones(64, 96, dtype=torch.float64, device='cuda'); "
+            "B = torch.ones(96, 80, dtype=torch.float64, device='cuda'); "
+            "C = c.contract('ij=ik*kj', A, B); torch.cuda.synchronize(); "
+            "assert bool((C == 96).all())")
+    env = dict(os.environ, COMET_AUTOTUNE="on", COMET_TUNE_CACHE=str(path))
+    print_case("autotune env")
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=os.path.dirname(os.path.dirname(__file__)),
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert len(json.loads(path.read_text())["entries"]) == 1

@@ -239,3 +239,71 @@ def test_contract_refuses_capture():
         except comet.CometError as e:
             err = e
     assert err is not None and err.name == "UNSUPPORTED"
+
+
+@pytest.mark.parametrize("cls", [0, 1, 2, 3])
+@pytest.mark.parametrize("kind", ["integer", "uniform"])
+def test_batch_each_tile_class_matches_oracle(cls, kind, monkeypatch):
+    """Every tile class of the FP32 batch forced through COMET_BATCH_CLASS on
+    problems with ragged extents (not multiples of the class tile): bit-exact
+    on integer inputs, <= 1e-5 otherwise; element-load problems keep class 0."""
+    host = make_batch(30, 20 + cls, "f32", extents=(8, 16, 24, 40, 56, 72), kind=kind, beta=1.0)
+    dev = to_device(host, "f32")
+    monkeypatch.setenv("COMET_BATCH_CLASS", str(cls))
+    print_case("batch class", cls, kind)
+    b = comet.Batch(dev, dtype=torch.float32)
+    d = b.describe()
+    assert d["classes"][cls] > 0 and sum(d["classes"]) == len(host)
+    b()
+    torch.cuda.synchronize()
+    for p, x in zip(host, dev):
+        ref = oracle.contract(p["spec"], p["A"], p["B"], p["C0"], alpha=p["alpha"], beta=p["beta"])
+        if kind == "integer":
+            assert np.array_equal(to_np(x["C"]), ref), p["spec"]
+        else:
+            assert oracle.relerr(to_np(x["C"]), ref) <= 1e-5, p["spec"]
+
+
+def test_batch_model_and_queues_describe():
+    """The untuned class choice and the queues: every problem is in exactly
+    one class, the queues hold every output tile, and each queue is used."""
+    host = make_batch(64, 31, "f32", extents=(8, 32, 64))
+    dev = to_device(host, "f32")
+    print_case("batch describe")
+    d = comet.Batch(dev, dtype=torch.float32).describe()
+    assert sum(d["classes"]) == 64 and d["tuned"] == 0
+    assert sum(d["queues"]) == d["tiles"] and min(d["queues"]) > 0
+
+
+@pytest.mark.parametrize("copy", ["1", "0"])
+def test_batch_element_load_problems_copy_or_gather(copy, monkeypatch):
+    """Problems of the patterns whose operands have their unit strides on
+    different summation labels: by default one operand is copied into a
+    vector-readable order before the launch, COMET_BATCH_COPY=0 gathers them
+    element by element; both bit-exact on integer inputs, twice in a row
+    with new input values in between (the copy is refreshed every execute)."""
+    specs = ["abij=ciak*bkjc", "cjkb=kcia*ajbi", "abij=acik*bkcj"]
+    monkeypatch.setenv("COMET_BATCH_COPY", copy)
+    rng = np.random.default_rng(5)
+    host = []
+    for t in range(12):
+        spec = specs[t % 3]
+        c, a, b = oracle.split_spec(spec)
+        ext = {ch: int(rng.choice([8, 16, 24, 40])) for ch in set(a + b)}
+        A = synth.integers(900 + 10 * t, shape_of(a, ext)).astype(np.float32)
+        B = synth.integers(901 + 10 * t, shape_of(b, ext)).astype(np.float32)
+        host.append(dict(spec=spec, A=A, B=B, C0=np.zeros(shape_of(c, ext), np.float32), alpha=1.0, beta=0.0))
+    dev = to_device(host, "f32")
+    print_case("batch copies", copy)
+    bt = comet.Batch(dev, dtype=torch.float32)
+    d = bt.describe()
+    assert (d["copies"] > 0) == (copy == "1")
+    for rep in range(2):
+        if rep == 1:
+            for p, x in zip(host, dev):
+                p["A"] = -2.0 * p["A"] + 1.0
+                x["A"].copy_(torch_dev(p["A"], torch.float32))
+        bt()
+        torch.cuda.synchronize()
+        for p, x in zip(host, dev):
+            assert np.array_equal(to_np(x["C"]), oracle.contract(p["spec"], p["A"], p["B"])), (rep, p["spec"])

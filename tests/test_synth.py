@@ -39,6 +39,9 @@ def test_torch_stream_matches_numpy():
     u_np = synth.uniform(123, (11, 13))
     u_t = synth.uniform_torch(123, (11, 13)).numpy()
     assert np.array_equal(u_np, u_t)
+    i_np = synth.integers(321, (17, 19))
+    i_t = synth.integers_torch(321, (17, 19)).numpy()
+    assert np.array_equal(i_np, i_t)
 
 
 def test_decay_envelope():
