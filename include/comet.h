@@ -203,6 +203,28 @@ comet_status_t comet_plan_execute(comet_plan_t plan, double alpha, const void *A
                                   double beta, void *C, void *workspace, size_t ws_bytes,
                                   void *stream);
 comet_status_t comet_plan_destroy(comet_plan_t plan);
+
+/*
+ * comet_plan_execute_noalloc -- comet_plan_execute without a caller
+ * workspace and without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device
+ * buffer of COMET_NOALLOC_SCRATCH_BYTES that the library holds on every GPU
+ * it runs on until the process ends; the caller still passes A, B, C and the
+ * stream as for comet_plan_execute, with the same meaning, layout and
+ * results.  A plan whose comet_plan_workspace_size exceeds the buffer is
+ * refused with COMET_ERR_WORKSPACE before anything is enqueued.  All calls on
+ * one GPU share that GPU's buffer, which keeps whatever the last call left
+ * (every plan writes each workspace byte before reading it, so nothing needs
+ * clearing): calls that may overlap in time on one GPU (two streams, or two
+ * threads) race on it and must be ordered by the caller.  The first call on a
+ * device looks up that device's buffer address (hipGetSymbolAddress), which
+ * is not capturable; later calls are.
+ */
+#define COMET_NOALLOC_SCRATCH_BYTES (128u << 20)
+comet_status_t comet_plan_execute_noalloc(comet_plan_t plan, double alpha, const void *A,
+                                          const void *B, double beta, void *C, void *stream);
+
 /* Writes a JSON description of the plan into buf (host only): path, the
  * label classes after fusion ("M", "N", "K" and the batch labels "X", with
  * extents and strides), flattened sizes m, n, k and batch entries nb,

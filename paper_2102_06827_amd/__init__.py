@@ -39,6 +39,7 @@ STATUS = {0: "OK", 1: "INVALID_SPEC", 2: "INVALID_SHAPE", 3: "INVALID_STRIDE", 4
 SYMBOLS = [
     "comet_contract", "comet_plan_create", "comet_plan_create_ex", "comet_plan_workspace_size",
     "comet_plan_execute", "comet_plan_destroy", "comet_plan_describe", "comet_analyze",
+    "comet_plan_execute_noalloc",
     "comet_batch_create", "comet_batch_workspace_size", "comet_batch_execute", "comet_batch_destroy",
     "comet_batch_describe",
     "comet_permute", "comet_fill", "comet_chain_plan", "comet_contract_chain", "comet_autotune", "comet_set_split_slices", "comet_set_int8_slices", "comet_last_error",
@@ -94,6 +95,7 @@ def lib():
         L.comet_plan_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
         L.comet_plan_execute.argtypes = [P, D, P, P, D, P, P, ctypes.c_size_t, P]
         L.comet_plan_destroy.argtypes = [P]
+        L.comet_plan_execute_noalloc.argtypes = [P, D, P, P, D, P, P]
         L.comet_plan_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
         L.comet_analyze.argtypes = [S, I64P, I64P, I64P, I64P, I, I, I, ctypes.c_char_p, ctypes.c_size_t]
         L.comet_batch_create.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(_Problem), I, I]
@@ -372,6 +374,15 @@ class Plan:
         _check(lib().comet_plan_execute(self._h, float(alpha), ctypes.c_void_p(A.data_ptr()),
                                         ctypes.c_void_p(B.data_ptr()), float(beta),
                                         ctypes.c_void_p(C.data_ptr()), wp, wn, _stream_handle(stream)))
+        return C
+
+    def execute_noalloc(self, A, B, C, alpha=1.0, beta=0.0, stream=None):
+        """The same contraction with the library's static device buffer as
+        workspace: nothing is allocated (C must be given)."""
+        _dtype_code(A, B, C)
+        _check(lib().comet_plan_execute_noalloc(self._h, float(alpha), ctypes.c_void_p(A.data_ptr()),
+                                                ctypes.c_void_p(B.data_ptr()), float(beta),
+                                                ctypes.c_void_p(C.data_ptr()), _stream_handle(stream)))
         return C
 
     def __del__(self):

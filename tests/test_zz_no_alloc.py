@@ -1,0 +1,89 @@
+"""comet_plan_execute_noalloc: the plan executed with the library's static
+device buffer as its workspace gives the same bits as comet_plan_execute with
+a caller workspace (pre-filled with 0xFF bytes, so nothing may rely on
+cleared scratch), on two calls in a row, the second with a smaller input;
+a plan needing more than the buffer is refused before anything runs."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_common import oracle, print_case, shape_of, synth, to_np, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+comet = pytest.importorskip("paper_2102_06827_amd")
+
+SPEC = "abij=acik*bkcj"
+LIMIT = 128 << 20
+
+
+def _case(V, O, seed):
+    ext = dict(a=V, b=V, c=V, i=O, j=O, k=O)
+    A = synth.uniform(seed + 1, shape_of("acik", ext))
+    B = synth.uniform(seed + 2, shape_of("bkcj", ext))
+    C0 = synth.uniform(seed + 3, shape_of("abij", ext))
+    return A, B, C0
+
+
+def _run_both(plan, Ad, Bd, C0d, alpha, beta):
+    ws = torch.full((max(plan.workspace_bytes, 1),), 255, dtype=torch.uint8, device="cuda")
+    ref = C0d.clone()
+    plan(Ad, Bd, ref, alpha=alpha, beta=beta, workspace=ws)
+    got = C0d.clone()
+    plan.execute_noalloc(Ad, Bd, got, alpha=alpha, beta=beta)
+    torch.cuda.synchronize()
+    return ref, got
+
+
+def test_noalloc_matches_plan_execute_twice_second_smaller():
+    # first call: the aligned BF16 split (its slices fill the buffer's front),
+    # second call: a smaller TTGT plan (permuted copies in the same buffer)
+    A1, B1, C1 = _case(48, 16, 7100)
+    A2, B2, C2 = _case(20, 6, 7200)
+    calls = [(A1, B1, C1, "split_bf16", "auto", 1e-9), (A2, B2, C2, "default", "ttgt", 1e-12)]
+    sizes = []
+    for A, B, C0, compute, path, tol in calls:
+        print_case("noalloc", compute, path, A.shape)
+        Ad, Bd, Cd = (torch_dev(x, torch.float64) for x in (A, B, C0))
+        plan = comet.Plan(SPEC, Ad, Bd, compute=compute, path=path)
+        assert 0 < plan.workspace_bytes <= LIMIT
+        sizes.append(plan.workspace_bytes)
+        ref, got = _run_both(plan, Ad, Bd, Cd, 0.75, -1.25)
+        assert torch.equal(ref, got)
+        want = oracle.contract(SPEC, A, B, C0, alpha=0.75, beta=-1.25)
+        assert oracle.relerr(to_np(got), want) <= tol
+    assert sizes[1] < sizes[0]
+
+
+def test_noalloc_integer_exact_fp32():
+    # FP32 storage on the gather path: bit-exact on integer inputs, and the
+    # same bits as the ordinary execute
+    ext = dict(a=16, b=16, c=16, i=8, j=8, k=8)
+    A = synth.integers(7301, shape_of("acik", ext))
+    B = synth.integers(7302, shape_of("bkcj", ext))
+    C0 = synth.integers(7303, shape_of("abij", ext))
+    Ad, Bd, Cd = (torch_dev(x, torch.float32) for x in (A, B, C0))
+    print_case("noalloc no-workspace f32")
+    plan = comet.Plan(SPEC, Ad, Bd, path="gett")
+    ref, got = _run_both(plan, Ad, Bd, Cd, 1.0, 1.0)
+    assert torch.equal(ref, got)
+    assert np.array_equal(to_np(got), oracle.contract(SPEC, A, B, C0, alpha=1.0, beta=1.0))
+
+
+def test_noalloc_refuses_plans_beyond_the_buffer():
+    # the headline-size aligned split needs about 189 MB of slices
+    V, O = 96, 32
+    ext = dict(a=V, b=V, c=V, i=O, j=O, k=O)
+    Ad = torch.zeros(shape_of("acik", ext), dtype=torch.float64, device="cuda")
+    Bd = torch.zeros(shape_of("bkcj", ext), dtype=torch.float64, device="cuda")
+    Cd = torch.full(shape_of("abij", ext), 3.0, dtype=torch.float64, device="cuda")
+    print_case("noalloc refuse")
+    plan = comet.Plan(SPEC, Ad, Bd, compute="split_bf16")
+    assert plan.workspace_bytes > LIMIT
+    with pytest.raises(comet.CometError) as ei:
+        plan.execute_noalloc(Ad, Bd, Cd)
+    assert ei.value.code == 6 and "static buffer" in str(ei.value)
+    torch.cuda.synchronize()
+    assert bool((Cd == 3.0).all())
