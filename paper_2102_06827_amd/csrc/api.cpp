@@ -424,11 +424,45 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
   return best;
 }
 
+// Short summations with many output tiles take the short-summation kernel
+// (tile 3, stores overlapped with the next tile's products): on MI355X the
+// K = 32 triples contraction's whole-tile kernel runs its products and its
+// 1 GB of stores one after the other.  Returns its workgroups, 0 if not
+// taken; COMET_GETT_SHORTK=0 / 1 turns it off / on where it exists.
+constexpr int kShortKMax = 32;
+int shortk_choice(const Analysis &an, int cus, bool vecA, bool vecB, int forced_tile) {
+  const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
+  const int dt = an.dtype == COMET_F64 ? 0 : 1, cp = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  if (!native || !an.X.empty() || an.empty_out || an.empty_sum || an.k > kShortKMax || !vecA || !vecB ||
+      !gett_tile_valid(3, dt, cp, true, true) || (forced_tile >= 0 && forced_tile != 3))
+    return 0;
+  GettLaunch g{};
+  g.dtype = dt;
+  g.compute = cp;
+  g.layoutA = an.layoutA;
+  g.layoutB = an.layoutB;
+  g.vecA = g.vecB = 1;
+  g.tile = 3;
+  g.shortk = 1;
+  const int res = gett_occupancy(g);
+  if (res <= 0) return 0;
+  const int64_t S = int64_t(std::max(cus, 1)) * res;
+  const int64_t T = ((an.m + 127) / 128) * ((an.n + 127) / 128);
+  const char *env = std::getenv("COMET_GETT_SHORTK");
+  if (env && *env) return std::atoi(env) != 0 ? int(S) : 0;
+  return T >= 4 * S ? int(S) : 0;
+}
+
 void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
   Analysis &an = p->an;
   Schedule sc = pick_schedule(an, cus, p->vecA_tables, p->vecB_tables, forced_tile);
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
   if (!native || an.empty_out || an.empty_sum || !an.X.empty()) sc.sk_tiles = sc.sk_blocks = sc.persist = 0;
+  an.shortk = sc.persist > 0 ? 0 : shortk_choice(an, cus, p->vecA_tables, p->vecB_tables, forced_tile);
+  if (an.shortk > 0) {
+    sc.tile = 3;
+    sc.sk_tiles = sc.sk_blocks = 0;
+  }
   an.tile = sc.tile;
   an.sk_tiles = sc.sk_tiles;
   an.sk_blocks = sc.sk_blocks;
@@ -654,6 +688,7 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
     g.sk.ws = ws;
   }
   if (an.persist > 0 && g.tile == an.tile) g.persistent = an.persist;
+  if (an.shortk > 0 && g.tile == an.tile && g.vecA && g.vecB) g.shortk = an.shortk;
   if (p->offAx) {
     g.bt.offA = p->offAx;
     g.bt.offB = p->offBx;
@@ -661,6 +696,7 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
     g.bt.count = an.nb;
     g.sk = StreamK{};
     g.persistent = 0;
+    g.shortk = 0;
   }
   HIP_TRY(launch_gett(g, s), "gett launch");
   return COMET_OK;
@@ -1340,7 +1376,7 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
        std::to_string(g_split_slices) + "|" + std::to_string(g_int8_slices);
   // every planner override in the environment
   for (const char *name : {"COMET_FORCE_PATH", "COMET_TTGT_ORDER", "COMET_GETT_TILE", "COMET_GETT_SK",
-                           "COMET_GETT_PERSIST", "COMET_SPLIT_TILE", "COMET_FUSED3"}) {
+                           "COMET_GETT_PERSIST", "COMET_GETT_SHORTK", "COMET_SPLIT_TILE", "COMET_FUSED3"}) {
     const char *v = std::getenv(name);
     k += "|";
     if (v) k += v;

@@ -41,20 +41,22 @@ constexpr int F3_LDK = F3_BK + 8;  // LDS pitch in bf16 (80 bytes: conflict-free
 template <int BM, int BN>
 constexpr int f3_lds() { return 3 * (BM + BN) * F3_LDK; }   // A and B, three slices (bf16 elements)
 
-// One BM x BN output tile of the fused BF16x3 product; 2 x 2 waves, each
-// (BM / 2) x (BN / 2) made of 16 x 16 blocks.
-template <int BM, int BN, int LA, int LB, bool V>
+// One BM x BN output tile of the fused BF16x3 product; a WGM x WGN grid of
+// waves, each (BM / WGM) x (BN / WGN) made of 16 x 16 blocks.
+template <int BM, int BN, int WGM, int WGN, int LA, int LB, bool V>
 __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const float *__restrict__ B,
                                             float *__restrict__ C, const GettTables &t, int64_t M, int64_t N,
                                             int64_t K, double alpha, double beta, int64_t m0, int64_t n0,
                                             __bf16 *smem) {
-  typedef Loader<float, float, BM, F3_BK, LA, V, NT> LoadA;
-  typedef Loader<float, float, BN, F3_BK, LB, V, NT> LoadB;
-  constexpr int FM = BM / 32, FN = BN / 32;
+  constexpr int NTH = 64 * WGM * WGN;
+  typedef Loader<float, float, BM, F3_BK, LA, V, NTH> LoadA;
+  typedef Loader<float, float, BN, F3_BK, LB, V, NTH> LoadB;
+  constexpr int FM = BM / WGM / 16, FN = BN / WGN / 16;
+  static_assert(FM * 16 * WGM == BM && FN * 16 * WGN == BN, "wave tile must be a multiple of 16");
   lds_t<__bf16> *const sA = to_lds(smem);
   lds_t<__bf16> *const sB = sA + 3 * BM * F3_LDK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave >> 1) * (BM / 2), wn0 = (wave & 1) * (BN / 2);
+  const int wm0 = (wave / WGN) * (BM / WGM), wn0 = (wave % WGN) * (BN / WGN);
   f4_t acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -111,12 +113,12 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
   }
   // the epilogue of the gather kernels (C offsets staged in LDS, which the
   // loop above no longer reads)
-  WaveTile<float, BM, BN, 2, 2> w;
+  WaveTile<float, BM, BN, WGM, WGN> w;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) w.acc[i][j] = acc[i][j];
-  gett_store<float, float, BM, BN, 2, 2>(w, C, t, M, N, alpha, beta, m0, n0, reinterpret_cast<float *>(smem));
+  gett_store<float, float, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, m0, n0, reinterpret_cast<float *>(smem));
 }
 
 template <int LA, int LB, bool V>
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(NT) void fused3_kernel(const float *__restrict__ A,
   __shared__ __attribute__((aligned(16))) __bf16 smem[f3_lds<TB, TB>()];
   int tm, tn;
   tile_coords(blockIdx.x, tilesM, tilesN, &tm, &tn);
-  fused3_tile<TB, TB, LA, LB, V>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * TB, int64_t(tn) * TB, smem);
+  fused3_tile<TB, TB, 2, 2, LA, LB, V>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * TB, int64_t(tn) * TB, smem);
 }
 
 // ---------------------------------------------------------------- batch ----
@@ -138,13 +140,21 @@ struct ClassShape {
 constexpr ClassShape kClass[kBatchClasses] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}};
 
 // which classes exist: element loads in class 0 only, and the larger
-// classes for native FP32 only.  Every class of one kernel shares its
-// register allocation, which the largest class sets: FP32 fits all four in
-// 256 registers (two workgroups per CU) without spilling, while the FP64
-// and fused BF16x3 kernels spill with any class beyond 64 x 64.
+// classes for FP32 storage only.  Every class of one kernel shares its
+// register allocation, which the largest class sets: the native FP32 kernel
+// (4 waves) fits all four in 256 registers (two workgroups per CU) without
+// spilling, the fused BF16x3 kernel does with 8 waves per workgroup (one
+// workgroup per CU), while the FP64 kernel spills with any class beyond
+// 64 x 64.
 constexpr bool class_ok(int cls, int dtype, int mode, bool vec) {
-  return cls == 0 || (vec && dtype == 1 && mode == 0);
+  return cls == 0 || (vec && dtype == 1);
 }
+
+// workgroup size and wave grid of the batch kernel of each mode: 2 x 2 waves
+// for the native products, 4 x 2 for the fused BF16x3 one
+template <int MODE> struct BatchWaves;
+template <> struct BatchWaves<0> { static constexpr int WGM = 2, WGN = 2, NT = 256, MINB = 2; };
+template <> struct BatchWaves<1> { static constexpr int WGM = 4, WGN = 2, NT = 512, MINB = 1; };
 
 template <typename T, int LA, int LB, bool V, int CLS>
 constexpr int native_lds_one() {
@@ -163,7 +173,7 @@ constexpr int native_lds_bytes() {
                                cmax(native_lds_cls<T, 2>(), native_lds_cls<T, 3>()))
                         : native_lds_cls<T, 0>();
 }
-constexpr int fused_lds_bytes() { return int(sizeof(__bf16)) * f3_lds<64, 64>(); }
+constexpr int fused_lds_bytes() { return int(sizeof(__bf16)) * f3_lds<128, 128>(); }
 
 template <typename T, int MODE, int CLS, int LA, int LB, bool V>
 __device__ __forceinline__ void run_item(const BatchDesc &d, int tile, char *smem) {
@@ -174,9 +184,9 @@ __device__ __forceinline__ void run_item(const BatchDesc &d, int tile, char *sme
                                                     static_cast<T *>(d.C), d.t, d.M, d.N, d.K, d.alpha, d.beta, m0,
                                                     n0, reinterpret_cast<T *>(smem));
   } else {
-    fused3_tile<BM, BN, LA, LB, V>(static_cast<const float *>(d.A), static_cast<const float *>(d.B),
-                                   static_cast<float *>(d.C), d.t, d.M, d.N, d.K, d.alpha, d.beta, m0, n0,
-                                   reinterpret_cast<__bf16 *>(smem));
+    fused3_tile<BM, BN, BatchWaves<1>::WGM, BatchWaves<1>::WGN, LA, LB, V>(
+        static_cast<const float *>(d.A), static_cast<const float *>(d.B), static_cast<float *>(d.C), d.t, d.M, d.N,
+        d.K, d.alpha, d.beta, m0, n0, reinterpret_cast<__bf16 *>(smem));
   }
 }
 
@@ -213,7 +223,7 @@ __device__ __forceinline__ void run_any(const BatchDesc &d, int tile, char *smem
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(NT, 2) void batch_kernel(const BatchDesc *__restrict__ descs,
+__global__ __launch_bounds__(BatchWaves<MODE>::NT, BatchWaves<MODE>::MINB) void batch_kernel(const BatchDesc *__restrict__ descs,
                                                    const BatchItem *__restrict__ items, BatchQueues q,
                                                    int *__restrict__ counters) {
   constexpr int LDS = MODE == 0 ? native_lds_bytes<T>() : fused_lds_bytes();
@@ -287,7 +297,7 @@ int batch_blocks_per_cu(int dtype, int mode) {
   int n = 0;
   hipError_t e;
   if (mode == 1)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<float, 1>, NT, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<float, 1>, BatchWaves<1>::NT, 0);
   else if (dtype == 0)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<double, 0>, NT, 0);
   else
@@ -301,7 +311,8 @@ hipError_t launch_batch(const BatchDesc *descs, const BatchItem *items, const Ba
   if (q.off[kBatchQueues] <= 0) return hipGetLastError();
   if (mode == 1) {
     if (dtype != 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((batch_kernel<float, 1>), dim3(grid), dim3(NT), 0, s, descs, items, q, counters);
+    hipLaunchKernelGGL((batch_kernel<float, 1>), dim3(grid), dim3(BatchWaves<1>::NT), 0, s, descs, items, q,
+                       counters);
   } else if (dtype == 0) {
     hipLaunchKernelGGL((batch_kernel<double, 0>), dim3(grid), dim3(NT), 0, s, descs, items, q, counters);
   } else {

@@ -369,10 +369,18 @@ __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &
 // stores still in flight.  C is written with nontemporal stores: the kernel
 // never reads it back, and streaming it past the caches made the
 // store-bound K = 32 triples contraction 10% faster on MI355X.
-template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN>
+//
+// With SINK, an element outside the output is stored to *sink (a
+// dummy location) instead of being skipped, so every lane issues every
+// store: the number of stores in flight is then the same on every path, and
+// the compiler can wait for loads issued before them without waiting for the
+// stores themselves (a skipped store makes that count unknown, and every
+// later wait a full one).
+template <typename Tin, typename Tc, int BM, int BN, int WGM, int WGN, bool SINK = false>
 __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM, WGN> &w, Tin *__restrict__ C,
                                                   const lds_t<int64_t> *cm, const lds_t<int64_t> *cn, int64_t M,
-                                                  int64_t N, double alpha, double beta, int64_t m0, int64_t n0) {
+                                                  int64_t N, double alpha, double beta, int64_t m0, int64_t n0,
+                                                  Tin *sink = nullptr) {
   typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
   typedef typename std::conditional<(sizeof(Tin) == 8 || sizeof(Tc) == 8), double, float>::type Te;
   constexpr int G = WT::FN * WT::FM;   // groups of four elements: (j, i)
@@ -393,8 +401,12 @@ __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM
 #pragma unroll
       for (int r = 0; r < 4; ++r) a[r] = addr(i, r, j);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (inside(i, r, j)) __builtin_nontemporal_store(Tin(al * Te(w.acc[i][j][r])), &gC[a[r]]);
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (SINK)
+          __builtin_nontemporal_store(Tin(al * Te(w.acc[i][j][r])), inside(i, r, j) ? &gC[a[r]] : to_glb(sink));
+        else if (inside(i, r, j))
+          __builtin_nontemporal_store(Tin(al * Te(w.acc[i][j][r])), &gC[a[r]]);
+      }
     }
     return;
   }
@@ -423,8 +435,13 @@ __device__ __forceinline__ void gett_store_staged(const WaveTile<Tc, BM, BN, WGM
 #pragma unroll
     for (int r = 0; r < 4; ++r) a[r] = addr(i, r, j);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (inside(i, r, j)) __builtin_nontemporal_store(Tin(al * Te(w.acc[i][j][r]) + be * Te(cv[g & 1][r])), &gC[a[r]]);
+    for (int r = 0; r < 4; ++r) {
+      const Tin v = Tin(al * Te(w.acc[i][j][r]) + be * Te(cv[g & 1][r]));
+      if constexpr (SINK)
+        __builtin_nontemporal_store(v, inside(i, r, j) ? &gC[a[r]] : to_glb(sink));
+      else if (inside(i, r, j))
+        __builtin_nontemporal_store(v, &gC[a[r]]);
+    }
   }
 }
 

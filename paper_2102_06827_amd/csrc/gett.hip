@@ -110,6 +110,8 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
 
 // the tile variants compiled with batch labels
 constexpr bool batch_tile(int tile) { return tile == 1 || tile == 3; }
+// the tile variants compiled for the short-summation kernel
+constexpr bool shortk_tile(int tile) { return tile == 3; }
 
 // Stream-K: the last sk.tiles tiles (ids dp .. dp + sk.tiles - 1) split
 // along the summation over sk.blocks workgroups, each taking an equal number
@@ -308,6 +310,172 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
   }
 }
 
+// Short summations (K <= kShortK) with large outputs, such as the triples
+// contraction (K = 32, a 1 GB output): the time goes to the MFMA phase and
+// to the output stores, and a workgroup per tile runs them one after the
+// other.  Here workgroup s of S walks the tiles s, s + S, ... (tile ids in
+// the XCD-aware order) with two LDS buffers for the operand tiles (each
+// holding the whole summation), so that the stores of one tile drain while
+// the next tile is multiplied.  A wave waits for its global loads with the
+// one vector-memory counter that its stores also count, and the compiler
+// waits for a load issued after a store by waiting for everything; so each
+// iteration issues the next tile's loads first, multiplies the current tile
+// (long enough for those loads and the previous tile's stores to finish),
+// only then waits and moves the loaded tile to the other LDS buffer, and
+// issues the current tile's stores last.  The row and C offsets a tile's
+// loads and stores use are staged in LDS one tile ahead.  Per tile j:
+//   1. barrier (tile j in LDS buffer j & 1)
+//   2. issue the loads of tile j + 1 (operands, into registers) and of the
+//      table entries of tiles j + 2 (rows) and j + 1 (C offsets)
+//   3. the products of tile j over the whole summation, from LDS
+//   4. registers -> LDS buffer (j + 1) & 1; table entries -> LDS
+//   5. the stores of tile j (C offsets from LDS, nontemporal)
+// The K-table entries do not depend on the tile and are fetched once.
+constexpr int kShortK = 32;
+
+// where the short-summation kernel's lanes outside the output store
+__device__ __align__(16) double shortk_sink[2];
+
+template <typename Tin, typename Tc, int TILE, int LA, int LB>
+constexpr int shortk_lds_elems() {
+  constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
+  return 2 * (Loader<Tin, Tc, kTiles[TILE].bm, kShortK, LA, true, NT>::ELEMS +
+              Loader<Tin, Tc, kTiles[TILE].bn, kShortK, LB, true, NT>::ELEMS);
+}
+
+// BETA0: beta == 0, so the epilogue has one path whose store count the
+// compiler knows; with beta != 0 its C loads follow earlier stores anyway.
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool BETA0>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, 1) void gett_shortk_kernel(
+    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+    int64_t K, double alpha, double beta, int tilesM, int tilesN) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  constexpr int KS = kShortK;
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  typedef Loader<Tin, Tc, BM, KS, LA, true, NT> LoadA;
+  typedef Loader<Tin, Tc, BN, KS, LB, true, NT> LoadB;
+  typedef typename WT::acc_t acc_t;
+  constexpr int NE = (BM + BN + NT - 1) / NT;   // table entries per thread and tile
+  constexpr int BUF = LoadA::ELEMS + LoadB::ELEMS;
+  __shared__ __attribute__((aligned(16))) Tc smem[shortk_lds_elems<Tin, Tc, TILE, LA, LB>()];
+  __shared__ int64_t rows_s[2][BM + BN];   // offAm / offBn entries of a tile
+  __shared__ int64_t ctab_s[2][BM + BN];   // offCm / offCn entries of a tile
+  lds_t<Tc> *const s0 = to_lds(smem);
+  lds_t<int64_t> *const rows = to_lds(&rows_s[0][0]);
+  lds_t<int64_t> *const ctab = to_lds(&ctab_s[0][0]);
+
+  const int T = tilesM * tilesN, S = gridDim.x, sb = blockIdx.x;
+  if (sb >= T) return;   // uniform: a workgroup without tiles
+  const int ntile = (T - 1 - sb) / S + 1;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WT::WM, wn0 = (wave % WGN) * WT::WN;
+  // (plain code rather than lambdas: a kernel argument captured by reference
+  // is given an address in scratch memory, and reading it back is one more
+  // vector memory load)
+  int64_t rv[NE], cv[NE];
+  // rows of tile jr and C offsets of tile jc, clamped to the last tile and
+  // entry so that every lane issues the same loads on every path
+#define SHORTK_FETCH_TABLES(jr_, jc_)                                                                  \
+  do {                                                                                                \
+    int tmr, tnr, tmc, tnc;                                                                           \
+    tile_coords(sb + ((jr_) < ntile ? (jr_) : ntile - 1) * S, tilesM, tilesN, &tmr, &tnr);            \
+    tile_coords(sb + ((jc_) < ntile ? (jc_) : ntile - 1) * S, tilesM, tilesN, &tmc, &tnc);            \
+    _Pragma("unroll") for (int q = 0; q < NE; ++q) {                                                  \
+      const int x = tid + q * NT < BM + BN ? tid + q * NT : BM + BN - 1;                             \
+      if (x < BM) {                                                                                   \
+        const int64_t mr = int64_t(tmr) * BM + x, mc = int64_t(tmc) * BM + x;                        \
+        rv[q] = to_glb(t.offAm)[mr < M ? mr : M - 1];                                                \
+        cv[q] = to_glb(t.offCm)[mc < M ? mc : M - 1];                                                \
+      } else {                                                                                        \
+        const int64_t nr = int64_t(tnr) * BN + (x - BM), nc = int64_t(tnc) * BN + (x - BM);          \
+        rv[q] = to_glb(t.offBn)[nr < N ? nr : N - 1];                                                \
+        cv[q] = to_glb(t.offCn)[nc < N ? nc : N - 1];                                                \
+      }                                                                                               \
+    }                                                                                                 \
+  } while (0)
+  // the staged table entries of rv into rows[rb], of cv into ctab[cb]
+#define SHORTK_STAGE_TABLES(rb_, cb_)                                                                  \
+  _Pragma("unroll") for (int q = 0; q < NE; ++q) {                                                    \
+    const int x = tid + q * NT;                                                                       \
+    if (x < BM + BN) {                                                                                \
+      rows[(rb_) * (BM + BN) + x] = rv[q];                                                            \
+      ctab[(cb_) * (BM + BN) + x] = cv[q];                                                            \
+    }                                                                                                 \
+  }
+
+  LoadA la;
+  LoadB lb;
+  // prologue: tile 0's rows from the tables, the K-table entries (the same
+  // for every tile), tile 0's operands into LDS buffer 0, tile 1's rows and
+  // tile 0's C offsets into LDS
+  {
+    int tm, tn;
+    tile_coords(sb, tilesM, tilesN, &tm, &tn);
+    la.init(tid, int64_t(tm) * BM, M, t.offAm);
+    lb.init(tid, int64_t(tn) * BN, N, t.offBn);
+  }
+  la.fetch_k(t.offAk, 0, K);
+  lb.fetch_k(t.offBk, 0, K);
+  la.load(A, 0, K);
+  lb.load(B, 0, K);
+  // tile 0's rows into rows[0]: the last iteration reloads its own tile from
+  // rows[j & 1], which for a workgroup with one tile no other step writes
+  SHORTK_FETCH_TABLES(0, 0);
+  SHORTK_STAGE_TABLES(0, 0)
+  SHORTK_FETCH_TABLES(1, 0);
+  la.store(s0);
+  lb.store(s0 + LoadA::ELEMS);
+  SHORTK_STAGE_TABLES(1, 0)
+
+  WT w;
+  for (int j = 0; j < ntile; ++j) {
+    __syncthreads();   // 1
+    // 2: the next tile's loads (on the last tile its own again, so that every
+    // iteration issues the same loads)
+    {
+      const int jn = j + 1 < ntile ? j + 1 : j;
+      int tm1, tn1;
+      tile_coords(sb + jn * S, tilesM, tilesN, &tm1, &tn1);
+      const int64_t m1 = int64_t(tm1) * BM, n1 = int64_t(tn1) * BN;
+      const lds_t<int64_t> *r1 = rows + (jn & 1) * (BM + BN);
+      la.init_from(tid, m1, M, r1, m1);
+      lb.init_from(tid, n1, N, r1 + BM, n1);
+      la.load(A, 0, K);
+      lb.load(B, 0, K);
+      SHORTK_FETCH_TABLES(j + 2, j + 1);
+    }
+    // 3: the products over the whole summation
+    const lds_t<Tc> *cur = s0 + (j & 1) * BUF;
+#pragma unroll
+    for (int i = 0; i < WT::FM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < WT::FN; ++jj) w.acc[i][jj] = acc_t{0, 0, 0, 0};
+    gett_mma_step<LoadA, LoadB, KS>(w, cur, cur + LoadA::ELEMS, lane, wm0, wn0);
+    // keep step 4 (whose waits also wait for the previous tile's stores) after
+    // every product: the scheduler would otherwise hoist the independent LDS
+    // writes, and their waits, into the middle of the products
+    __builtin_amdgcn_sched_barrier(0);
+    // 4: the next tile into the other buffer (its previous contents were last
+    // read before barrier 1)
+    lds_t<Tc> *nxt = s0 + ((j + 1) & 1) * BUF;
+    la.store(nxt);
+    lb.store(nxt + LoadA::ELEMS);
+    SHORTK_STAGE_TABLES(j & 1, (j + 1) & 1)
+    // 5: the stores, which drain under the next tile's products
+    int tm0, tn0;
+    tile_coords(sb + j * S, tilesM, tilesN, &tm0, &tn0);
+    const lds_t<int64_t> *ct = ctab + (j & 1) * (BM + BN);
+    gett_store_staged<Tin, Tc, BM, BN, WGM, WGN, true>(w, C, ct, ct + BM, M, N, alpha, BETA0 ? 0.0 : beta,
+                                                       int64_t(tm0) * BM, int64_t(tn0) * BN,
+                                                       reinterpret_cast<Tin *>(shortk_sink));
+  }
+#undef SHORTK_FETCH_TABLES
+#undef SHORTK_STAGE_TABLES
+}
+
 // Sum the workspace pieces of each split stream-K tile, in workgroup order,
 // and write alpha * sum + beta * C.  Workgroup (x, y) takes stream-K tile x
 // and accumulator element y = i * FN + j of every thread, so that a tile's
@@ -371,6 +539,15 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
     constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn;
     constexpr int NT = 64 * kTiles[TILE].wgm * kTiles[TILE].wgn;
     if (g.occupancy) {
+      if (g.shortk > 0) {
+        if constexpr (!(VA && VB && shortk_tile(TILE))) {
+          *g.occupancy = 0;
+          return hipSuccess;
+        } else {
+          return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              g.occupancy, gett_shortk_kernel<Tin, Tc, TILE, LA, LB, true>, NT, 0);
+        }
+      }
       if (g.query_sk)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy,
                                                             gett_sk_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
@@ -409,6 +586,21 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
           if (e != hipSuccess) return e;
         }
         return hipSuccess;
+      }
+    }
+    if (g.shortk > 0) {
+      if constexpr (!(VA && VB && shortk_tile(TILE))) {
+        return hipErrorInvalidValue;
+      } else {
+        if (g.K > kShortK) return hipErrorInvalidValue;
+        const dim3 grid(std::min(g.shortk, tilesM * tilesN));
+        if (g.beta == 0.0)
+          hipLaunchKernelGGL((gett_shortk_kernel<Tin, Tc, TILE, LA, LB, true>), grid, dim3(NT), 0, s, A, B, C, g.t,
+                             g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+        else
+          hipLaunchKernelGGL((gett_shortk_kernel<Tin, Tc, TILE, LA, LB, false>), grid, dim3(NT), 0, s, A, B, C, g.t,
+                             g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+        return hipGetLastError();
       }
     }
     if (g.persistent > 0) {

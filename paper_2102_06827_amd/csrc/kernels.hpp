@@ -51,6 +51,7 @@ struct GettLaunch {
   int query_sk = 0;           // with occupancy: of the stream-K kernel instead
   StreamK sk;
   int persistent = 0;         // > 0: this many persistent workgroups walk the tiles (no stream-K)
+  int shortk = 0;             // > 0: the short-summation kernel (K <= 32, tile 3) with this many workgroups
   GettBatch bt;               // batch labels: whole tiles only (no stream-K, not persistent)
 };
 

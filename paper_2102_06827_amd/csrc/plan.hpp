@@ -94,6 +94,9 @@ struct Analysis {
   int sk_tiles = 0, sk_blocks = 0;
   // > 0: the persistent kernel with this many workgroups (short summations)
   int persist = 0;
+  // > 0: the short-summation kernel (stores overlapped with the next tile's
+  // products) with this many workgroups
+  int shortk = 0;
   int split_slices = 5;
 
   TTGTChoice ttgt;

@@ -160,3 +160,50 @@ def test_lds_positions_in_buffer(tile, tc_bytes, VEC, layoutA, layoutB):
         reads = np.concatenate(reads)
         assert reads.min() >= 0 and reads.max() < elems
         assert set(reads.tolist()) <= cover
+
+
+# ---- the short-summation kernel's staging schedule (gett.hip, gett_shortk_kernel)
+def shortk_schedule(ntile):
+    """Replay the LDS staging of one workgroup with `ntile` tiles: which tile's
+    row offsets and C offsets each parity buffer holds when it is read, and
+    which operand buffer holds which tile when it is multiplied.  Returns the
+    list of (step, buffer, tile read, tile expected) for every read."""
+    clamp = lambda j: min(j, ntile - 1)
+    rows = [None, None]   # tile whose row offsets each buffer holds
+    ctab = [None, None]   # tile whose C offsets each buffer holds
+    ops = [None, None]    # tile whose operands each LDS buffer holds
+    reads = []
+    # prologue: rows of tile 0 -> rows[0]; rows of tile 1 -> rows[1], C of tile 0 -> ctab[0]
+    rows[0] = clamp(0)
+    ctab[0] = clamp(0)
+    rows[1] = clamp(1)
+    ctab[0] = clamp(0)
+    ops[0] = 0
+    for j in range(ntile):
+        jn = j + 1 if j + 1 < ntile else j
+        reads.append(("rows", jn & 1, rows[jn & 1], jn))          # step 2: init_from the next tile's rows
+        loaded = jn
+        fetched_rows, fetched_c = clamp(j + 2), clamp(j + 1)
+        reads.append(("mma", j & 1, ops[j & 1], j))               # step 3: products of tile j
+        ops[(j + 1) & 1] = loaded                                 # step 4
+        rows[j & 1] = fetched_rows
+        ctab[(j + 1) & 1] = fetched_c
+        reads.append(("ctab", j & 1, ctab[j & 1], j))             # step 5: stores of tile j
+    return reads
+
+
+@pytest.mark.parametrize("ntile", [1, 2, 3, 4, 5, 32])
+def test_shortk_staging_reads_what_was_written(ntile):
+    for what, buf, got, want in shortk_schedule(ntile):
+        assert got is not None, (what, buf, "read before written")
+        assert got == want, (what, buf, got, want)
+
+
+def test_shortk_staging_without_the_prologue_row_copy_reads_unwritten_lds():
+    """Regression for a fault: without staging tile 0's rows into rows[0] in
+    the prologue, a workgroup with a single tile reloads its tile from an
+    LDS buffer that nothing wrote (garbage row offsets)."""
+    rows = [None, 1]      # only the prologue's rows of tile 1
+    ntile = 1
+    jn = 0
+    assert rows[jn & 1] is None
