@@ -315,9 +315,18 @@ def bench_triples(comet, reps):
     pts = np.stack([rng.integers(0, n, 256) for n in C.shape], axis=1)
     flush = torch.ones(512 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
     out = {}
-    for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2", "split_int8", "f64_ttgt"):
+    for mode in ("f64", "split_bf16", "split_bf16x3", "split_fp16x2", "split_int8", "f64_ttgt", "f64_whole_tiles"):
         if mode == "f64_ttgt":
             plan = comet.Plan(spec, Ad, Bd, C, compute="f64", path="ttgt")
+            run = lambda: plan(Ad, Bd, C)
+        elif mode == "f64_whole_tiles":
+            # the gather kernel with a workgroup per tile, for comparison with
+            # the short-summation kernel the planner takes
+            os.environ["COMET_GETT_SHORTK"] = "0"
+            try:
+                plan = comet.Plan(spec, Ad, Bd, C, compute="f64")
+            finally:
+                os.environ.pop("COMET_GETT_SHORTK", None)
             run = lambda: plan(Ad, Bd, C)
         else:
             run = lambda: comet.contract(spec, Ad, Bd, C, compute=mode)
@@ -336,6 +345,9 @@ def bench_triples(comet, reps):
         out[mode] = {"ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 1),
                      "hbm_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
                      "frac_hbm_peak": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "relerr_vs_oracle": None}
+        if mode == "f64":
+            d = comet.Plan(spec, Ad, Bd, C, compute="f64").describe()
+            out[mode]["schedule"] = {k: d[k] for k in ("path", "tile", "shortk", "sk_tiles")}
     del C, flush
     torch.cuda.empty_cache()
     return out

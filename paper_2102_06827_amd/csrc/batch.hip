@@ -42,8 +42,16 @@ template <int BM, int BN>
 constexpr int f3_lds() { return 3 * (BM + BN) * F3_LDK; }   // A and B, three slices (bf16 elements)
 
 // One BM x BN output tile of the fused BF16x3 product; a WGM x WGN grid of
-// waves, each (BM / WGM) x (BN / WGN) made of 16 x 16 blocks.
-template <int BM, int BN, int WGM, int WGN, int LA, int LB, bool V>
+// waves, each (BM / WGM) x (BN / WGN) made of 16 x 16 blocks.  NBUF = 2
+// double-buffers the sliced tiles in LDS: the next step's values are split
+// and stored into one buffer while the products read the other, so the
+// splitting (VALU and LDS writes) runs under the matrix-core work of the
+// same waves and each step has one barrier; NBUF = 1 (the stand-alone
+// kernel, two workgroups per CU) splits between two barriers.
+template <int BM, int BN>
+constexpr int f3_stage() { return 3 * (BM + BN) * F3_LDK; }
+
+template <int BM, int BN, int WGM, int WGN, int LA, int LB, bool V, int NBUF = 1>
 __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const float *__restrict__ B,
                                             float *__restrict__ C, const GettTables &t, int64_t M, int64_t N,
                                             int64_t K, double alpha, double beta, int64_t m0, int64_t n0,
@@ -53,8 +61,8 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
   typedef Loader<float, float, BN, F3_BK, LB, V, NTH> LoadB;
   constexpr int FM = BM / WGM / 16, FN = BN / WGN / 16;
   static_assert(FM * 16 * WGM == BM && FN * 16 * WGN == BN, "wave tile must be a multiple of 16");
-  lds_t<__bf16> *const sA = to_lds(smem);
-  lds_t<__bf16> *const sB = sA + 3 * BM * F3_LDK;
+  constexpr int STAGE = f3_stage<BM, BN>();
+  lds_t<__bf16> *const s0 = to_lds(smem);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * (BM / WGM), wn0 = (wave % WGN) * (BN / WGN);
   f4_t acc[FM][FN];
@@ -73,10 +81,12 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
   lb.load(B, 0, K);
   la.fetch_k(t.offAk, F3_BK, K);
   lb.fetch_k(t.offBk, F3_BK, K);
-  la.template store_split3<F3_LDK>(sA);
-  lb.template store_split3<F3_LDK>(sB);
+  la.template store_split3<F3_LDK>(s0);
+  lb.template store_split3<F3_LDK>(s0 + 3 * BM * F3_LDK);
   __syncthreads();
   for (int64_t step = 0; step < nsteps; ++step) {
+    lds_t<__bf16> *const sA = s0 + (NBUF == 2 ? int(step & 1) * STAGE : 0);
+    lds_t<__bf16> *const sB = sA + 3 * BM * F3_LDK;
     la.load(A, (step + 1) * F3_BK, K);
     lb.load(B, (step + 1) * F3_BK, K);
     la.fetch_k(t.offAk, (step + 2) * F3_BK, K);
@@ -106,10 +116,18 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
         }
       }
     }
-    __syncthreads();
-    la.template store_split3<F3_LDK>(sA);
-    lb.template store_split3<F3_LDK>(sB);
-    __syncthreads();
+    if constexpr (NBUF == 2) {
+      // the other buffer was last read before the previous barrier
+      lds_t<__bf16> *const nA = s0 + int((step + 1) & 1) * STAGE;
+      la.template store_split3<F3_LDK>(nA);
+      lb.template store_split3<F3_LDK>(nA + 3 * BM * F3_LDK);
+      __syncthreads();
+    } else {
+      __syncthreads();
+      la.template store_split3<F3_LDK>(sA);
+      lb.template store_split3<F3_LDK>(sB);
+      __syncthreads();
+    }
   }
   // the epilogue of the gather kernels (C offsets staged in LDS, which the
   // loop above no longer reads)
@@ -173,7 +191,7 @@ constexpr int native_lds_bytes() {
                                cmax(native_lds_cls<T, 2>(), native_lds_cls<T, 3>()))
                         : native_lds_cls<T, 0>();
 }
-constexpr int fused_lds_bytes() { return int(sizeof(__bf16)) * f3_lds<128, 128>(); }
+constexpr int fused_lds_bytes() { return 2 * int(sizeof(__bf16)) * f3_stage<128, 128>(); }
 
 template <typename T, int MODE, int CLS, int LA, int LB, bool V>
 __device__ __forceinline__ void run_item(const BatchDesc &d, int tile, char *smem) {
@@ -184,7 +202,7 @@ __device__ __forceinline__ void run_item(const BatchDesc &d, int tile, char *sme
                                                     static_cast<T *>(d.C), d.t, d.M, d.N, d.K, d.alpha, d.beta, m0,
                                                     n0, reinterpret_cast<T *>(smem));
   } else {
-    fused3_tile<BM, BN, BatchWaves<1>::WGM, BatchWaves<1>::WGN, LA, LB, V>(
+    fused3_tile<BM, BN, BatchWaves<1>::WGM, BatchWaves<1>::WGN, LA, LB, V, 2>(
         static_cast<const float *>(d.A), static_cast<const float *>(d.B), static_cast<float *>(d.C), d.t, d.M, d.N,
         d.K, d.alpha, d.beta, m0, n0, reinterpret_cast<__bf16 *>(smem));
   }
