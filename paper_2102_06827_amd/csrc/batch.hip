@@ -97,14 +97,14 @@ __device__ __forceinline__ void fused3_tile(const float *__restrict__ A, const f
 #pragma unroll
       for (int j = 0; j < FN; ++j)
         bF[q][j] = *reinterpret_cast<const lds_t<bf16x8> *>(
-            &sB[(q * BN + wn0 + j * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
+            &sB[q * BN * F3_LDK + split3_pos<F3_LDK>(wn0 + j * 16 + (lane & 15), 8 * (lane >> 4))]);
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
       bf16x8 aF[FM];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
         aF[i] = *reinterpret_cast<const lds_t<bf16x8> *>(
-            &sA[(p * BM + wm0 + i * 16 + (lane & 15)) * F3_LDK + 8 * (lane >> 4)]);
+            &sA[p * BM * F3_LDK + split3_pos<F3_LDK>(wm0 + i * 16 + (lane & 15), 8 * (lane >> 4))]);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         if (p + q <= 2) {

@@ -99,6 +99,17 @@ __device__ __forceinline__ void tile_coords(int bid, int tilesM, int tilesN, int
 // divergent branch (which would force a full wait at the join).  The K-offset
 // table entries a step needs are fetched one step ahead, so a data load never
 // waits on the table load that addresses it.
+// Position of element (row, k) in a sliced bfloat16 tile with row pitch LDK
+// (32 summation indices per row): the row's four 8-element chunks are
+// swizzled by (row / 16) mod 4.  Sixteen consecutive rows (one MFMA
+// fragment) share the swizzle, so fragment reads stay as they were, while
+// the stores of an operand contiguous along rows -- one element in each of
+// 32 rows four apart, at one k -- spread over four times as many banks.
+template <int LDK>
+__device__ __forceinline__ int split3_pos(int row, int k) {
+  return row * LDK + ((((k >> 3) ^ (row >> 4)) & 3) << 3) + (k & 7);
+}
+
 template <typename Tin, typename Tc, int R, int BK, int LAYOUT, bool VECLD, int NT>
 struct Loader {
   static constexpr int VEC = V16<Tin>::N;
@@ -211,23 +222,39 @@ struct Loader {
   // Store as three bfloat16 slices x = b0 + b1 + b2 (b0 = bf16(x), b1 = bf16 of
   // the remainder, b2 = bf16 of what is left; exact for FP32 x), in the layout
   // s[slice][row][k] with row pitch LDK (k contiguous, as the 16x16x32 MFMA
-  // operands are read).
+  // operands are read) and the 8-element chunks of a row swizzled by
+  // split3_pos.  K-contiguous operands store each slice's four consecutive k
+  // as one 8-byte write.
   template <int LDK>
   __device__ __forceinline__ void store_split3(lds_t<__bf16> *s) const {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int p = 0; p < P; ++p) {
+      __bf16 b[3][VEC];
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
         const float x = ((vmask >> (p * VEC + i)) & 1u) ? float(v[p][i]) : 0.0f;
-        const __bf16 b0 = __bf16(x);
-        const float r1 = x - float(b0);
-        const __bf16 b1 = __bf16(r1);
-        const __bf16 b2 = __bf16(r1 - float(b1));
-        const int row = LAYOUT == 0 ? rr[p] : rr[p] + i;
-        const int k = LAYOUT == 0 ? kk[p] + i : kk[p];
-        s[(0 * R + row) * LDK + k] = b0;
-        s[(1 * R + row) * LDK + k] = b1;
-        s[(2 * R + row) * LDK + k] = b2;
+        b[0][i] = __bf16(x);
+        const float r1 = x - float(b[0][i]);
+        b[1][i] = __bf16(r1);
+        b[2][i] = __bf16(r1 - float(b[1][i]));
+      }
+      if constexpr (LAYOUT == 0 && VEC == 4) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          bf16x4 w;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) w[i] = b[q][i];
+          *reinterpret_cast<lds_t<bf16x4> *>(&s[q * R * LDK + split3_pos<LDK>(rr[p], kk[p])]) = w;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+          const int row = LAYOUT == 0 ? rr[p] : rr[p] + i;
+          const int k = LAYOUT == 0 ? kk[p] + i : kk[p];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) s[q * R * LDK + split3_pos<LDK>(row, k)] = b[q][i];
+        }
       }
     }
   }
