@@ -59,8 +59,8 @@
  *          COMET_ERR_HIP; a device fault surfaces at the caller's next sync.
  * determinism  the same plan and inputs give bit-identical outputs: no
  *          atomics in any reduction; where the summation of an output tile
- *          is split across workgroups (stream-K), the pieces are added in a
- *          fixed order.
+ *          is split across workgroups (stream-K, or the balanced schedule's
+ *          pieces), the pieces are added in a fixed order.
  */
 #ifndef COMET_H
 #define COMET_H
@@ -185,9 +185,11 @@ comet_status_t comet_contract(const char *spec, const int64_t *extents,
  * Pointer arguments of execute must satisfy the alignment the plan was
  * made for; misaligned pointers take the scalar gather, never an error.
  * The workspace holds TTGT's permuted operands, the split modes' slices, or
- * the partial sums of a stream-K schedule (output tiles whose summation is
- * split over several workgroups and summed afterwards in a fixed order, so
- * results do not depend on timing); its contents on entry do not matter and
+ * the partial sums of a stream-K or balanced schedule (output tiles whose
+ * summation is split over several workgroups and summed afterwards in a
+ * fixed order, so results do not depend on timing; the balanced schedule
+ * cuts the tiles left after the last full round of whole tiles into one
+ * more full round of equal pieces); its contents on entry do not matter and
  * executions that share one workspace must not overlap.
  */
 comet_status_t comet_plan_create(comet_plan_t *plan, const char *spec, const int64_t *extents,
@@ -229,7 +231,9 @@ comet_status_t comet_plan_execute_noalloc(comet_plan_t plan, double alpha, const
  * label classes after fusion ("M", "N", "K" and the batch labels "X", with
  * extents and strides), flattened sizes m, n, k and batch entries nb,
  * operand layouts and contiguous runs, tile shape, stream-K split
- * (sk_tiles, sk_blocks), persistent workgroups, resident workgroups per CU,
+ * (sk_tiles, sk_blocks; with even = 1 the balanced schedule: the first
+ * even_whole tiles whole, then the sk_tiles leftover tiles cut into sk_blocks
+ * pieces), persistent workgroups, resident workgroups per CU,
  * the split tile and whether FP32 BF16x3 runs fused, TTGT permutations and
  * cost.  COMET_ERR_WORKSPACE if buf is too small (the text is truncated). */
 comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len);

@@ -234,6 +234,7 @@ int tile_resident(const Analysis &an, int tile, bool vecA, bool vecB) {
 struct Schedule {
   int tile = 1;
   int sk_tiles = 0, sk_blocks = 0;
+  int even = 0, even_whole = 0;
   int persist = 0;
   double us = 1e300;
 };
@@ -424,6 +425,47 @@ Schedule pick_schedule(const Analysis &an, int cus, bool vecA, bool vecB, int fo
   return best;
 }
 
+// The balanced schedule replaces a stream-K split of the last, partial round
+// when that round has at most half as many tiles as there are resident
+// workgroups: the leftover tiles are cut into one full round of equal
+// summation pieces, run at the whole-tile kernel's occupancy (the stream-K
+// kernel, which may cross tiles, needs more registers and runs at a lower
+// one).  COMET_GETT_EVEN=0 turns it off; =1 takes it wherever it fits, also
+// where the model keeps whole tiles.
+void even_choice(const Analysis &an, int cus, bool vecA, bool vecB, Schedule &sc) {
+  const char *env = std::getenv("COMET_GETT_EVEN");
+  const int mode = env && *env ? std::atoi(env) : -1;
+  const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
+  if (mode == 0 || !native || !vecA || !vecB || !an.X.empty() || an.empty_out || an.empty_sum || sc.persist > 0 ||
+      std::getenv("COMET_GETT_SK"))
+    return;
+  if (mode < 0 && sc.sk_tiles == 0) return;
+  // full rounds of the whole-tile kernel, then one round of the piece
+  // kernel (at most as many workgroups per CU)
+  GettLaunch g{};
+  g.dtype = an.dtype == COMET_F64 ? 0 : 1;
+  g.compute = an.compute == COMET_COMPUTE_F64 ? 0 : 1;
+  g.layoutA = an.layoutA;
+  g.layoutB = an.layoutB;
+  g.vecA = g.vecB = 1;
+  g.tile = sc.tile;
+  g.query_sk = 2;
+  const int res = tile_resident(an, sc.tile, true, true), res_p = std::min(gett_occupancy(g), res);
+  if (res <= 0 || res_p <= 0) return;
+  int bm, bn, bk;
+  gett_tile_shape(sc.tile, &bm, &bn, &bk);
+  const int64_t T = ((an.m + bm - 1) / bm) * ((an.n + bn - 1) / bn);
+  const int64_t C = std::max(cus, 1);
+  const int64_t S = C * res, Sp = C * res_p;
+  const int64_t nk = (an.k + bk - 1) / bk;
+  const int64_t q = T / S, R = T - q * S;
+  if (R == 0 || 2 * R > Sp || T > INT32_MAX || nk < kSkSmallSteps * ((Sp + R - 1) / R)) return;
+  sc.even = 1;
+  sc.even_whole = int(q * S);
+  sc.sk_tiles = int(R);
+  sc.sk_blocks = int(Sp);
+}
+
 // Short summations with many output tiles take the short-summation kernel
 // (tile 3, stores overlapped with the next tile's products): on MI355X the
 // K = 32 triples contraction's whole-tile kernel runs its products and its
@@ -462,13 +504,18 @@ void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
   if (an.shortk > 0) {
     sc.tile = 3;
     sc.sk_tiles = sc.sk_blocks = 0;
+  } else {
+    even_choice(an, cus, p->vecA_tables, p->vecB_tables, sc);
   }
   an.tile = sc.tile;
   an.sk_tiles = sc.sk_tiles;
   an.sk_blocks = sc.sk_blocks;
+  an.even = sc.even;
+  an.even_whole = sc.even_whole;
   an.persist = sc.persist;
   const size_t slot = gett_sk_slot_bytes(sc.tile, an.compute == COMET_COMPUTE_F64 ? 0 : 1);
-  p->sk_bytes = sc.sk_tiles > 0 ? align256(2 * size_t(sc.sk_blocks) * slot) : 0;
+  // stream-K: two slots per workgroup (its first and last tile); balanced: one
+  p->sk_bytes = sc.sk_tiles > 0 ? align256(size_t(sc.even ? 1 : 2) * size_t(sc.sk_blocks) * slot) : 0;
 }
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
@@ -612,7 +659,7 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   // (or reads its cache), and a forced gather schedule keeps the gather path.
   const bool tuning = tune && tune_cache().mode() != 0;
   const bool gather_forced = std::getenv("COMET_GETT_TILE") || std::getenv("COMET_GETT_SK") ||
-                             std::getenv("COMET_GETT_PERSIST");
+                             std::getenv("COMET_GETT_PERSIST") || std::getenv("COMET_GETT_EVEN");
   if (path == COMET_PATH_AUTO && native && !tuning && !gather_forced && an.path == COMET_PATH_GETT &&
       an.X.empty() && !an.empty_out && !an.empty_sum && !(p->vecA_tables && p->vecB_tables)) {
     std::unique_ptr<comet_plan_s> tt;
@@ -686,6 +733,14 @@ comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, cons
     g.sk.tiles = an.sk_tiles;
     g.sk.blocks = an.sk_blocks;
     g.sk.ws = ws;
+    // the balanced schedule reads vectors: with a misaligned operand every
+    // tile is computed whole
+    if (an.even && g.vecA && g.vecB) {
+      g.sk.even = 1;
+      g.sk.whole = an.even_whole;
+    } else if (an.even) {
+      g.sk = StreamK{};
+    }
   }
   if (an.persist > 0 && g.tile == an.tile) g.persistent = an.persist;
   if (an.shortk > 0 && g.tile == an.tile && g.vecA && g.vecB) g.shortk = an.shortk;
@@ -929,7 +984,7 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
     return autotune_split(p.get(), tc);
   if (tc.mode() == 0 || !native || an.empty_out || an.empty_sum) return COMET_OK;
   if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH") || std::getenv("COMET_GETT_SK") ||
-      std::getenv("COMET_GETT_PERSIST"))
+      std::getenv("COMET_GETT_PERSIST") || std::getenv("COMET_GETT_EVEN"))
     return COMET_OK;
   const std::string key = tune_key(an, arch_id(p->device));
   TuneEntry best;
@@ -1376,7 +1431,7 @@ std::string cache_key(const char *spec, const int64_t *ext, size_t nlab, const i
        std::to_string(g_split_slices) + "|" + std::to_string(g_int8_slices);
   // every planner override in the environment
   for (const char *name : {"COMET_FORCE_PATH", "COMET_TTGT_ORDER", "COMET_GETT_TILE", "COMET_GETT_SK",
-                           "COMET_GETT_PERSIST", "COMET_GETT_SHORTK", "COMET_SPLIT_TILE", "COMET_FUSED3"}) {
+                           "COMET_GETT_PERSIST", "COMET_GETT_SHORTK", "COMET_GETT_EVEN", "COMET_SPLIT_TILE", "COMET_FUSED3"}) {
     const char *v = std::getenv(name);
     k += "|";
     if (v) k += v;

@@ -310,6 +310,86 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
   }
 }
 
+// Balanced schedule for a tile count just above a whole number of rounds
+// (the CCSD-like headline: 576 tiles of 128 x 128 on 512 resident
+// workgroups).  The whole-tile kernel computes the full rounds (sk.whole
+// tiles); the R = sk.tiles leftover tiles then share one more round of
+// S = sk.blocks workgroups, tile r taking workgroups
+// first(r) = floor(S r / R) .. first(r + 1) - 1, which cut its summation into
+// that many equal pieces (give or take a step).  Every workgroup of a round
+// so runs the same work -- stream-K instead gives the leftover tiles a kernel
+// of its own at a lower occupancy.  A piece is written to workspace slot b;
+// gett_piece_fixup_kernel sums a leftover tile's slots in piece order, so
+// the result does not depend on timing.  The piece kernel is a whole-tile
+// kernel over a shorter summation (the k tables moved to the piece's first
+// index), so it keeps that kernel's registers and occupancy: one fused
+// kernel doing the whole tiles and then the piece needed more registers than
+// two workgroups per CU leave, and spilled.
+__device__ __forceinline__ int even_first(int S, int R, int r) { return int(int64_t(S) * r / R); }
+
+// a wave-uniform 64-bit value, held in scalar registers
+__device__ __forceinline__ int64_t scalar64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x)));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x) >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_piece_kernel(
+    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+    int64_t K, double alpha, double beta, int tilesM, int tilesN, StreamK sk) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
+  const int S = sk.blocks, R = sk.tiles, b = blockIdx.x;
+  // leftover tile r: the largest r with first(r) <= b
+  const int r = int((int64_t(b + 1) * R - 1) / S);
+  const int f0 = even_first(S, R, r), P = even_first(S, R, r + 1) - f0, j = b - f0;
+  const int64_t nk = (K + BK - 1) / BK;
+  // the divisions run on the vector unit: move their (uniform) results back
+  // to scalar registers, or the loop's bounds and k indices would take
+  // vector registers the accumulation has none left for
+  const int64_t k0 = scalar64(nk * j / P * BK), k1 = nk * (j + 1) / P * BK;
+  const int64_t Kp = scalar64((k1 < K ? k1 : K) - k0);
+  GettTables tk = t;
+  tk.offAk += k0;
+  tk.offBk += k0;
+  int tm, tn;
+  group_coords(sk.whole + r, tilesM, tilesN, &tm, &tn);
+  WT w;
+  gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(w, A, B, tk, M, N, Kp, int64_t(tm) * BM,
+                                                                 int64_t(tn) * BN, 0, (Kp + BK - 1) / BK, smem);
+  constexpr int64_t kSlot = int64_t(WT::FM) * WT::FN * NT;   // 4-vectors per slot
+  gett_store_partial<Tc, BM, BN, WGM, WGN>(w, static_cast<typename WT::acc_t *>(sk.ws) + b * kSlot);
+}
+
+// Sum the pieces of each leftover tile of the balanced schedule in piece
+// order and write alpha * sum + beta * C.  Workgroup (r, f) takes leftover
+// tile r and accumulator element f = i * FN + j of every thread.
+template <typename Tin, typename Tc, int TILE>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn) void gett_piece_fixup_kernel(
+    Tin *__restrict__ C, GettTables t, int64_t M, int64_t N, double alpha, double beta, int tilesM, int tilesN,
+    StreamK sk) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
+  typedef typename WT::acc_t acc_t;
+  const int r = blockIdx.x, f = blockIdx.y;
+  const int f0 = even_first(sk.blocks, sk.tiles, r), f1 = even_first(sk.blocks, sk.tiles, r + 1);
+  const glb_t<const acc_t> *const ws = to_glb(static_cast<const acc_t *>(sk.ws));
+  constexpr int64_t kSlot = int64_t(WT::FM) * WT::FN * NT;
+  const int64_t e = int64_t(f) * NT + threadIdx.x;
+  acc_t v = ws[f0 * kSlot + e];
+  for (int p = f0 + 1; p < f1; ++p) v = v + ws[p * kSlot + e];
+  int tm, tn;
+  group_coords(sk.whole + r, tilesM, tilesN, &tm, &tn);
+  gett_store_fragment<Tin, Tc, BM, BN, WGM, WGN>(v, f / WT::FN, f % WT::FN, C, t, M, N, alpha, beta,
+                                                 int64_t(tm) * BM, int64_t(tn) * BN);
+}
+
 // Short summations (K <= kShortK) with large outputs, such as the triples
 // contraction (K = 32, a 1 GB output): the time goes to the MFMA phase and
 // to the output stores, and a workgroup per tile runs them one after the
@@ -548,6 +628,9 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
               g.occupancy, gett_shortk_kernel<Tin, Tc, TILE, LA, LB, true>, NT, 0);
         }
       }
+      if (g.query_sk == 2)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy,
+                                                            gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
       if (g.query_sk)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy,
                                                             gett_sk_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
@@ -613,6 +696,27 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
                            g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
         return hipGetLastError();
       }
+    }
+    if (g.sk.even) {
+      // the balanced schedule: its shape must match the tile grid exactly
+      const StreamK &ev = g.sk;
+      if (!ev.ws || ev.blocks <= 0 || ev.whole < 0 || ev.tiles < 1 || 2 * int64_t(ev.tiles) > ev.blocks ||
+          int64_t(ev.whole) + ev.tiles != int64_t(tilesM) * tilesN)
+        return hipErrorInvalidValue;
+      if (ev.whole > 0) {
+        hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.whole), dim3(NT), 0, s, A, B, C, g.t,
+                           g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL((gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.blocks), dim3(NT), 0, s, A, B, C,
+                         g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, ev);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      constexpr int FRAGS = (BM / kTiles[TILE].wgm / 16) * (BN / kTiles[TILE].wgn / 16);
+      hipLaunchKernelGGL((gett_piece_fixup_kernel<Tin, Tc, TILE>), dim3(ev.tiles, FRAGS), dim3(NT), 0, s, C, g.t, g.M,
+                         g.N, g.alpha, g.beta, tilesM, tilesN, ev);
+      return hipGetLastError();
     }
     StreamK sk = g.sk;
     if (sk.blocks <= 0 || sk.tiles <= 0 || sk.tiles > tilesM * tilesN || !sk.ws) sk = StreamK{};

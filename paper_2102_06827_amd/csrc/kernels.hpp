@@ -21,6 +21,14 @@ struct StreamK {
   int tiles = 0;
   int blocks = 0;
   void *ws = nullptr;
+  // nonzero: the balanced schedule instead: the first `whole` tiles whole
+  // (gett_kernel), then one round of `blocks` workgroups (gett_piece_kernel)
+  // that split the `tiles` leftover tiles along the summation, tile r into
+  // the pieces floor(blocks * r / tiles) .. floor(blocks * (r + 1) / tiles) - 1
+  // (at least two), which gett_piece_fixup_kernel sums; ws holds one slot
+  // per piece
+  int even = 0;
+  int whole = 0;
 };
 
 // Batch labels: entries first .. first + count - 1 of the per-entry base
@@ -48,7 +56,7 @@ struct GettLaunch {
   int vecA, vecB;      // 16-byte vector loads allowed
   int tile;            // tile variant
   int *occupancy = nullptr;   // when set: store the resident workgroups per CU, launch nothing
-  int query_sk = 0;           // with occupancy: of the stream-K kernel instead
+  int query_sk = 0;           // with occupancy: of the stream-K kernel instead (2: of the balanced one)
   StreamK sk;
   int persistent = 0;         // > 0: this many persistent workgroups walk the tiles (no stream-K)
   int shortk = 0;             // > 0: the short-summation kernel (K <= 32, tile 3) with this many workgroups

@@ -92,6 +92,10 @@ struct Analysis {
   // stream-K: the last sk_tiles output tiles are split along K over
   // sk_blocks workgroups (0: every tile is computed whole)
   int sk_tiles = 0, sk_blocks = 0;
+  // nonzero: the balanced schedule instead of stream-K -- the first
+  // even_whole tiles whole (full rounds of the whole-tile kernel), then the
+  // sk_tiles leftover tiles cut into sk_blocks summation pieces
+  int even = 0, even_whole = 0;
   // > 0: the persistent kernel with this many workgroups (short summations)
   int persist = 0;
   // > 0: the short-summation kernel (stores overlapped with the next tile's

@@ -8,8 +8,9 @@ last tile) and are summed per tile, in workgroup order, by the fixup kernel.
 This mirror re-derives every piece and checks that the steps of every tile
 are covered exactly once, that every slot index lies inside the 2*blocks
 slots the plan allocates, that no slot is written twice, and that the fixup
-reads exactly the slots written for its tile.  The mirror must be kept in
-step with the device code.
+reads exactly the slots written for its tile.  The same for the balanced
+schedule's pieces (gett_piece_kernel, gett_piece_fixup_kernel).  The mirror
+must be kept in step with the device code.
 """
 import pytest
 
@@ -102,3 +103,63 @@ def test_owner_matches_shares():
         for x in range(0, I, max(1, I // 200)):
             s = sk_owner(I, blocks, x)
             assert sk_begin(I, blocks, s) <= x < sk_begin(I, blocks, s + 1)
+
+
+# ---- the balanced schedule (gett_piece_kernel, gett_piece_fixup_kernel) ----
+# S workgroups share R leftover tiles: tile r takes workgroups
+# first(r) = floor(S r / R) .. first(r + 1) - 1, workgroup b finds its tile as
+# r = floor(((b + 1) R - 1) / S) and its piece j = b - first(r) of P = first(r
+# + 1) - first(r) pieces covers the summation indices
+# [floor(nk j / P) BK, floor(nk (j + 1) / P) BK) clipped to K.
+
+def even_first(S, R, r):
+    return S * r // R
+
+
+def even_pieces(S, R, K, BK):
+    nk = -(-K // BK)
+    out = []
+    for b in range(S):
+        r = ((b + 1) * R - 1) // S
+        f0 = even_first(S, R, r)
+        P = even_first(S, R, r + 1) - f0
+        j = b - f0
+        k0 = nk * j // P * BK
+        k1 = nk * (j + 1) // P * BK
+        out.append((b, r, k0, min(k1, K) - k0, P))
+    return out
+
+
+@pytest.mark.parametrize("S,R", [(512, 64), (512, 73), (512, 253), (512, 256), (1024, 216), (768, 240),
+                                 (256, 1), (7, 3), (5, 2), (2048, 824)])
+@pytest.mark.parametrize("K", [3072, 232, 16 * 35 - 8])
+def test_balanced_pieces_cover_each_leftover_tile_once(S, R, K):
+    BK = 16
+    nk = -(-K // BK)
+    P_max = -(-S // R)
+    if nk < 4 * P_max:
+        pytest.skip("the planner needs at least four steps per piece")
+    ps = even_pieces(S, R, K, BK)
+    # every workgroup has one piece; the owner formula inverts first()
+    for b, r, k0, kn, P in ps:
+        assert 0 <= r < R
+        assert even_first(S, R, r) <= b < even_first(S, R, r + 1)
+        assert P >= 2 and kn > 0
+        # the piece kernel's summation range lies inside the tables
+        assert 0 <= k0 and k0 + kn <= K
+    # per tile: pieces in slot order tile [0, K) without gaps or overlaps
+    for r in range(R):
+        mine = [(k0, kn) for b, rr, k0, kn, P in ps if rr == r]
+        assert len(mine) == even_first(S, R, r + 1) - even_first(S, R, r)
+        at = 0
+        for k0, kn in mine:
+            assert k0 == at
+            at += kn
+        assert at == K
+        # piece lengths differ by at most one step within a tile
+        lens = [kn for k0, kn in mine[:-1]]
+        if lens:
+            assert max(lens) - min(lens) <= BK
+    # piece counts differ by at most one between tiles
+    counts = [even_first(S, R, r + 1) - even_first(S, R, r) for r in range(R)]
+    assert max(counts) - min(counts) <= 1
