@@ -28,6 +28,10 @@ The same line also carries, each timed with HIP events on the launch stream:
   batch_labels  contractions with a label in C, A and B (batched products),
              against torch.bmm where the layout allows;
   roofline   of the headline kernel; cpu_baseline: the oracle on the host.
+
+Before each timed region the workload runs untimed for a quarter of a second
+(on top of the warm-up steps), so that every figure is taken at the clocks
+the GPU sustains under load rather than during their ramp from idle.
 """
 from __future__ import annotations
 
@@ -49,20 +53,24 @@ FLOPS = 2.0 * V ** 3 * O ** 3            # 2 * M * N * K, M = N = K = 3072
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "i8": 5033.2}
 HBM_PEAK_GBS = 8000.0
 # The headline contraction runs as one launch group of the gather kernel:
-# whole output tiles (gett_kernel), the stream-K pieces of the tiles left
-# after the last full round (gett_sk_kernel) and the sum of those pieces
-# (gett_fixup_kernel).  HBM bytes of one group from FETCH_SIZE / WRITE_SIZE
+# whole output tiles (gett_kernel), the summation pieces of the tiles left
+# after the last full round (gett_piece_kernel, or gett_sk_kernel when
+# stream-K is planned) and the sum of those pieces (gett_piece_fixup_kernel
+# or gett_fixup_kernel).  HBM bytes of one group from FETCH_SIZE / WRITE_SIZE
 # counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
 # valid only for the schedule and kernel version recorded, null otherwise.
-HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 256}, "kernel_version": "k7",
-                    "bytes": 812120259}
-KERNEL_VERSION = "k7"
+HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512, "even": 1}, "kernel_version": "k9",
+                    "bytes": 940968320}
+KERNEL_VERSION = "k9"
 
 
 def headline_kernels(d):
     t = d["tile"]
     ks = ["gett_kernel<double, double, %d, 0, 1, true, true>" % t]
-    if d.get("sk_tiles"):
+    if d.get("sk_tiles") and d.get("even"):
+        ks += ["gett_piece_kernel<double, double, %d, 0, 1, true, true>" % t,
+               "gett_piece_fixup_kernel<double, double, %d>" % t]
+    elif d.get("sk_tiles"):
         ks += ["gett_sk_kernel<double, double, %d, 0, 1, true, true>" % t, "gett_fixup_kernel<double, double, %d>" % t]
     return ks
 MODES = {
@@ -133,6 +141,20 @@ def make_inputs():
     B = synth.decayed_normal(synth.config_seed(2, "B"), "bkcj", shape("bkcj"), "abc", "ijk")
     C0 = synth.decayed_normal(synth.config_seed(2, "C0"), "abij", shape("abij"), "abc", "ijk")
     return A, B, C0
+
+
+def prime(fn, seconds=0.25):
+    """Run fn untimed for about `seconds`, synchronizing every few calls, so
+    that the timed runs that follow start at the sustained clocks: on MI355X
+    a kernel sequence started from idle takes some 25 ms of load to get
+    there (the headline gather kernel ramps from about 1.0 to 0.82 ms per
+    call), and host work between sections lets the clocks drop again."""
+    import torch
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
 
 
 def timed(fn, reps, stream):
@@ -248,6 +270,7 @@ def bench_modes(comet, A, B, C0, steps, warmup, want):
                          got, C0.astype(np.float32), 1.0, 1.0, cfg["tol"])
         else:
             check_points(["modes", name, "relerr_vs_oracle"], SPEC, A, B, pts, got, C0, 1.0, 1.0, cfg["tol"])
+        prime(run)
         for _ in range(warmup):
             run()
         ms = timed(run, steps, stream)
@@ -291,6 +314,7 @@ def bench_backward(comet, A, B, C0, reps):
                      dA[tuple(torch.from_numpy(ptsA).to(dev).T)].cpu().numpy())
         check_points(["backward", mode, "relerr_dB"], sb, A, W, ptsB,
                      dB[tuple(torch.from_numpy(ptsB).to(dev).T)].cpu().numpy())
+        prime(step)
         ms = timed(step, reps, stream)
         out[mode] = {"ms": round(ms, 4), "gflops": round(3 * FLOPS / (ms * 1e-3) / 1e9, 1),
                      "relerr_dA": None, "relerr_dB": None}
@@ -334,6 +358,7 @@ def bench_triples(comet, reps):
         torch.cuda.synchronize()
         check_points(["triples", mode, "relerr_vs_oracle"], spec, A, B, pts,
                      C[tuple(torch.from_numpy(pts).to(dev).T)].cpu().numpy())
+        prime(run)
         tot = 0.0
         for _ in range(reps):
             # evict the 256 MB last-level cache between runs by reading 512 MB:
@@ -497,6 +522,7 @@ def bench_ttgt_study(comet, reps=3):
         ref(A, B, C, beta=beta)
         torch.cuda.synchronize()
         R = C.clone()
+        prime(lambda: ref(A, B, C, beta=beta))
         t_gett = timed(lambda: ref(A, B, C, beta=beta), reps, stream)
         M = [l for l in a if l in c]
         N = [l for l in b if l in c]
@@ -612,6 +638,7 @@ def bench_batch(comet, reps, n=1024):
             batch(workspace=ws)
         g.replay()
         torch.cuda.synchronize()
+        prime(g.replay)
         ms = timed(g.replay, reps, torch.cuda.current_stream())
         gflops = flops / (ms * 1e-3) / 1e9
         mf = "f32" if mode == "default" else "bf16"
@@ -688,6 +715,70 @@ def bench_batch_labels(comet, reps=5):
     return out
 
 
+def profile_pass(comet, which):
+    """Each workload a few times, untimed, for a profiler's kernel-trace or
+    counter pass (the counters of a kernel do not depend on the operand
+    values, so the batched workload takes plain random values).  About one
+    second of headline products first brings the clocks up, so that the
+    trace's durations are those of the timed runs."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    A, B, C0 = make_inputs()
+    Ad, Bd, Cd = (torch.from_numpy(x).to(dev) for x in (A, B, C0))
+    p = comet.Plan(SPEC, Ad, Bd, Cd, compute="f64")
+    t_end = time.perf_counter() + 1.0
+    while time.perf_counter() < t_end:
+        p(Ad, Bd, Cd, beta=1.0)
+        torch.cuda.synchronize()
+    print("warm-up done", flush=True)
+    if "headline" in which or "split" in which:
+        if "headline" in which:
+            for _ in range(10):
+                p(Ad, Bd, Cd, beta=1.0)
+            torch.cuda.synchronize()
+            print("headline done", flush=True)
+        if "split" in which:
+            for mode in ("split_bf16", "split_int8", "split_bf16x3", "split_fp16x2", "f32"):
+                if mode == "f32":
+                    A32, B32, C32 = Ad.float(), Bd.float(), Cd.float()
+                    p = comet.Plan(SPEC, A32, B32, C32)
+                    for _ in range(3):
+                        p(A32, B32, C32, beta=1.0)
+                else:
+                    p = comet.Plan(SPEC, Ad, Bd, Cd, compute=mode)
+                    for _ in range(3):
+                        p(Ad, Bd, Cd, beta=1.0)
+                torch.cuda.synchronize()
+                print(mode, "done", flush=True)
+    if "triples" in which:
+        A = torch.rand((32, 32, 16, 16), dtype=torch.float64, device=dev)
+        B = torch.rand((32, 32, 32, 16), dtype=torch.float64, device=dev)
+        C = torch.empty((32, 32, 32, 16, 16, 16), dtype=torch.float64, device=dev)
+        p = comet.Plan("abcijk=daij*bcdk", A, B, C)
+        for _ in range(10):
+            p(A, B, C)
+        torch.cuda.synchronize()
+        print("triples done", flush=True)
+    if "batch" in which:
+        f = torch.float32
+        problems = []
+        for i, (spec, ext) in enumerate(synth.batch_problems(1024, synth.config_seed(5, "A"))):
+            c, a, b = split_spec(spec)
+            A = torch.rand(shape(a, ext), dtype=f, device=dev)
+            B = torch.rand(shape(b, ext), dtype=f, device=dev)
+            W = torch.rand(shape(c, ext), dtype=f, device=dev)
+            sa, sb = grad_specs(spec)
+            problems += [dict(spec=spec, A=A, B=B, C=torch.empty(shape(c, ext), dtype=f, device=dev)),
+                         dict(spec=sa, A=W, B=B, C=torch.empty_like(A)),
+                         dict(spec=sb, A=A, B=W, C=torch.empty_like(B))]
+        for mode in ("default", "split_bf16x3"):
+            bt = comet.Batch(problems, dtype=f, compute=mode)
+            bt()
+            torch.cuda.synchronize()
+            print("batch", mode, "done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -701,6 +792,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MB (HBM counter calibration)")
+    ap.add_argument("--profile-pass", default="",
+                    help="only run each named workload a few times, untimed, for a profiler's counter pass "
+                         "(comma list of headline, split, triples, batch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -720,6 +814,10 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}), flush=True)
         return
 
+    if args.profile_pass:
+        profile_pass(comet, args.profile_pass.split(","))
+        return
+
     A, B, C0 = make_inputs()
     # bring the clocks up before anything is timed (about one second of work)
     Ah, Bh = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
@@ -734,13 +832,14 @@ def main():
     if "f64" not in want:
         want = ["f64"] + want
     modes = bench_modes(comet, A, B, C0, args.steps, args.warmup, want)
+    print("[bench] headline modes done", file=sys.stderr, flush=True)
     head = modes["f64"]
     ms = head["ms"]
     achieved = FLOPS / (ms * 1e-3) / 1e12
     Ad = torch.empty(shape("acik"), dtype=torch.float64, device="cuda")
     Bd = torch.empty(shape("bkcj"), dtype=torch.float64, device="cuda")
     sched = comet.Plan(SPEC, Ad, Bd, compute="f64").describe()
-    sched = {k: sched[k] for k in ("path", "tile", "sk_tiles", "sk_blocks", "resident")}
+    sched = {k: sched[k] for k in ("path", "tile", "sk_tiles", "sk_blocks", "even", "even_whole", "resident")}
     del Ad, Bd
     same = (HEADLINE_TRAFFIC["kernel_version"] == KERNEL_VERSION and
             all(HEADLINE_TRAFFIC["schedule"][k] == sched[k] for k in HEADLINE_TRAFFIC["schedule"]))
@@ -784,11 +883,14 @@ def main():
             if name not in sections:
                 print("unknown section %r" % name, file=sys.stderr)
                 sys.exit(2)
+            t0 = time.perf_counter()
             line[name] = sections[name]()
+            print("[bench] %s done in %.1f s" % (name, time.perf_counter() - t0), file=sys.stderr, flush=True)
     if not args.no_cpu:
         # the CPU leg: oracle references for every recorded check, and the
         # oracle's own throughput
         cpu_leg(line, A, B, C0)
+        print("[bench] cpu leg done", file=sys.stderr, flush=True)
     if "config1" in line:
         line["config1"].pop("A")
         line["config1"].pop("B")
