@@ -823,7 +823,8 @@ comet_status_t execute_one(const comet_plan_s *p, double alpha, const void *A, c
   if (an.compute == COMET_COMPUTE_SPLIT_BF16 || an.compute == COMET_COMPUTE_SPLIT_BF16X3 ||
       an.compute == COMET_COMPUTE_SPLIT_FP16X2 || an.compute == COMET_COMPUTE_SPLIT_INT8) {
     const void *Ak = an.swapped ? B : A, *Bk = an.swapped ? A : B;
-    HIP_TRY(split_execute(an, p->split, p->t, alpha, Ak, Bk, beta, C, ws, s), "split launch");
+    HIP_TRY(split_execute(an, p->split, p->t, alpha, Ak, Bk, beta, C, ws, s, p->vecA_tables, p->vecB_tables),
+            "split launch");
     return COMET_OK;
   }
   if (an.path == COMET_PATH_TTGT) {

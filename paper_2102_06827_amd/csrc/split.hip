@@ -84,15 +84,17 @@ constexpr int PT = 256;   // slicer threads
 constexpr int PI = PR * PK / PT;   // elements per thread per tile
 
 // Element e (0..PI-1) of thread tid in a PR x PK tile.  Threads walk the
-// operand's unit-stride dimension: k for LAYOUT 0, rows for LAYOUT 1.
-template <int LAYOUT>
+// operand's unit-stride dimension: k for LAYOUT 0, rows for LAYOUT 1, V
+// consecutive elements at a time (V > 1: one vector load of V elements that
+// are contiguous in memory, where the offset tables allow it).
+template <int LAYOUT, int V>
 __device__ __forceinline__ void tile_pos(int tid, int e, int *rl, int *kl) {
   if (LAYOUT == 0) {
-    *kl = tid % PK;
-    *rl = tid / PK + (PT / PK) * e;
+    *kl = (tid % (PK / V)) * V + e % V;
+    *rl = tid / (PK / V) + (PT / (PK / V)) * (e / V);
   } else {
-    *rl = tid % PR;
-    *kl = tid / PR + (PT / PR) * e;
+    *rl = (tid % (PR / V)) * V + e % V;
+    *kl = tid / (PR / V) + (PT / (PR / V)) * (e / V);
   }
 }
 
@@ -100,51 +102,74 @@ __device__ __forceinline__ void tile_pos(int tid, int e, int *rl, int *kl) {
 // the operand.  ro[e] holds the row offset of element e (hoisted by the
 // caller: rows are fixed per thread).  The loads are branch-free -- clamped
 // indices, zeros applied afterwards -- so that all of them are in flight at
-// once instead of one wait per element.
-template <typename Tin, int LAYOUT>
+// once instead of one wait per element.  With V > 1 the vector's first
+// element is addressed and the vector is loaded whole: the offset tables then
+// make V consecutive indices along the unit-stride dimension contiguous and
+// V-aligned, and that dimension's extent a multiple of V, so a vector is
+// either inside the operand or wholly outside (and then clamped to the last
+// vector).
+template <typename Tin, int LAYOUT, int V>
 __device__ __forceinline__ void load_tile(double *x, const Tin *__restrict__ base, const int64_t *ro,
                                           const int64_t *__restrict__ offK, int64_t r0, int64_t k0, int64_t R,
                                           int64_t K) {
   const int tid = threadIdx.x;
   Tin v[PI];
+  if constexpr (V == 1) {
 #pragma unroll
-  for (int e = 0; e < PI; ++e) {
-    int rl, kl;
-    tile_pos<LAYOUT>(tid, e, &rl, &kl);
-    const int64_t k = k0 + kl;
-    v[e] = base[ro[e] + offK[k < K ? k : K - 1]];
+    for (int e = 0; e < PI; ++e) {
+      int rl, kl;
+      tile_pos<LAYOUT, V>(tid, e, &rl, &kl);
+      const int64_t k = k0 + kl;
+      v[e] = base[ro[e] + offK[k < K ? k : K - 1]];
+    }
+  } else {
+    typedef Tin vec_t __attribute__((ext_vector_type(V)));
+    // LAYOUT 0: the vector runs along k, so its start is clamped to K - V
+    const int64_t klast = LAYOUT == 0 ? K - V : K - 1;
+#pragma unroll
+    for (int e = 0; e < PI; e += V) {
+      int rl, kl;
+      tile_pos<LAYOUT, V>(tid, e, &rl, &kl);
+      const int64_t k = k0 + kl;
+      const vec_t w = *reinterpret_cast<const vec_t *>(base + ro[e] + offK[k <= klast ? k : klast]);
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[e + i] = w[i];
+    }
   }
 #pragma unroll
   for (int e = 0; e < PI; ++e) {
     int rl, kl;
-    tile_pos<LAYOUT>(tid, e, &rl, &kl);
+    tile_pos<LAYOUT, V>(tid, e, &rl, &kl);
     x[e] = (r0 + rl < R && k0 + kl < K) ? double(v[e]) : 0.0;
   }
 }
 
 // Gather a PR x PK tile into LDS (zeros outside the operand).
-template <typename Tin, int LAYOUT>
+template <typename Tin, int LAYOUT, int V>
 __device__ __forceinline__ void gather_tile(double (*t)[PK + 1], const Tin *__restrict__ base, const int64_t *ro,
                                             const int64_t *__restrict__ offK, int64_t r0, int64_t k0, int64_t R,
                                             int64_t K) {
   double x[PI];
-  load_tile<Tin, LAYOUT>(x, base, ro, offK, r0, k0, R, K);
+  load_tile<Tin, LAYOUT, V>(x, base, ro, offK, r0, k0, R, K);
 #pragma unroll
   for (int e = 0; e < PI; ++e) {
     int rl, kl;
-    tile_pos<LAYOUT>(threadIdx.x, e, &rl, &kl);
+    tile_pos<LAYOUT, V>(threadIdx.x, e, &rl, &kl);
     t[rl][kl] = x[e];
   }
 }
 
 // Row offsets of a thread's elements (fixed for every tile of the same rows).
-template <int LAYOUT>
+// A vector along rows (LAYOUT 1, V > 1) takes its first row's offset, clamped
+// to the last whole vector.
+template <int LAYOUT, int V>
 __device__ __forceinline__ void row_offsets(int64_t *ro, const int64_t *__restrict__ offR, int64_t r0, int64_t R) {
+  const int64_t rlast = (LAYOUT == 1 && V > 1) ? R - V : R - 1;
 #pragma unroll
   for (int e = 0; e < PI; ++e) {
     int rl, kl;
-    tile_pos<LAYOUT>(threadIdx.x, e, &rl, &kl);
-    ro[e] = offR[r0 + rl < R ? r0 + rl : R - 1];
+    tile_pos<LAYOUT, V>(threadIdx.x, e, &rl, &kl);
+    ro[e] = offR[r0 + rl <= rlast ? r0 + rl : rlast];
   }
 }
 
@@ -157,6 +182,7 @@ struct SliceOperand {
   const int64_t *offR, *offK;
   int64_t R;
   int layout;
+  int vec;             // vector loads along the unit-stride dimension
   int tilesR;
   int *part;
   int *e;
@@ -175,7 +201,7 @@ struct SliceArgs {
 // operand 1, and summation range y; the maxima stay in registers over the
 // range, then in LDS, and one plain store per row and range leaves the block
 // (no initialisation and no global atomics).
-template <typename Tin, int LAYOUT>
+template <typename Tin, int LAYOUT, int V>
 __device__ __forceinline__ void exp_block(const SliceOperand &op, int rt, int64_t K, int ky, int *emax) {
   const int tid = threadIdx.x;
   if (tid < PR) emax[tid] = kExpNone;
@@ -184,27 +210,29 @@ __device__ __forceinline__ void exp_block(const SliceOperand &op, int rt, int64_
   const int64_t tilesK = (K + PK - 1) / PK;
   const int64_t kt0 = tilesK * blockIdx.y / ky, kt1 = tilesK * (blockIdx.y + 1) / ky;
   int64_t ro[PI];
-  row_offsets<LAYOUT>(ro, op.offR, r0, R);
-  // LAYOUT 0: a thread's elements lie in PI rows; LAYOUT 1: in one row
-  constexpr int NR = LAYOUT == 0 ? PI : 1;
+  row_offsets<LAYOUT, V>(ro, op.offR, r0, R);
+  // the rows of a thread's elements: LAYOUT 0, one per element; LAYOUT 1, V
+  // (element e lies in row number e mod V of them)
+  constexpr int NR = LAYOUT == 0 ? PI : V;
   int mx[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) mx[q] = kExpNone;
   for (int64_t kt = kt0; kt < kt1; ++kt) {
     double x[PI];
-    load_tile<Tin, LAYOUT>(x, base, ro, op.offK, r0, kt * PK, R, K);
+    load_tile<Tin, LAYOUT, V>(x, base, ro, op.offK, r0, kt * PK, R, K);
 #pragma unroll
-    for (int q = 0; q < PI; ++q) {
+    for (int e = 0; e < PI; ++e) {
+      const int q = LAYOUT == 0 ? e : e % V;
       int ex = kExpNone;
-      if (x[q] != 0.0) (void)frexp(x[q], &ex);
-      mx[LAYOUT == 0 ? q : 0] = ex > mx[LAYOUT == 0 ? q : 0] ? ex : mx[LAYOUT == 0 ? q : 0];
+      if (x[e] != 0.0) (void)frexp(x[e], &ex);
+      mx[q] = ex > mx[q] ? ex : mx[q];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
     int rl, kl;
-    tile_pos<LAYOUT>(tid, q, &rl, &kl);
+    tile_pos<LAYOUT, V>(tid, q, &rl, &kl);
     if (mx[q] != kExpNone) atomicMax(&emax[rl], mx[q]);
   }
   __syncthreads();
@@ -213,13 +241,15 @@ __device__ __forceinline__ void exp_block(const SliceOperand &op, int rt, int64_
 
 template <typename Tin>
 __global__ __launch_bounds__(PT) void split_exp_kernel(SliceArgs a) {
+  constexpr int VEC = 16 / int(sizeof(Tin));
   __shared__ int emax[PR];
   const int w = int(blockIdx.x) < a.op[0].tilesR ? 0 : 1;
   const int rt = int(blockIdx.x) - (w ? a.op[0].tilesR : 0);
-  if (a.op[w].layout == 0)
-    exp_block<Tin, 0>(a.op[w], rt, a.K, a.ky, emax);
+  const SliceOperand &op = a.op[w];
+  if (op.layout == 0)
+    op.vec ? exp_block<Tin, 0, VEC>(op, rt, a.K, a.ky, emax) : exp_block<Tin, 0, 1>(op, rt, a.K, a.ky, emax);
   else
-    exp_block<Tin, 1>(a.op[w], rt, a.K, a.ky, emax);
+    op.vec ? exp_block<Tin, 1, VEC>(op, rt, a.K, a.ky, emax) : exp_block<Tin, 1, 1>(op, rt, a.K, a.ky, emax);
 }
 
 // Cut a PR x PK tile into S slices, written K-contiguous: out[p][r][k]
@@ -228,28 +258,38 @@ __global__ __launch_bounds__(PT) void split_exp_kernel(SliceArgs a) {
 // The block first reduces its rows' partial exponents; blocks of the first
 // summation tile also store them as the rows' final exponents, which the
 // product's epilogue reads.
-template <typename Tin, typename ST, int LAYOUT, int MODE, int S>
+template <typename Tin, typename ST, int LAYOUT, int V, int MODE, int S>
 __device__ __forceinline__ void pack_block(const SliceOperand &op, int64_t bid, int64_t K, int64_t Kp, int ky,
-                                           double (*t)[PK + 1], int *erow) {
+                                           double (*t)[PK + 1], int *erow, int *red) {
   const Tin *__restrict__ base = static_cast<const Tin *>(op.base);
   ST *__restrict__ out = static_cast<ST *>(op.out);
   const int64_t R = op.R, Rp = op.Rp;
   const int64_t r0 = (bid % op.tilesR) * PR, k0 = (bid / op.tilesR) * PK;
   const int tid = threadIdx.x;
-  if (tid < PR) {
+  {
+    // the rows' partial exponents, ky per row, reduced by all threads: a
+    // quarter of the ranges each, then the four quarters below
+    const int rr = tid % PR, y0 = tid / PR;
     int ex = kExpNone;
-    if (r0 + tid < R)
-      for (int y = 0; y < ky; ++y) {
-        const int v = op.part[int64_t(y) * Rp + r0 + tid];
+    if (r0 + rr < R)
+      for (int y = y0; y < ky; y += PT / PR) {
+        const int v = op.part[int64_t(y) * Rp + r0 + rr];
         ex = v > ex ? v : ex;
       }
-    erow[tid] = ex;
-    if (k0 == 0 && r0 + tid < R) op.e[r0 + tid] = ex;
+    red[tid] = ex;
   }
   {
     int64_t ro[PI];
-    row_offsets<LAYOUT>(ro, op.offR, r0, R);
-    gather_tile<Tin, LAYOUT>(t, base, ro, op.offK, r0, k0, R, K);
+    row_offsets<LAYOUT, V>(ro, op.offR, r0, R);
+    gather_tile<Tin, LAYOUT, V>(t, base, ro, op.offK, r0, k0, R, K);
+  }
+  __syncthreads();
+  if (tid < PR) {
+    int ex = red[tid];
+#pragma unroll
+    for (int q = 1; q < PT / PR; ++q) ex = red[tid + q * PR] > ex ? red[tid + q * PR] : ex;
+    erow[tid] = ex;
+    if (k0 == 0 && r0 + tid < R) op.e[r0 + tid] = ex;
   }
   __syncthreads();
   const int rl = tid / 4;
@@ -299,15 +339,25 @@ __device__ __forceinline__ void pack_block(const SliceOperand &op, int64_t bid, 
 
 template <typename Tin, typename ST, int MODE, int S>
 __global__ __launch_bounds__(PT) void split_pack_kernel(SliceArgs a) {
+  constexpr int VEC = 16 / int(sizeof(Tin));
   __shared__ double t[PR][PK + 1];
   __shared__ int erow[PR];
+  __shared__ int red[PT];
   const int64_t nA = int64_t(a.op[0].tilesR) * (a.Kp / PK);
   const int w = int64_t(blockIdx.x) < nA ? 0 : 1;
   const int64_t bid = int64_t(blockIdx.x) - (w ? nA : 0);
-  if (a.op[w].layout == 0)
-    pack_block<Tin, ST, 0, MODE, S>(a.op[w], bid, a.K, a.Kp, a.ky, t, erow);
-  else
-    pack_block<Tin, ST, 1, MODE, S>(a.op[w], bid, a.K, a.Kp, a.ky, t, erow);
+  const SliceOperand &op = a.op[w];
+  if (op.layout == 0) {
+    if (op.vec)
+      pack_block<Tin, ST, 0, VEC, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+    else
+      pack_block<Tin, ST, 0, 1, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+  } else {
+    if (op.vec)
+      pack_block<Tin, ST, 1, VEC, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+    else
+      pack_block<Tin, ST, 1, 1, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+  }
 }
 
 // ------------------------------------------------------- slice-pair GEMM --
@@ -845,7 +895,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 template <typename Tin, typename ST, int MODE, int S>
 hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
-                     const void *B, double beta, void *C, void *ws, hipStream_t s) {
+                     const void *B, double beta, void *C, void *ws, hipStream_t s, bool vecA, bool vecB) {
   char *w = static_cast<char *>(ws);
   ST *As = reinterpret_cast<ST *>(w + sp.offA);
   ST *Bs = reinterpret_cast<ST *>(w + sp.offB);
@@ -853,10 +903,10 @@ hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &
   int *eB = reinterpret_cast<int *>(w + sp.offEB);
   // both operands in one exponent launch and one pack launch
   SliceArgs a{};
-  a.op[0] = SliceOperand{A, t.offAm, t.offAk, an.m, an.layoutA, int(sp.Mp / PR), reinterpret_cast<int *>(w + sp.offPA),
-                         eA, As, sp.Mp};
-  a.op[1] = SliceOperand{B, t.offBn, t.offBk, an.n, an.layoutB, int(sp.Np / PR), reinterpret_cast<int *>(w + sp.offPB),
-                         eB, Bs, sp.Np};
+  a.op[0] = SliceOperand{A, t.offAm, t.offAk, an.m, an.layoutA, vecA ? 1 : 0, int(sp.Mp / PR),
+                         reinterpret_cast<int *>(w + sp.offPA), eA, As, sp.Mp};
+  a.op[1] = SliceOperand{B, t.offBn, t.offBk, an.n, an.layoutB, vecB ? 1 : 0, int(sp.Np / PR),
+                         reinterpret_cast<int *>(w + sp.offPB), eB, Bs, sp.Np};
   a.K = an.k;
   a.Kp = sp.Kp;
   a.ky = sp.ky;
@@ -894,25 +944,25 @@ hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &
 
 template <typename Tin>
 hipError_t dispatch(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
-                    const void *B, double beta, void *C, void *ws, hipStream_t s) {
-  if (sp.mode == 1) return run_split<Tin, __bf16, 1, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
-  if (sp.mode == 2) return run_split<Tin, _Float16, 2, 2>(an, sp, t, alpha, A, B, beta, C, ws, s);
+                    const void *B, double beta, void *C, void *ws, hipStream_t s, bool vecA, bool vecB) {
+  if (sp.mode == 1) return run_split<Tin, __bf16, 1, 3>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+  if (sp.mode == 2) return run_split<Tin, _Float16, 2, 2>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
   if (sp.mode == 3) {
     switch (sp.S) {
-      case 3: return run_split<Tin, signed char, 3, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
-      case 4: return run_split<Tin, signed char, 3, 4>(an, sp, t, alpha, A, B, beta, C, ws, s);
-      case 5: return run_split<Tin, signed char, 3, 5>(an, sp, t, alpha, A, B, beta, C, ws, s);
-      case 6: return run_split<Tin, signed char, 3, 6>(an, sp, t, alpha, A, B, beta, C, ws, s);
-      case 7: return run_split<Tin, signed char, 3, 7>(an, sp, t, alpha, A, B, beta, C, ws, s);
-      case 8: return run_split<Tin, signed char, 3, 8>(an, sp, t, alpha, A, B, beta, C, ws, s);
+      case 3: return run_split<Tin, signed char, 3, 3>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+      case 4: return run_split<Tin, signed char, 3, 4>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+      case 5: return run_split<Tin, signed char, 3, 5>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+      case 6: return run_split<Tin, signed char, 3, 6>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+      case 7: return run_split<Tin, signed char, 3, 7>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+      case 8: return run_split<Tin, signed char, 3, 8>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
       default: return hipErrorInvalidValue;
     }
   }
   switch (sp.S) {
-    case 3: return run_split<Tin, __bf16, 0, 3>(an, sp, t, alpha, A, B, beta, C, ws, s);
-    case 4: return run_split<Tin, __bf16, 0, 4>(an, sp, t, alpha, A, B, beta, C, ws, s);
-    case 5: return run_split<Tin, __bf16, 0, 5>(an, sp, t, alpha, A, B, beta, C, ws, s);
-    case 6: return run_split<Tin, __bf16, 0, 6>(an, sp, t, alpha, A, B, beta, C, ws, s);
+    case 3: return run_split<Tin, __bf16, 0, 3>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+    case 4: return run_split<Tin, __bf16, 0, 4>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+    case 5: return run_split<Tin, __bf16, 0, 5>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+    case 6: return run_split<Tin, __bf16, 0, 6>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
     default: return hipErrorInvalidValue;
   }
 }
@@ -975,9 +1025,12 @@ Status split_prepare(const Analysis &an, SplitPlan &sp, int force_tile) {
 }
 
 hipError_t split_execute(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
-                         const void *B, double beta, void *C, void *ws, hipStream_t s) {
-  if (an.dtype == COMET_F64) return dispatch<double>(an, sp, t, alpha, A, B, beta, C, ws, s);
-  return dispatch<float>(an, sp, t, alpha, A, B, beta, C, ws, s);
+                         const void *B, double beta, void *C, void *ws, hipStream_t s, bool vecA, bool vecB) {
+  // the slicers read vectors only from 16-byte aligned operands
+  vecA = vecA && reinterpret_cast<uintptr_t>(A) % 16 == 0;
+  vecB = vecB && reinterpret_cast<uintptr_t>(B) % 16 == 0;
+  if (an.dtype == COMET_F64) return dispatch<double>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
+  return dispatch<float>(an, sp, t, alpha, A, B, beta, C, ws, s, vecA, vecB);
 }
 
 }  // namespace comet

@@ -23,7 +23,11 @@ struct SplitPlan {
 // force_tile >= 0 sets the slice-pair tile of modes 1 and 2 (the autotuner's
 // choice); otherwise a size rule, which COMET_SPLIT_TILE overrides.
 Status split_prepare(const Analysis &an, SplitPlan &sp, int force_tile = -1);
+// vecA / vecB: the offset tables allow vector loads of the operand along its
+// unit-stride dimension (the gather path's condition); the slicers use them
+// where the operand's pointer is also 16-byte aligned.
 hipError_t split_execute(const Analysis &an, const SplitPlan &sp, const GettTables &t, double alpha, const void *A,
-                         const void *B, double beta, void *C, void *ws, hipStream_t s);
+                         const void *B, double beta, void *C, void *ws, hipStream_t s, bool vecA = false,
+                         bool vecB = false);
 
 }  // namespace comet

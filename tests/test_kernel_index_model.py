@@ -207,3 +207,65 @@ def test_shortk_staging_without_the_prologue_row_copy_reads_unwritten_lds():
     ntile = 1
     jn = 0
     assert rows[jn & 1] is None
+
+
+# ---- the slicer's tile walk (split.hip: tile_pos, row_offsets, load_tile) ----
+# A 64 x 64 tile, 256 threads, 16 elements each; V consecutive elements along
+# the operand's unit-stride dimension form one vector load (V = 1: element
+# loads).  Mirror of the device mapping, checked for full coverage, vector
+# contiguity and in-range clamped addresses.
+
+SPR, SPK, SPT = 64, 64, 256
+SPI = SPR * SPK // SPT
+
+
+def slicer_pos(layout, V, tid, e):
+    if layout == 0:
+        return tid // (SPK // V) + (SPT // (SPK // V)) * (e // V), (tid % (SPK // V)) * V + e % V
+    return (tid % (SPR // V)) * V + e % V, tid // (SPR // V) + (SPT // (SPR // V)) * (e // V)
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("V", [1, 2, 4])
+def test_slicer_tile_walk_covers_the_tile_once(layout, V):
+    seen = {}
+    for tid in range(SPT):
+        for e in range(SPI):
+            seen.setdefault(slicer_pos(layout, V, tid, e), []).append((tid, e))
+    assert len(seen) == SPR * SPK and all(len(v) == 1 for v in seen.values())
+    # a vector's V elements: consecutive along the unit-stride dimension,
+    # starting at a multiple of V
+    for tid in range(SPT):
+        for e in range(0, SPI, V):
+            r0, k0 = slicer_pos(layout, V, tid, e)
+            for i in range(V):
+                r, k = slicer_pos(layout, V, tid, e + i)
+                if layout == 0:
+                    assert (r, k) == (r0, k0 + i) and k0 % V == 0
+                else:
+                    assert (r, k) == (r0 + i, k0) and r0 % V == 0
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("V,R,K", [(1, 70, 37), (2, 70, 38), (2, 64, 130), (4, 68, 36), (4, 132, 64)])
+def test_slicer_vector_loads_stay_inside_the_operand(layout, V, R, K):
+    """Every (clamped) vector start lies inside the operand with its whole
+    vector; elements masked out are exactly those outside it."""
+    for r0 in range(0, R + SPR - 1, SPR):
+        for k0 in range(0, K + SPK - 1, SPK):
+            for tid in range(SPT):
+                for e in range(0, SPI, V):
+                    rl, kl = slicer_pos(layout, V, tid, e)
+                    rlast = R - V if (layout == 1 and V > 1) else R - 1
+                    klast = K - V if (layout == 0 and V > 1) else K - 1
+                    r = min(r0 + rl, rlast)
+                    k = min(k0 + kl, klast)
+                    if layout == 0:
+                        assert 0 <= r < R and 0 <= k and k + V <= K
+                    else:
+                        assert 0 <= k < K and 0 <= r and r + V <= R
+                    # with the vectorized extent a multiple of V, a vector is
+                    # wholly inside the operand or wholly outside (masked)
+                    inside = [r0 + slicer_pos(layout, V, tid, e + i)[0] < R and
+                              k0 + slicer_pos(layout, V, tid, e + i)[1] < K for i in range(V)]
+                    assert all(inside) or not any(inside)

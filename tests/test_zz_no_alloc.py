@@ -87,3 +87,28 @@ def test_noalloc_refuses_plans_beyond_the_buffer():
     assert ei.value.code == 6 and "static buffer" in str(ei.value)
     torch.cuda.synchronize()
     assert bool((Cd == 3.0).all())
+
+
+def test_noalloc_balanced_schedule_full_size():
+    """The CCSD-like contraction at full size, whose plan cuts the tiles left
+    after the first full round into summation pieces (partial tiles in the
+    workspace): the static buffer gives the same bits as a plan workspace,
+    twice in a row, and sampled outputs match the oracle."""
+    V, O = 96, 32
+    A, B, C0 = _case(V, O, 7400)
+    ext = dict(a=V, b=V, c=V, i=O, j=O, k=O)
+    print_case("noalloc balanced", A.shape)
+    Ad, Bd, Cd = (torch_dev(x, torch.float64) for x in (A, B, C0))
+    plan = comet.Plan(SPEC, Ad, Bd, Cd, compute="f64")
+    assert 0 < plan.workspace_bytes <= LIMIT
+    for _ in range(2):
+        ref, got = _run_both(plan, Ad, Bd, Cd, 1.0, 0.5)
+        assert torch.equal(ref, got)
+    rng = np.random.default_rng(7401)
+    shp = shape_of("abij", ext)
+    pts = np.stack([rng.integers(0, e, 4000) for e in shp], axis=1)
+    pts = np.concatenate([pts, np.zeros((1, 4), np.int64), np.array([shp]) - 1])
+    idx = torch.from_numpy(pts).cuda()
+    g = got[tuple(idx.T)].cpu().numpy()
+    want = oracle.contract_points(SPEC, A, B, pts, C0, 1.0, 0.5)
+    assert oracle.relerr(g, want) <= 1e-12
