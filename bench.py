@@ -10,7 +10,7 @@ C ABI (plan cached) on the FP64 matrix cores, inputs resident in HBM.
 The same line also carries, each timed with HIP events on the launch stream:
   modes      the headline contraction in every compute mode, with its relative
              error against the CPU FP64 oracle on sampled outputs;
-  backward   forward + dA + dB of the same contraction (FP64 and aligned split);
+  backward   forward + dA + dB of the same contraction (FP64, aligned BF16 and INT8 splits, BF16x3);
   triples    the 6D-output contraction C[a,b,c,i,j,k] = sum_d A[d,a,i,j] B[b,c,d,k]
              (virtual 32, occupied 16), bound by writing C to HBM;
   config1    the all-16 contraction (latency-bound): per call through the
@@ -287,7 +287,7 @@ def bench_modes(comet, A, B, C0, steps, warmup, want):
 
 
 def bench_backward(comet, A, B, C0, reps):
-    """forward + dA + dB for loss = sum(C * W), FP64 and aligned split."""
+    """forward + dA + dB for loss = sum(C * W): FP64, the aligned BF16 and INT8 splits and BF16x3."""
     import torch
     import synth
     dev = torch.device("cuda:0")
@@ -303,7 +303,7 @@ def bench_backward(comet, A, B, C0, reps):
     C = torch.empty(shape("abij"), dtype=torch.float64, device=dev)
     dA = torch.empty_like(Ad)
     dB = torch.empty_like(Bd)
-    for mode in ("f64", "split_bf16", "split_int8"):
+    for mode in ("f64", "split_bf16", "split_int8", "split_bf16x3"):
         def step():
             comet.contract(SPEC, Ad, Bd, C, compute=mode)
             comet.contract(sa, Wd, Bd, dA, compute=mode)

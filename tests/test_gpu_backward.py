@@ -1,7 +1,8 @@
 """Backward of the contraction: dA and dB are themselves permuted contractions
 run by the same kernels, behind torch.autograd.Function.
 
-Checked against the oracle's gradient (FP64 <= 1e-12, aligned split <= 1e-9),
+Checked against the oracle's gradient (FP64 <= 1e-12, aligned BF16 and INT8
+splits <= 1e-9, BF16x3 <= 1e-5),
 against central finite differences of the GPU forward on a 12-extent copy of
 the CCSD-like workload (h = 1e-6; the loss is bilinear, so the difference
 quotient is exact up to rounding), and by the dot-product (adjoint) identity.
@@ -28,7 +29,8 @@ def ccsd_inputs(V, O, seed):
     return ext, A, B, C0, W
 
 
-@pytest.mark.parametrize("compute,tol", [("f64", 1e-12), ("split_bf16", 1e-9)])
+@pytest.mark.parametrize("compute,tol", [("f64", 1e-12), ("split_bf16", 1e-9), ("split_int8", 1e-9),
+                                         ("split_bf16x3", 1e-5)])
 @pytest.mark.parametrize("V,O", [(12, 12), (40, 12)])
 def test_backward_matches_oracle_gradient(compute, tol, V, O):
     ext, A, B, C0, W = ccsd_inputs(V, O, 900)
