@@ -385,6 +385,78 @@ constexpr int GNT = 64 * GWM * GWN;
 // then hit 64 distinct banks.
 __device__ __forceinline__ int sw(int r, int c) { return r * GBK + ((c ^ ((r >> 2) & 3)) << 3); }
 
+// One stage of the slice-pair products, moved from the packed slices into
+// LDS by direct-to-LDS loads (no registers, no LDS store instructions).  The
+// stage is S slices of BM rows of A, then S slices of BN rows of B, each row
+// 64 bytes (32 16-bit or 64 8-bit summation indices), its four 16-byte
+// chunks swizzled as sw() / sw8() place them.  It is cut into 1 KB blocks of
+// 16 rows; one load of 64 lanes x 16 bytes fills a block, lane L writing
+// bytes 16 L .. 16 L + 15 of it, i.e. row 16 g + L / 4 at chunk position
+// L mod 4, which holds the row's chunk (L mod 4) ^ ((row / 4) mod 4).  Wave w
+// of NW takes blocks w, w + NW, ...  A and B: the packed slices, rows of
+// row_bytes.  The addresses do not depend on the stage but for its first
+// byte along the summation, so they are worked out once (init) and a stage
+// is NU loads (issue).  The loads are counted by the wave's vector-memory
+// counter: wait for it to reach zero, then a barrier, before the stage is
+// read.
+template <int BM, int BN, int S, int NW>
+struct StageDMA {
+  static constexpr int BLK = 16;
+  static constexpr int NBA = S * BM / BLK, NBB = S * BN / BLK;
+  static constexpr int NU = (NBA + NBB + NW - 1) / NW;
+  const char *src[NU];   // this lane's 16 bytes of block w + u NW, at summation byte 0
+  int dst[NU];           // the block's byte offset in a stage buffer (uniform)
+  int nu;                // blocks of this wave (uniform)
+
+  __device__ __forceinline__ void init(const char *__restrict__ A, const char *__restrict__ B, int64_t Mp,
+                                       int64_t Np, int64_t row_bytes, int64_t m0, int64_t n0, int wave,
+                                       int lane) {
+    const int w = __builtin_amdgcn_readfirstlane(wave);   // (the compiler cannot tell it is uniform)
+    nu = 0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int blk = w + u * NW;
+      int p, g, base;
+      const char *rows;
+      int64_t rows_p;
+      if (blk < NBA) {   // constant divisors on either side
+        p = blk / (BM / BLK);
+        g = blk % (BM / BLK);
+        rows = A;
+        rows_p = int64_t(p) * Mp + m0;
+        base = p * BM * 64;
+      } else {
+        const int b2 = blk - NBA < NBB ? blk - NBA : NBB - 1;
+        p = b2 / (BN / BLK);
+        g = b2 % (BN / BLK);
+        rows = B;
+        rows_p = int64_t(p) * Np + n0;
+        base = S * BM * 64 + p * BN * 64;
+      }
+      const int row = g * BLK + (lane >> 2);
+      const int c = (lane & 3) ^ ((row >> 2) & 3);
+      src[u] = rows + (rows_p + row) * row_bytes + c * 16;
+      dst[u] = base + g * BLK * 64;
+      nu += blk < NBA + NBB ? 1 : 0;
+    }
+  }
+
+  __device__ __forceinline__ void issue(lds_t<char> *buf, int64_t kb0) const {
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if ((NBA + NBB) % NW == 0 || u < nu)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const glb_t<void> *>(to_glb(src[u] + kb0)),
+                                         reinterpret_cast<lds_t<void> *>(buf + dst[u]), 16, 0, 0);
+  }
+};
+
+// every direct-to-LDS load of this wave has landed (vector-memory counter at
+// zero, the other counters left alone); then the barrier
+__device__ __forceinline__ void stage_landed() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+}
+
 // Epilogue of the slice-pair products: C = alpha * 2^(eA[m] + eB[n]) * val +
 // beta * C for the thread's accumulator elements (row 4 * (lane / 16) + r of
 // each 16 x 16 block, the layout of the 16-bit and 8-bit MFMA outputs), val(i,
@@ -475,9 +547,13 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
   constexpr int NVB = S * GBN * (GBK / 8);
   constexpr int NV = (NVA + NVB + GNT - 1) / GNT;    // per thread
   constexpr int STAGE = S * (GBM + GBN) * GBK;       // elements per LDS buffer
-  // two buffers when they fit in LDS (S <= 6 with 64-byte rows), else one
+  // two buffers when they fit in LDS (S <= 6 with 64-byte rows), else one;
+  // two buffers are two objects, filled by direct-to-LDS loads, so that the
+  // compiler can tell the loads into one from the reads of the other
   constexpr int NBUF = 2 * STAGE * int(sizeof(ST)) <= 150 * 1024 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) ST smem[NBUF * STAGE];
+  __shared__ __attribute__((aligned(16))) ST smem[NBUF == 1 ? STAGE : 1];
+  __shared__ __attribute__((aligned(16))) ST smem0_[NBUF == 2 ? STAGE : 1];
+  __shared__ __attribute__((aligned(16))) ST smem1_[NBUF == 2 ? STAGE : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // XCD-aware tile order, as in the gather kernel
@@ -579,19 +655,40 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
     }
   };
 
-  gload(0);
-  lstore(smem);
-  __syncthreads();
-  for (int64_t st = 0; st < nst; ++st) {
-    ST *cur = smem + (NBUF == 2 ? int(st & 1) * STAGE : 0);
-    gload(st + 1);
-    compute(cur);
-    if (PP::FOLD > 0 && ((st + 1) % (PP::FOLD > 0 ? PP::FOLD : 1)) == 0) fold();
-    if constexpr (NBUF == 2) {
-      // the other buffer was last read before the previous barrier
-      lstore(smem + int((st + 1) & 1) * STAGE);
-      __syncthreads();
-    } else {
+  constexpr int FOLD = PP::FOLD > 0 ? PP::FOLD : 1;
+  if constexpr (NBUF == 2) {
+    // nst is even (Kp is a multiple of 64); each buffer was last read before
+    // the barrier that ended the previous half step, and its loads are kept
+    // ahead of the products (the scheduler would sink them, which have no
+    // users, to the wait)
+    StageDMA<GBM, GBN, S, GNT / 64> sd;
+    sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, Kp * int64_t(sizeof(ST)),
+            m0, n0, wave, lane);
+    auto dma = [&](ST *buf, int64_t st) {
+      sd.issue(reinterpret_cast<lds_t<char> *>(to_lds(buf)), (st < nst ? st : nst - 1) * GBK * int64_t(sizeof(ST)));
+    };
+    dma(smem0_, 0);
+    stage_landed();
+    for (int64_t st = 0; st < nst; st += 2) {
+      dma(smem1_, st + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(smem0_);
+      if (PP::FOLD > 0 && (st + 1) % FOLD == 0) fold();
+      stage_landed();
+      dma(smem0_, st + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(smem1_);
+      if (PP::FOLD > 0 && (st + 2) % FOLD == 0) fold();
+      stage_landed();
+    }
+  } else {
+    gload(0);
+    lstore(smem);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+      gload(st + 1);
+      compute(smem);
+      if (PP::FOLD > 0 && (st + 1) % FOLD == 0) fold();
       __syncthreads();
       lstore(smem);
       __syncthreads();
@@ -600,8 +697,9 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
   fold();
 
   // epilogue: C = alpha * 2^(eA + eB) * acc + beta * C
-  static_assert((GBM + GBN) * 12 <= NBUF * STAGE * int(sizeof(ST)), "epilogue tables fit in LDS");
-  split_store<Tout, GBM, GBN, FM, FN, GNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem,
+  static_assert((GBM + GBN) * 12 <= STAGE * int(sizeof(ST)), "epilogue tables fit in LDS");
+  split_store<Tout, GBM, GBN, FM, FN, GNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0,
+                                          NBUF == 2 ? static_cast<void *>(smem0_) : static_cast<void *>(smem),
                                           [&](int i, int j, int r) { return acc64[i][j][r]; });
 }
 
@@ -630,14 +728,15 @@ __global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restric
   typedef typename Vec8<ST>::type v8;
   constexpr int WM = XBM / XWM, WN = XBN / XWN;      // 96 x 48
   constexpr int FM = WM / 16, FN = WN / 16;          // 6 x 3
-  constexpr int NVA = S * XBM * (GBK / 8);           // 16-byte vectors per stage
-  constexpr int NVB = S * XBN * (GBK / 8);
-  constexpr int NV = (NVA + NVB) / XNT;              // per thread
-  static_assert(NV * XNT == NVA + NVB, "stage must split evenly over the workgroup");
   constexpr int STAGE = S * (XBM + XBN) * GBK;       // elements per LDS buffer
   static_assert(2 * STAGE * int(sizeof(ST)) <= 160 * 1024, "two stages must fit in LDS");
-  __shared__ __attribute__((aligned(16))) ST smem_[2 * STAGE];
-  lds_t<ST> *const smem = to_lds(smem_);
+  // two buffers as two objects, so that the compiler can tell the loads
+  // into one from the reads of the other and does not wait for the former
+  // before the latter
+  __shared__ __attribute__((aligned(16))) ST smem0_[STAGE];
+  __shared__ __attribute__((aligned(16))) ST smem1_[STAGE];
+  lds_t<ST> *const buf0 = to_lds(smem0_);
+  lds_t<ST> *const buf1 = to_lds(smem1_);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int tm, tn;
@@ -663,45 +762,18 @@ __global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restric
       for (int j = 0; j < FN; ++j) acc[a][i][j] = f4_t{0, 0, 0, 0};
 
   // a buffer holds A slices [S][XBM rows] then B slices [S][XBN rows]
-  auto a_at = [&](lds_t<ST> *buf, int p, int row, int c) { return buf + (p * XBM) * GBK + sw(row, c); };
-  auto b_at = [&](lds_t<ST> *buf, int p, int row, int c) {
+  auto a_at = [&](const lds_t<ST> *buf, int p, int row, int c) { return buf + (p * XBM) * GBK + sw(row, c); };
+  auto b_at = [&](const lds_t<ST> *buf, int p, int row, int c) {
     return buf + S * XBM * GBK + (p * XBN) * GBK + sw(row, c);
   };
-  const glb_t<const ST> *gA = to_glb(As);
-  const glb_t<const ST> *gB = to_glb(Bs);
-
-  v8 pre[NV];
-  const int64_t nst = Kp / GBK;
-  auto gload = [&](int64_t st) {
-    const int64_t k0 = (st < nst ? st : nst - 1) * GBK;
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      const int v = tid + u * XNT;
-      if (v < NVA) {
-        const int p = v / (XBM * 4), rem = v % (XBM * 4), row = rem / 4, kc = (rem % 4) * 8;
-        pre[u] = *reinterpret_cast<const glb_t<v8> *>(gA + (int64_t(p) * Mp + m0 + row) * Kp + k0 + kc);
-      } else {
-        const int w = v - NVA;
-        const int p = w / (XBN * 4), rem = w % (XBN * 4), row = rem / 4, kc = (rem % 4) * 8;
-        pre[u] = *reinterpret_cast<const glb_t<v8> *>(gB + (int64_t(p) * Np + n0 + row) * Kp + k0 + kc);
-      }
-    }
+  const int64_t nst = Kp / GBK;   // even: Kp is a multiple of 64
+  StageDMA<XBM, XBN, S, XNT / 64> sd;
+  sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, Kp * int64_t(sizeof(ST)), m0,
+          n0, wave, lane);
+  auto dma = [&](lds_t<ST> *buf, int64_t st) {
+    sd.issue(reinterpret_cast<lds_t<char> *>(buf), (st < nst ? st : nst - 1) * GBK * int64_t(sizeof(ST)));
   };
-  auto lstore = [&](lds_t<ST> *buf) {
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      const int v = tid + u * XNT;
-      if (v < NVA) {
-        const int p = v / (XBM * 4), rem = v % (XBM * 4), row = rem / 4, c = rem % 4;
-        *reinterpret_cast<lds_t<v8> *>(a_at(buf, p, row, c)) = pre[u];
-      } else {
-        const int w = v - NVA;
-        const int p = w / (XBN * 4), rem = w % (XBN * 4), row = rem / 4, c = rem % 4;
-        *reinterpret_cast<lds_t<v8> *>(b_at(buf, p, row, c)) = pre[u];
-      }
-    }
-  };
-  auto compute = [&](lds_t<ST> *buf) {
+  auto compute = [&](const lds_t<ST> *buf) {
     v8 bF[S][FN];
 #pragma unroll
     for (int q = 0; q < S; ++q)
@@ -726,22 +798,27 @@ __global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restric
       }
     }
   };
+  auto land = [&]() { stage_landed(); };
 
-  gload(0);
-  lstore(smem);
-  __syncthreads();
-  for (int64_t st = 0; st < nst; ++st) {
-    lds_t<ST> *cur = smem + int(st & 1) * STAGE;
-    gload(st + 1);
-    compute(cur);
-    // the other buffer was last read before the previous barrier
-    lstore(smem + int((st + 1) & 1) * STAGE);
-    __syncthreads();
+  dma(buf0, 0);
+  land();
+  for (int64_t st = 0; st < nst; st += 2) {
+    // each buffer was last read before the barrier that ended the previous
+    // half step; the loads are kept ahead of the products (the scheduler
+    // would otherwise sink them, which have no users, to the wait)
+    dma(buf1, st + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(buf0);
+    land();
+    dma(buf0, st + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(buf1);
+    land();
   }
 
   // epilogue: C = alpha * 2^(eA + eB) * sum_a scale(a) * acc[a] + beta * C
-  static_assert((XBM + XBN) * 12 <= 2 * STAGE * int(sizeof(ST)), "epilogue tables fit in LDS");
-  split_store<Tout, XBM, XBN, FM, FN, XNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem_,
+  static_assert((XBM + XBN) * 12 <= STAGE * int(sizeof(ST)), "epilogue tables fit in LDS");
+  split_store<Tout, XBM, XBN, FM, FN, XNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem0_,
                                           [&](int i, int j, int r) {
                                             double sum = 0.0;
 #pragma unroll
@@ -775,8 +852,10 @@ __global__ __launch_bounds__(GNT) void split_gemm_i8_kernel(const signed char *_
   constexpr int NVB = S * GBN * (IBK / 16);
   constexpr int NV = (NVA + NVB + GNT - 1) / GNT;
   constexpr int STAGE = S * (GBM + GBN) * IBK;       // bytes per LDS buffer
-  constexpr int NBUF = 2 * STAGE <= 150 * 1024 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) signed char smem[NBUF * STAGE];
+  constexpr int NBUF = 2 * STAGE <= 150 * 1024 ? 2 : 1;   // two buffers as two objects, as above
+  __shared__ __attribute__((aligned(16))) signed char smem[NBUF == 1 ? STAGE : 1];
+  __shared__ __attribute__((aligned(16))) signed char smem0_[NBUF == 2 ? STAGE : 1];
+  __shared__ __attribute__((aligned(16))) signed char smem1_[NBUF == 2 ? STAGE : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int tm, tn;
@@ -861,25 +940,45 @@ __global__ __launch_bounds__(GNT) void split_gemm_i8_kernel(const signed char *_
     }
   };
 
-  gload(0);
-  lstore(smem);
-  __syncthreads();
-  for (int64_t st = 0; st < nst; ++st) {
-    signed char *cur = smem + (NBUF == 2 ? int(st & 1) * STAGE : 0);
-    gload(st + 1);
-    compute(cur);
-    if constexpr (NBUF == 2) {
-      lstore(smem + int((st + 1) & 1) * STAGE);
-      __syncthreads();
-    } else {
+  if constexpr (NBUF == 2) {
+    StageDMA<GBM, GBN, S, GNT / 64> sd;
+    sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, Kp, m0, n0, wave, lane);
+    auto dma = [&](signed char *buf, int64_t st) {
+      sd.issue(reinterpret_cast<lds_t<char> *>(to_lds(buf)), k_begin + (st < nst ? st : nst - 1) * IBK);
+    };
+    dma(smem0_, 0);
+    stage_landed();
+    int64_t st = 0;
+    for (; st + 1 < nst; st += 2) {
+      dma(smem1_, st + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(smem0_);
+      stage_landed();
+      dma(smem0_, st + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(smem1_);
+      stage_landed();
+    }
+    if (st < nst) compute(smem0_);   // an odd last stage, loaded by the last half step
+  } else {
+    gload(0);
+    lstore(smem);
+    __syncthreads();
+    for (int64_t st = 0; st < nst; ++st) {
+      gload(st + 1);
+      compute(smem);
       __syncthreads();
       lstore(smem);
       __syncthreads();
     }
   }
 
-  static_assert((GBM + GBN) * 12 <= NBUF * STAGE, "epilogue tables fit in LDS");
-  split_store<Tout, GBM, GBN, FM, FN, GNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem,
+  static_assert((GBM + GBN) * 12 <= STAGE, "epilogue tables fit in LDS");
+  // (after an odd last stage, buffer 0 is still being read: wait for every
+  // wave before its first bytes take the epilogue tables)
+  if constexpr (NBUF == 2) __syncthreads();
+  split_store<Tout, GBM, GBN, FM, FN, GNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0,
+                                          NBUF == 2 ? static_cast<void *>(smem0_) : static_cast<void *>(smem),
                                           [&](int i, int j, int r) {
                                             double sum = 0.0;
 #pragma unroll
