@@ -61,7 +61,7 @@ HBM_PEAK_GBS = 8000.0
 # valid only for the schedule and kernel version recorded, null otherwise.
 HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512, "even": 1}, "kernel_version": "k9",
                     "bytes": 940968320}
-KERNEL_VERSION = "k9"
+KERNEL_VERSION = "k10"
 
 
 def headline_kernels(d):

@@ -189,9 +189,24 @@ struct Loader {
 
   // load the step starting at k0, addressed by the K-table entries fetched
   // for it; the raw values are kept and masked only when stored to LDS, so
-  // no instruction between here and the store waits for the loads
+  // no instruction between here and the store waits for the loads.  FULL:
+  // the tile lies inside the operand and the summation is a whole number of
+  // steps, so nothing is masked (a step past the end, loaded but never
+  // multiplied, reads the clamped last step).
+  template <bool FULL = false>
   __device__ __forceinline__ void load(const Tin *__restrict__ base_, int64_t k0, int64_t K) {
     const glb_t<const Tin> *base = to_glb(base_);
+    if constexpr (FULL && VECLD) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const typename V16<Tin>::type x =
+            *reinterpret_cast<const glb_t<typename V16<Tin>::type> *>(base + roff[p][0] + kofs[p][0]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) v[p][i] = x[i];
+      }
+      vmask = ~0u;
+      return;
+    }
     uint32_t vm = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -330,7 +345,8 @@ __device__ __forceinline__ void gett_mma_step(WT &w, const lds_t<typename WT::el
 // the offset tables into double-buffered LDS tiles and multiply on the
 // 16 x 16 x 4 MFMA.  All threads of the workgroup must call it (it
 // synchronizes); smem holds gett_lds_elems values.
-template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, int LA, int LB, bool VA, bool VB>
+template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, int LA, int LB, bool VA, bool VB,
+          bool FULL = false>
 __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &w, const Tin *__restrict__ A,
                                                 const Tin *__restrict__ B, const GettTables &t, int64_t M,
                                                 int64_t N, int64_t K, int64_t m0, int64_t n0, int64_t s_begin,
@@ -364,8 +380,8 @@ __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &
   const int64_t k_begin = s_begin * BK;
   la.fetch_k(t.offAk, k_begin, K);
   lb.fetch_k(t.offBk, k_begin, K);
-  la.load(A, k_begin, K);
-  lb.load(B, k_begin, K);
+  la.template load<FULL>(A, k_begin, K);
+  lb.template load<FULL>(B, k_begin, K);
   la.fetch_k(t.offAk, k_begin + BK, K);
   lb.fetch_k(t.offBk, k_begin + BK, K);
   la.store(sA[0]);
@@ -373,8 +389,8 @@ __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &
   __syncthreads();
   for (int64_t step = s_begin; step < s_end; ++step) {
     const int cur = int((step - s_begin) & 1);
-    la.load(A, (step + 1) * BK, K);
-    lb.load(B, (step + 1) * BK, K);
+    la.template load<FULL>(A, (step + 1) * BK, K);
+    lb.template load<FULL>(B, (step + 1) * BK, K);
     la.fetch_k(t.offAk, (step + 2) * BK, K);
     lb.fetch_k(t.offBk, (step + 2) * BK, K);
     gett_mma_step<LoadA, LoadB, BK>(w, sA[cur], sB[cur], lane, wm0, wn0);
@@ -579,15 +595,16 @@ __device__ __forceinline__ void gett_store_partial(const WaveTile<Tc, BM, BN, WG
 }
 
 // One BM x BN output tile at (m0, n0) over the whole summation range.
-template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, int LA, int LB, bool VA, bool VB>
+template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, int LA, int LB, bool VA, bool VB,
+          bool FULL = false>
 __device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C,
                                           const GettTables &t, int64_t M, int64_t N, int64_t K, double alpha,
                                           double beta, int64_t m0, int64_t n0, Tc *smem) {
   static_assert(8 * (BM + BN) <= int(sizeof(Tc)) * gett_lds_elems<Tin, Tc, BM, BN, BK, 64 * WGM * WGN, LA, LB, VA, VB>(),
                 "the tile's C offsets fit in its LDS");
   WaveTile<Tc, BM, BN, WGM, WGN> w;
-  gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(w, A, B, t, M, N, K, m0, n0, 0,
-                                                                 (K + BK - 1) / BK, smem);
+  gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB, FULL>(w, A, B, t, M, N, K, m0, n0, 0,
+                                                                       (K + BK - 1) / BK, smem);
   gett_store<Tin, Tc, BM, BN, WGM, WGN>(w, C, t, M, N, alpha, beta, m0, n0, smem);
 }
 

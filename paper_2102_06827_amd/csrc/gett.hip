@@ -73,7 +73,9 @@ __device__ __forceinline__ int sk_owner(int64_t I, int S, int64_t x) {
 
 // Whole tiles: workgroup b computes tile id b of the first gridDim.x ids in
 // the XCD-aware order (all tiles, or all but the sk.tiles stream-K ones).
-template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+// FULL: every tile lies inside the output and the summation is a whole
+// number of K steps, so the loads are not masked.
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB, bool FULL = false>
 __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_kernel(
     const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
     int64_t K, double alpha, double beta, int tilesM, int tilesN) {
@@ -83,8 +85,8 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
   __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
   int tm, tn;
   group_coords(xcd_remap(blockIdx.x, gridDim.x), tilesM, tilesN, &tm, &tn);
-  gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(A, B, C, t, M, N, K, alpha, beta, int64_t(tm) * BM,
-                                                           int64_t(tn) * BN, smem);
+  gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB, FULL>(A, B, C, t, M, N, K, alpha, beta,
+                                                                 int64_t(tm) * BM, int64_t(tn) * BN, smem);
 }
 
 // Batch labels: blockIdx.y selects batch entry bt.first + blockIdx.y, whose
@@ -112,6 +114,8 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
 constexpr bool batch_tile(int tile) { return tile == 1 || tile == 3; }
 // the tile variants compiled for the short-summation kernel
 constexpr bool shortk_tile(int tile) { return tile == 3; }
+// the tile variants compiled with unmasked loads for whole tiles
+constexpr bool full_tile(int tile) { return tile == 3; }
 
 // Stream-K: the last sk.tiles tiles (ids dp .. dp + sk.tiles - 1) split
 // along the summation over sk.blocks workgroups, each taking an equal number
@@ -334,7 +338,7 @@ __device__ __forceinline__ int64_t scalar64(int64_t x) {
   return int64_t((uint64_t(hi) << 32) | lo);
 }
 
-template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB>
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB, bool FULL = false>
 __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_piece_kernel(
     const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
     int64_t K, double alpha, double beta, int tilesM, int tilesN, StreamK sk) {
@@ -359,8 +363,8 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
   int tm, tn;
   group_coords(sk.whole + r, tilesM, tilesN, &tm, &tn);
   WT w;
-  gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB>(w, A, B, tk, M, N, Kp, int64_t(tm) * BM,
-                                                                 int64_t(tn) * BN, 0, (Kp + BK - 1) / BK, smem);
+  gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB, FULL>(w, A, B, tk, M, N, Kp, int64_t(tm) * BM,
+                                                                       int64_t(tn) * BN, 0, (Kp + BK - 1) / BK, smem);
   constexpr int64_t kSlot = int64_t(WT::FM) * WT::FN * NT;   // 4-vectors per slot
   gett_store_partial<Tc, BM, BN, WGM, WGN>(w, static_cast<typename WT::acc_t *>(sk.ws) + b * kSlot);
 }
@@ -647,6 +651,8 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
                                                           NT, 0);
     }
     const int tilesM = int((g.M + BM - 1) / BM), tilesN = int((g.N + BN - 1) / BN);
+    // every tile inside the output and whole K steps: the unmasked loads
+    const bool full = full_tile(TILE) && VA && VB && g.M % BM == 0 && g.N % BN == 0 && g.K % kTiles[TILE].bk == 0;
     const Tin *A = static_cast<const Tin *>(g.A), *B = static_cast<const Tin *>(g.B);
     Tin *C = static_cast<Tin *>(g.C);
     if (g.bt.offA) {
@@ -704,13 +710,21 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
           int64_t(ev.whole) + ev.tiles != int64_t(tilesM) * tilesN)
         return hipErrorInvalidValue;
       if (ev.whole > 0) {
-        hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.whole), dim3(NT), 0, s, A, B, C, g.t,
-                           g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+        if (full)
+          hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB, full_tile(TILE)>), dim3(ev.whole), dim3(NT), 0,
+                             s, A, B, C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+        else
+          hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.whole), dim3(NT), 0, s, A, B, C,
+                             g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
-      hipLaunchKernelGGL((gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.blocks), dim3(NT), 0, s, A, B, C,
-                         g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, ev);
+      if (full)
+        hipLaunchKernelGGL((gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB, full_tile(TILE)>), dim3(ev.blocks),
+                           dim3(NT), 0, s, A, B, C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, ev);
+      else
+        hipLaunchKernelGGL((gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.blocks), dim3(NT), 0, s, A, B,
+                           C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, ev);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       constexpr int FRAGS = (BM / kTiles[TILE].wgm / 16) * (BN / kTiles[TILE].wgn / 16);
@@ -721,7 +735,12 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
     StreamK sk = g.sk;
     if (sk.blocks <= 0 || sk.tiles <= 0 || sk.tiles > tilesM * tilesN || !sk.ws) sk = StreamK{};
     const int dp = tilesM * tilesN - sk.tiles;
-    if (dp > 0) {
+    if (dp > 0 && full) {
+      hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB, full_tile(TILE)>), dim3(dp), dim3(NT), 0, s, A, B,
+                         C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    } else if (dp > 0) {
       hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(dp), dim3(NT), 0, s, A, B, C, g.t, g.M,
                          g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
       hipError_t e = hipGetLastError();

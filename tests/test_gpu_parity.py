@@ -431,6 +431,40 @@ def test_tile_variants(tile, dtype, spec, ext, monkeypatch):
     check(spec, ext, dtype, seed=720 + tile, alpha=-0.5, beta=0.25)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("spec,ext", [
+    ("abij=acik*bkcj", dict(a=16, b=24, c=8, i=16, j=16, k=6)),      # A k-contiguous, B n-contiguous
+    ("ajbi=kcia*cjkb", dict(a=16, b=16, c=4, i=16, j=24, k=8)),       # A m-contiguous (after the swap)
+    ("abij=ijcd*cdab", dict(a=16, b=8, c=4, d=12, i=8, j=32)),        # B k-contiguous
+    ("abij=acik*cbkj", dict(a=16, b=16, c=8, i=8, j=8, k=4)),         # both m/n-contiguous
+])
+def test_whole_tiles_unmasked_loads(dtype, spec, ext, monkeypatch):
+    """Outputs that are whole 128 x 128 tiles with a summation of whole
+    16-index steps take tile 3's unmasked loads (the planner's default for
+    such shapes, and forced here): bit-exact on integer inputs, within the
+    bar on uniform ones, with the balanced schedule's pieces as well."""
+    monkeypatch.setenv("COMET_GETT_TILE", "3")
+    check(spec, ext, dtype, seed=1100, kind="integer", alpha=1.0, beta=1.0)
+    check(spec, ext, dtype, seed=1110, alpha=-0.5, beta=0.25)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_whole_tiles_unmasked_loads_in_pieces(dtype, monkeypatch):
+    """Six whole tiles over a long summation (K = 5504 = 344 steps), cut into
+    the balanced schedule's pieces: the pieces' unmasked loads run over k
+    tables moved to each piece's first index."""
+    monkeypatch.setenv("COMET_GETT_TILE", "3")
+    monkeypatch.setenv("COMET_GETT_EVEN", "1")
+    spec, ext = "abij=acik*bkcj", dict(a=16, b=24, c=86, i=16, j=16, k=64)
+    A = torch.zeros(shape_of("acik", ext), dtype=torch.float64, device="cuda")
+    B = torch.zeros(shape_of("bkcj", ext), dtype=torch.float64, device="cuda")
+    d = comet.Plan(spec, A, B, path="gett").describe()
+    if dtype == "f64":
+        assert d["even"] == 1 and d["sk_tiles"] == 6, d
+    check(spec, ext, dtype, seed=1120, kind="integer", alpha=2.0, beta=1.0, path="gett")
+    check(spec, ext, dtype, seed=1130, alpha=0.5, beta=0.0, path="gett")
+
+
 SK_CASES = [
     # (tile, "tiles,blocks") on a 480 x 480 x 480 contraction with ragged edges:
     # shares inside one tile, shares over tile boundaries, more blocks than
