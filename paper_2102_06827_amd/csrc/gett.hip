@@ -114,7 +114,9 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
 constexpr bool batch_tile(int tile) { return tile == 1 || tile == 3; }
 // the tile variants compiled for the short-summation kernel
 constexpr bool shortk_tile(int tile) { return tile == 3; }
-// the tile variants compiled with unmasked loads for whole tiles
+// the tile variants compiled with unmasked loads for whole tiles (the
+// planner's choice for large FP64 products; the FP32 ones, split over
+// stream-K pieces, measured no faster unmasked)
 constexpr bool full_tile(int tile) { return tile == 3; }
 
 // Stream-K: the last sk.tiles tiles (ids dp .. dp + sk.tiles - 1) split

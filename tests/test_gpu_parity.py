@@ -438,14 +438,18 @@ def test_tile_variants(tile, dtype, spec, ext, monkeypatch):
     ("abij=ijcd*cdab", dict(a=16, b=8, c=4, d=12, i=8, j=32)),        # B k-contiguous
     ("abij=acik*cbkj", dict(a=16, b=16, c=8, i=8, j=8, k=4)),         # both m/n-contiguous
 ])
-def test_whole_tiles_unmasked_loads(dtype, spec, ext, monkeypatch):
-    """Outputs that are whole 128 x 128 tiles with a summation of whole
-    16-index steps take tile 3's unmasked loads (the planner's default for
-    such shapes, and forced here): bit-exact on integer inputs, within the
-    bar on uniform ones, with the balanced schedule's pieces as well."""
-    monkeypatch.setenv("COMET_GETT_TILE", "3")
+@pytest.mark.parametrize("tile", [3, 4])
+def test_whole_tiles_unmasked_loads(tile, dtype, spec, ext, monkeypatch):
+    """Outputs that are whole tiles with a summation of whole 16-index
+    steps: tile 3 (128 x 128) takes the unmasked loads for its whole tiles,
+    tile 4 (256 x 128) the masked ones on the same shapes; whole and in a
+    forced stream-K split (which keeps masked loads): bit-exact on integer
+    inputs, within the bar on uniform ones."""
+    monkeypatch.setenv("COMET_GETT_TILE", str(tile))
     check(spec, ext, dtype, seed=1100, kind="integer", alpha=1.0, beta=1.0)
     check(spec, ext, dtype, seed=1110, alpha=-0.5, beta=0.25)
+    monkeypatch.setenv("COMET_GETT_SK", "2,5")
+    check(spec, ext, dtype, seed=1140, kind="integer", alpha=1.5, beta=-1.0, path="gett")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
