@@ -431,7 +431,7 @@ constexpr int shortk_lds_elems() {
 
 // BETA0: beta == 0, so the epilogue has one path whose store count the
 // compiler knows; with beta != 0 its C loads follow earlier stores anyway.
-template <typename Tin, typename Tc, int TILE, int LA, int LB, bool BETA0>
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool BETA0, bool FULL = false>
 __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, 1) void gett_shortk_kernel(
     const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
     int64_t K, double alpha, double beta, int tilesM, int tilesN) {
@@ -505,8 +505,8 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, 1) void g
   }
   la.fetch_k(t.offAk, 0, K);
   lb.fetch_k(t.offBk, 0, K);
-  la.load(A, 0, K);
-  lb.load(B, 0, K);
+  la.template load<FULL>(A, 0, K);
+  lb.template load<FULL>(B, 0, K);
   // tile 0's rows into rows[0]: the last iteration reloads its own tile from
   // rows[j & 1], which for a workgroup with one tile no other step writes
   SHORTK_FETCH_TABLES(0, 0);
@@ -529,8 +529,8 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, 1) void g
       const lds_t<int64_t> *r1 = rows + (jn & 1) * (BM + BN);
       la.init_from(tid, m1, M, r1, m1);
       lb.init_from(tid, n1, N, r1 + BM, n1);
-      la.load(A, 0, K);
-      lb.load(B, 0, K);
+      la.template load<FULL>(A, 0, K);
+      lb.template load<FULL>(B, 0, K);
       SHORTK_FETCH_TABLES(j + 2, j + 1);
     }
     // 3: the products over the whole summation
@@ -685,7 +685,11 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
       } else {
         if (g.K > kShortK) return hipErrorInvalidValue;
         const dim3 grid(std::min(g.shortk, tilesM * tilesN));
-        if (g.beta == 0.0)
+        // whole tiles over the whole short summation: unmasked loads
+        if (g.beta == 0.0 && g.M % BM == 0 && g.N % BN == 0 && g.K == kShortK)
+          hipLaunchKernelGGL((gett_shortk_kernel<Tin, Tc, TILE, LA, LB, true, true>), grid, dim3(NT), 0, s, A, B, C,
+                             g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
+        else if (g.beta == 0.0)
           hipLaunchKernelGGL((gett_shortk_kernel<Tin, Tc, TILE, LA, LB, true>), grid, dim3(NT), 0, s, A, B, C, g.t,
                              g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
         else

@@ -18,6 +18,7 @@ comet = pytest.importorskip("paper_2102_06827_amd")
 @pytest.mark.parametrize("spec,ext", [
     ("abcijk=daij*bcdk", dict(a=9, b=7, c=5, d=32, i=6, j=10, k=12)),   # the triples pattern, ragged
     ("abcijk=daij*bcdk", dict(a=4, b=3, c=2, d=17, i=16, j=8, k=16)),   # K = 17
+    ("abcijk=daij*bcdk", dict(a=8, b=4, c=8, d=32, i=4, j=8, k=8)),     # whole tiles, K = 32: unmasked loads
     ("mn=km*kn", dict(m=300, n=520, k=4)),                              # both operands M/N-contiguous
     ("mn=mk*nk", dict(m=260, n=390, k=32)),                             # both K-contiguous
     ("mn=mk*kn", dict(m=1000, n=999, k=8)),
