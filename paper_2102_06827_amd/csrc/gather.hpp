@@ -274,6 +274,26 @@ struct Loader {
     }
   }
 
+  // Direct-to-LDS load of the step whose K-table entries were fetched last
+  // (unmasked: whole tiles only), for a row-contiguous operand (LAYOUT 1)
+  // whose tile rows span one wave: pass p of wave w is summation index kk[p]
+  // (the same in every lane), lane L the elements 2 L, 2 L + 1 -- exactly
+  // the 16 bytes at L x 16 from the start of that index's row in the LDS
+  // tile.  No registers hold the data; the loads are counted by the
+  // vector-memory counter.
+  static constexpr bool dma_ok = LAYOUT == 1 && VECLD && VEC * sizeof(Tin) == 16 && R / VEC == 64 &&
+                                 sizeof(Tin) == sizeof(Tc);
+  __device__ __forceinline__ void dma(const Tin *__restrict__ base_, lds_t<Tc> *s) const {
+    static_assert(dma_ok, "direct-to-LDS loads need one wave per tile row");
+    const glb_t<const Tin> *base = to_glb(base_);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int kr = __builtin_amdgcn_readfirstlane(kk[p]);
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const glb_t<void> *>(base + roff[p][0] + kofs[p][0]),
+                                       reinterpret_cast<lds_t<void> *>(s + idx(0, kr)), 16, 0, 0);
+    }
+  }
+
   __device__ __forceinline__ void store(lds_t<Tc> *s) const {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -300,9 +320,20 @@ struct Loader {
 
 
 // Elements of LDS (of type Tc) one gett_tile call needs.
-template <typename Tin, typename Tc, int BM, int BN, int BK, int NT, int LA, int LB, bool VA, bool VB>
+// Whether a whole-tile (FULL) accumulation moves B into LDS by direct-to-LDS
+// loads, into two buffers of its own.
+template <typename Tin, typename Tc, int BN, int BK, int LB, bool VB, int NT, bool FULL>
+constexpr bool gett_dma_b() {
+  return FULL && Loader<Tin, Tc, BN, BK, LB, VB, NT>::dma_ok;
+}
+
+// Elements of LDS (of type Tc) one gett_tile call needs (besides the B
+// buffers of a direct-to-LDS accumulation, which it declares itself).
+template <typename Tin, typename Tc, int BM, int BN, int BK, int NT, int LA, int LB, bool VA, bool VB,
+          bool FULL = false>
 constexpr int gett_lds_elems() {
-  return 2 * (Loader<Tin, Tc, BM, BK, LA, VA, NT>::ELEMS + Loader<Tin, Tc, BN, BK, LB, VB, NT>::ELEMS);
+  return 2 * (Loader<Tin, Tc, BM, BK, LA, VA, NT>::ELEMS +
+              (gett_dma_b<Tin, Tc, BN, BK, LB, VB, NT, FULL>() ? 0 : Loader<Tin, Tc, BN, BK, LB, VB, NT>::ELEMS));
 }
 
 // The register tile of one workgroup: a WGM x WGN grid of waves, each owning
@@ -373,6 +404,49 @@ __device__ __forceinline__ void gett_accumulate(WaveTile<Tc, BM, BN, WGM, WGN> &
   LoadB lb;
   la.init(tid, m0, M, t.offAm);
   lb.init(tid, n0, N, t.offBn);
+
+  if constexpr (gett_dma_b<Tin, Tc, BN, BK, LB, VB, NT, FULL>()) {
+    // B by direct-to-LDS loads into two buffers that are objects of their
+    // own (so that the compiler can tell the loads into one from the reads
+    // of the other), the step loop unrolled by two so that each half names
+    // its buffers; A as below, through registers
+    __shared__ __attribute__((aligned(16))) Tc sB0_[LoadB::ELEMS];
+    __shared__ __attribute__((aligned(16))) Tc sB1_[LoadB::ELEMS];
+    lds_t<Tc> *const sB0 = to_lds(sB0_), *const sB1 = to_lds(sB1_);
+    const lds_t<Tc> *const sA0 = s0;
+    lds_t<Tc> *const sA1 = s0 + LoadA::ELEMS;
+    const int64_t k_begin = s_begin * BK;
+    la.fetch_k(t.offAk, k_begin, K);
+    lb.fetch_k(t.offBk, k_begin, K);
+    la.template load<true>(A, k_begin, K);
+    lb.dma(B, sB0);
+    la.fetch_k(t.offAk, k_begin + BK, K);
+    lb.fetch_k(t.offBk, k_begin + BK, K);
+    la.store(s0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vector-memory counter at zero: B landed
+    __syncthreads();
+    // step `step` from (sAc, sBc); step + 1 into (sAn, sBn)
+    auto half = [&](int64_t step, const lds_t<Tc> *sAc, lds_t<Tc> *sAn, const lds_t<Tc> *sBc, lds_t<Tc> *sBn) {
+      la.template load<true>(A, (step + 1) * BK, K);
+      lb.dma(B, sBn);
+      la.fetch_k(t.offAk, (step + 2) * BK, K);
+      lb.fetch_k(t.offBk, (step + 2) * BK, K);
+      // every load of the step issued before the products (the direct-to-LDS
+      // ones have no users, and the scheduler would sink them to the wait)
+      __builtin_amdgcn_sched_barrier(0);
+      gett_mma_step<LoadA, LoadB, BK>(w, sAc, sBc, lane, wm0, wn0);
+      la.store(sAn);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      __syncthreads();
+    };
+    int64_t step = s_begin;
+    for (; step + 1 < s_end; step += 2) {
+      half(step, sA0, sA1, sB0, sB1);
+      half(step + 1, sA1, const_cast<lds_t<Tc> *>(sA0), sB1, sB0);
+    }
+    if (step < s_end) half(step, sA0, sA1, sB0, sB1);
+    return;
+  }
 
   // Software pipeline, uniform across steps: the last step also issues a
   // (masked, clamped-address) load of the step past the end, so the loop body
@@ -600,7 +674,8 @@ template <typename Tin, typename Tc, int BM, int BN, int BK, int WGM, int WGN, i
 __device__ __forceinline__ void gett_tile(const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C,
                                           const GettTables &t, int64_t M, int64_t N, int64_t K, double alpha,
                                           double beta, int64_t m0, int64_t n0, Tc *smem) {
-  static_assert(8 * (BM + BN) <= int(sizeof(Tc)) * gett_lds_elems<Tin, Tc, BM, BN, BK, 64 * WGM * WGN, LA, LB, VA, VB>(),
+  static_assert(8 * (BM + BN) <=
+                    int(sizeof(Tc)) * gett_lds_elems<Tin, Tc, BM, BN, BK, 64 * WGM * WGN, LA, LB, VA, VB, FULL>(),
                 "the tile's C offsets fit in its LDS");
   WaveTile<Tc, BM, BN, WGM, WGN> w;
   gett_accumulate<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB, FULL>(w, A, B, t, M, N, K, m0, n0, 0,

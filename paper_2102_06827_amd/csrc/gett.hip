@@ -82,7 +82,7 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
   constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
   constexpr int NT = 64 * WGM * WGN;
-  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB, FULL>()];
   int tm, tn;
   group_coords(xcd_remap(blockIdx.x, gridDim.x), tilesM, tilesN, &tm, &tn);
   gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB, FULL>(A, B, C, t, M, N, K, alpha, beta,
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
   constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
   constexpr int NT = 64 * WGM * WGN;
   typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
-  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB>()];
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB, FULL>()];
   const int S = sk.blocks, R = sk.tiles, b = blockIdx.x;
   // leftover tile r: the largest r with first(r) <= b
   const int r = int((int64_t(b + 1) * R - 1) / S);
