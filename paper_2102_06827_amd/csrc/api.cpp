@@ -907,14 +907,17 @@ double time_us(F fn, hipStream_t s, bool *ok) {
   return best;
 }
 
-// The classic splits (BF16x3, FP16x2): time the slice-pair product's
-// 128 x 64 and 192 x 192 tiles and, for FP32 storage in BF16x3, the fused
-// kernel; record the fastest (entry tile 0, 1, or 2 for fused) per problem
-// class and apply it.  Called with the cache lock held.
+// The split products: time the slice-pair product's tiles -- 128 x 64 and
+// 192 x 192 for the classic splits (BF16x3, FP16x2) and, for FP32 storage in
+// BF16x3, the fused kernel; 128 x 64 and 128 x 96 for the aligned BF16
+// slices -- and record the fastest (entry tile 0, 1, or 2 for the fused
+// kernel or the 128 x 96 tile) per problem class and apply it.  Called with
+// the cache lock held.
 comet_status_t autotune_split(comet_plan_s *p, TuneCache &tc) {
   Analysis &an = p->an;
   const std::string key = tune_key(an, arch_id(p->device));
   const bool can_fuse = an.compute == COMET_COMPUTE_SPLIT_BF16X3 && an.dtype == COMET_F32;
+  const bool aligned = an.compute == COMET_COMPUTE_SPLIT_BF16;
   auto apply = [&](int choice) -> comet_status_t {
     p->fused3 = choice == 2 && can_fuse;
     if (p->fused3) {
@@ -922,7 +925,7 @@ comet_status_t autotune_split(comet_plan_s *p, TuneCache &tc) {
       p->ws_bytes = 0;
       return COMET_OK;
     }
-    Status st = split_prepare(an, p->split, choice < 0 ? -1 : choice == 1 ? 1 : 0);
+    Status st = split_prepare(an, p->split, choice < 0 ? -1 : aligned ? choice : choice == 1 ? 1 : 0);
     if (!st.ok()) return fail(st);
     p->ws_bytes = p->split.ws_bytes;
     return COMET_OK;
@@ -941,8 +944,11 @@ comet_status_t autotune_split(comet_plan_s *p, TuneCache &tc) {
   if (ok) {
     (void)fill_value(bufA, std::max<int64_t>(an.sizeA, 1), dt, 0.5, s);
     (void)fill_value(bufB, std::max<int64_t>(an.sizeB, 1), dt, -0.25, s);
-    for (int choice = 0; choice <= (can_fuse ? 2 : 1); ++choice) {
+    for (int choice = 0; choice <= (can_fuse || aligned ? 2 : 1); ++choice) {
+      if (aligned && choice == 1) continue;
       if (apply(choice) != COMET_OK) continue;
+      // (a tile the problem cannot take falls back to 128 x 64: time it once)
+      if (aligned && choice == 2 && p->split.tile != 2) continue;
       if (p->ws_bytes > wsb) {
         if (ws) (void)hipFree(ws);
         ws = nullptr;
@@ -979,7 +985,8 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) cus = 256;
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
-  const bool classic = an.compute == COMET_COMPUTE_SPLIT_BF16X3 || an.compute == COMET_COMPUTE_SPLIT_FP16X2;
+  const bool classic = an.compute == COMET_COMPUTE_SPLIT_BF16X3 || an.compute == COMET_COMPUTE_SPLIT_FP16X2 ||
+                       an.compute == COMET_COMPUTE_SPLIT_BF16;
   if (tc.mode() != 0 && classic && !an.empty_out && !an.empty_sum && an.X.empty() && !std::getenv("COMET_SPLIT_TILE") &&
       !std::getenv("COMET_FUSED3"))
     return autotune_split(p.get(), tc);

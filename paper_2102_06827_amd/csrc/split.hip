@@ -33,8 +33,9 @@
 // Kernels, one launch each for both operands: an exponent pass (partial row
 // maxima over ranges of the summation, HBM-bound) and a pack pass (reduce a
 // row's partial maxima, gather through the offset tables into an LDS tile so
-// reads are coalesced along the operand's unit-stride label, then write
-// K-contiguous slices -- this is also the transpose of TTGT); then the
+// reads are coalesced along the operand's unit-stride label, then write the
+// slices K-contiguous in 64-byte runs, blocked along the summation -- this
+// is also the transpose of TTGT); then the
 // slice-pair matrix product on v_mfma_f32_16x16x32_{bf16,f16} or
 // v_mfma_i32_16x16x64_i8.
 #include <algorithm>
@@ -173,10 +174,22 @@ __device__ __forceinline__ void row_offsets(int64_t *ro, const int64_t *__restri
   }
 }
 
+// The packed slices of both operands share one layout, blocked along the
+// summation: a block holds, for 64 bytes of summation indices (32 16-bit or
+// 64 8-bit values), every row of every slice of A, then of B -- RT = S (Mp +
+// Np) rows of 64 bytes, block after block.  Element (slice p, row r, index k)
+// of an operand sits at row (k / CK) RT + p Rp + r of that layout counted
+// from the operand's first row (A's at 0, B's at S Mp), byte (k mod CK) x
+// the element size, CK = 64 / the element size.  A product's stage (one
+// block of the summation for a tile's rows) is then S runs of contiguous
+// rows per operand, and each 1 KB load of 16 rows reads 1 KB of memory.
+__host__ __device__ constexpr int64_t slice_rows(int S, int64_t Mp, int64_t Np) { return int64_t(S) * (Mp + Np); }
+
 // The two operands of one product, as the slicer kernels see them: rows R
 // (M or N) and summation K through the offset tables, tilesR slicer tiles of
 // rows, `part` the partial row maxima (ky ranges of the summation, pitch Rp),
-// `e` the final row exponents, `out` the slices (pitch Kp, Rp rows each).
+// `e` the final row exponents, `out` the operand's first slice row in the
+// blocked layout (Rp rows per slice).
 struct SliceOperand {
   const void *base;
   const int64_t *offR, *offK;
@@ -192,6 +205,7 @@ struct SliceOperand {
 struct SliceArgs {
   SliceOperand op[2];
   int64_t K, Kp;
+  int64_t RT;          // rows of one summation block of the packed slices
   int ky;
 };
 
@@ -252,15 +266,16 @@ __global__ __launch_bounds__(PT) void split_exp_kernel(SliceArgs a) {
     op.vec ? exp_block<Tin, 1, VEC>(op, rt, a.K, a.ky, emax) : exp_block<Tin, 1, 1>(op, rt, a.K, a.ky, emax);
 }
 
-// Cut a PR x PK tile into S slices, written K-contiguous: out[p][r][k]
-// (pitch Kp, Rp rows per slice).  Thread t writes 16 consecutive k of row
-// t/4, so the four threads of a row write one 128-byte line per 16-bit slice.
+// Cut a PR x PK tile into S slices, written in the blocked layout.  Thread t
+// writes 16 consecutive k of row t/4, so a wave writes, per slice and 64-byte
+// block of the summation, 16 consecutive rows: 1 KB of contiguous memory.
 // The block first reduces its rows' partial exponents; blocks of the first
 // summation tile also store them as the rows' final exponents, which the
 // product's epilogue reads.
 template <typename Tin, typename ST, int LAYOUT, int V, int MODE, int S>
-__device__ __forceinline__ void pack_block(const SliceOperand &op, int64_t bid, int64_t K, int64_t Kp, int ky,
+__device__ __forceinline__ void pack_block(const SliceOperand &op, int64_t bid, int64_t K, int64_t RT, int ky,
                                            double (*t)[PK + 1], int *erow, int *red) {
+  constexpr int CK = 64 / int(sizeof(ST));
   const Tin *__restrict__ base = static_cast<const Tin *>(op.base);
   ST *__restrict__ out = static_cast<ST *>(op.out);
   const int64_t R = op.R, Rp = op.Rp;
@@ -333,7 +348,8 @@ __device__ __forceinline__ void pack_block(const SliceOperand &op, int64_t bid, 
     }
 #pragma unroll
     for (int p = 0; p < S; ++p)
-      *reinterpret_cast<typename Vec8<ST>::type *>(out + (int64_t(p) * Rp + r) * Kp + k0 + kc) = sl[p];
+      *reinterpret_cast<typename Vec8<ST>::type *>(
+          out + (((k0 + kc) / CK) * RT + int64_t(p) * Rp + r) * CK + (k0 + kc) % CK) = sl[p];
   }
 }
 
@@ -349,14 +365,14 @@ __global__ __launch_bounds__(PT) void split_pack_kernel(SliceArgs a) {
   const SliceOperand &op = a.op[w];
   if (op.layout == 0) {
     if (op.vec)
-      pack_block<Tin, ST, 0, VEC, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+      pack_block<Tin, ST, 0, VEC, MODE, S>(op, bid, a.K, a.RT, a.ky, t, erow, red);
     else
-      pack_block<Tin, ST, 0, 1, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+      pack_block<Tin, ST, 0, 1, MODE, S>(op, bid, a.K, a.RT, a.ky, t, erow, red);
   } else {
     if (op.vec)
-      pack_block<Tin, ST, 1, VEC, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+      pack_block<Tin, ST, 1, VEC, MODE, S>(op, bid, a.K, a.RT, a.ky, t, erow, red);
     else
-      pack_block<Tin, ST, 1, 1, MODE, S>(op, bid, a.K, a.Kp, a.ky, t, erow, red);
+      pack_block<Tin, ST, 1, 1, MODE, S>(op, bid, a.K, a.RT, a.ky, t, erow, red);
   }
 }
 
@@ -393,10 +409,11 @@ __device__ __forceinline__ int sw(int r, int c) { return r * GBK + ((c ^ ((r >> 
 // 16 rows; one load of 64 lanes x 16 bytes fills a block, lane L writing
 // bytes 16 L .. 16 L + 15 of it, i.e. row 16 g + L / 4 at chunk position
 // L mod 4, which holds the row's chunk (L mod 4) ^ ((row / 4) mod 4).  Wave w
-// of NW takes blocks w, w + NW, ...  A and B: the packed slices, rows of
-// row_bytes.  The addresses do not depend on the stage but for its first
-// byte along the summation, so they are worked out once (init) and a stage
-// is NU loads (issue).  The loads are counted by the wave's vector-memory
+// of NW takes blocks w, w + NW, ...  A and B: the first row of each
+// operand's packed slices (64-byte rows in the blocked layout).  The
+// addresses do not depend on the stage but for its summation block's offset,
+// the same for A and B, so they are worked out once (init) and a stage is NU
+// loads (issue).  The loads are counted by the wave's vector-memory
 // counter: wait for it to reach zero, then a barrier, before the stage is
 // read.
 template <int BM, int BN, int S, int NW>
@@ -409,8 +426,7 @@ struct StageDMA {
   int nu;                // blocks of this wave (uniform)
 
   __device__ __forceinline__ void init(const char *__restrict__ A, const char *__restrict__ B, int64_t Mp,
-                                       int64_t Np, int64_t row_bytes, int64_t m0, int64_t n0, int wave,
-                                       int lane) {
+                                       int64_t Np, int64_t m0, int64_t n0, int wave, int lane) {
     const int w = __builtin_amdgcn_readfirstlane(wave);   // (the compiler cannot tell it is uniform)
     nu = 0;
 #pragma unroll
@@ -435,7 +451,7 @@ struct StageDMA {
       }
       const int row = g * BLK + (lane >> 2);
       const int c = (lane & 3) ^ ((row >> 2) & 3);
-      src[u] = rows + (rows_p + row) * row_bytes + c * 16;
+      src[u] = rows + (rows_p + row) * 64 + c * 16;
       dst[u] = base + g * BLK * 64;
       nu += blk < NBA + NBB ? 1 : 0;
     }
@@ -447,6 +463,58 @@ struct StageDMA {
       if ((NBA + NBB) % NW == 0 || u < nu)
         __builtin_amdgcn_global_load_lds(reinterpret_cast<const glb_t<void> *>(to_glb(src[u] + kb0)),
                                          reinterpret_cast<lds_t<void> *>(buf + dst[u]), 16, 0, 0);
+  }
+};
+
+// The same stage loads with 32-bit lane offsets from one base (the A slices'
+// first row; B's follows dB bytes on, and a summation block of both spans
+// less than 4 GB), one per block of this wave: wave w of NW
+// takes blocks w, w + NW, ..., every wave the same number (a wave short of
+// blocks loads the last one again, the same bytes to the same place).  A
+// block's place in the stage buffer is its index x 1 KB: A's S slices of BM
+// rows, then B's S slices of BN rows, 64-byte rows.
+template <int BM, int BN, int S, int NW>
+struct StageDMA32 {
+  static constexpr int BLK = 16;
+  static constexpr int NBA = S * BM / BLK, NBB = S * BN / BLK;
+  static constexpr int NU = (NBA + NBB + NW - 1) / NW;
+  uint32_t voff[NU];
+  int w;
+
+  __device__ __forceinline__ void init(int64_t dB, int64_t Mp, int64_t Np, int64_t m0, int64_t n0, int wave,
+                                       int lane) {
+    w = __builtin_amdgcn_readfirstlane(wave);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int b0 = w + u * NW;
+      const int blk = b0 < NBA + NBB ? b0 : NBA + NBB - 1;
+      int64_t row;   // row of the packed slices (all S of an operand stacked), relative to its base
+      int64_t base;
+      int g;
+      if (blk < NBA) {   // constant divisors on either side
+        g = blk % (BM / BLK);
+        row = int64_t(blk / (BM / BLK)) * Mp + m0;
+        base = 0;
+      } else {
+        g = (blk - NBA) % (BN / BLK);
+        row = int64_t((blk - NBA) / (BN / BLK)) * Np + n0;
+        base = dB;
+      }
+      const int r = g * BLK + (lane >> 2);
+      const int c = (lane & 3) ^ ((r >> 2) & 3);
+      voff[u] = uint32_t(base + (row + r) * 64 + c * 16);
+    }
+  }
+
+  __device__ __forceinline__ void issue(const char *__restrict__ base, lds_t<char> *buf, int64_t kb0) const {
+    const glb_t<const char> *b = to_glb(base + kb0);
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int b0 = w + u * NW;
+      const int blk = b0 < NBA + NBB ? b0 : NBA + NBB - 1;
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const glb_t<void> *>(b + voff[u]),
+                                       reinterpret_cast<lds_t<void> *>(buf + blk * 1024), 16, 0, 0);
+    }
   }
 };
 
@@ -588,18 +656,19 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
 
   v8 pre[NV];
   const int64_t nst = Kp / GBK;
+  const int64_t RT = slice_rows(S, Mp, Np);
   auto gload = [&](int64_t st) {
-    const int64_t k0 = (st < nst ? st : nst - 1) * GBK;
+    const int64_t kr = (st < nst ? st : nst - 1) * RT;   // the stage's summation block, in rows
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
       const int v = tid + u * GNT;
       if (v < NVA) {
         const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, kc = (rem % 4) * 8;
-        pre[u] = *reinterpret_cast<const v8 *>(As + (int64_t(p) * Mp + m0 + row) * Kp + k0 + kc);
+        pre[u] = *reinterpret_cast<const v8 *>(As + (kr + int64_t(p) * Mp + m0 + row) * GBK + kc);
       } else if (v < NVA + NVB) {
         const int w = v - NVA;
         const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, kc = (rem % 4) * 8;
-        pre[u] = *reinterpret_cast<const v8 *>(Bs + (int64_t(p) * Np + n0 + row) * Kp + k0 + kc);
+        pre[u] = *reinterpret_cast<const v8 *>(Bs + (kr + int64_t(p) * Np + n0 + row) * GBK + kc);
       }
     }
   };
@@ -662,10 +731,9 @@ __global__ __launch_bounds__(GNT) void split_gemm_kernel(const ST *__restrict__ 
     // ahead of the products (the scheduler would sink them, which have no
     // users, to the wait)
     StageDMA<GBM, GBN, S, GNT / 64> sd;
-    sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, Kp * int64_t(sizeof(ST)),
-            m0, n0, wave, lane);
+    sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, m0, n0, wave, lane);
     auto dma = [&](ST *buf, int64_t st) {
-      sd.issue(reinterpret_cast<lds_t<char> *>(to_lds(buf)), (st < nst ? st : nst - 1) * GBK * int64_t(sizeof(ST)));
+      sd.issue(reinterpret_cast<lds_t<char> *>(to_lds(buf)), (st < nst ? st : nst - 1) * RT * 64);
     };
     dma(smem0_, 0);
     stage_landed();
@@ -768,10 +836,10 @@ __global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restric
   };
   const int64_t nst = Kp / GBK;   // even: Kp is a multiple of 64
   StageDMA<XBM, XBN, S, XNT / 64> sd;
-  sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, Kp * int64_t(sizeof(ST)), m0,
-          n0, wave, lane);
+  sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, m0, n0, wave, lane);
+  const int64_t RT = slice_rows(S, Mp, Np);
   auto dma = [&](lds_t<ST> *buf, int64_t st) {
-    sd.issue(reinterpret_cast<lds_t<char> *>(buf), (st < nst ? st : nst - 1) * GBK * int64_t(sizeof(ST)));
+    sd.issue(reinterpret_cast<lds_t<char> *>(buf), (st < nst ? st : nst - 1) * RT * 64);
   };
   auto compute = [&](const lds_t<ST> *buf) {
     v8 bF[S][FN];
@@ -826,6 +894,205 @@ __global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restric
                                               sum += double(acc[a][i][j][r]) * PP::scale(a);
                                             return sum;
                                           });
+}
+
+// ------------------------------------- wide-tile aligned slice-pair GEMM --
+//
+// The aligned BF16 split (three FP32 accumulators per output block plus the
+// FP64 sum they are folded into) on large products: a 128 x 96 workgroup
+// tile of 4 waves, each owning 64 x 48 outputs (4 x 3 blocks of the
+// 16x16x32 MFMA), one workgroup per CU (two stages of S <= 5 slices fill 140
+// KB of LDS) -- a 3072^2 output is 768 tiles, three full rounds.  Against
+// the 128 x 64 tile of 8 waves every fragment read feeds twice as many
+// products.
+//
+// The folds of the accumulators into FP64 sit among the products so that
+// they overlap them: the exact diagonal accumulators right after their last
+// products of the stage that ends a group of FOLD stages, the third one at
+// the start of the stage after (before its first product there).
+constexpr int WBM = 128, WBN = 96;             // block tile
+constexpr int WWM = 2, WWN = 2;                // wave grid
+constexpr int WNT = 64 * WWM * WWN;
+
+// stages of S slices (64-byte rows of 16-bit values) of a WBM x WBN tile fit
+// twice in LDS
+constexpr bool wide_tile_fits(int S) { return 2 * S * (WBM + WBN) * 64 <= 160 * 1024; }
+
+template <typename ST, typename Tout, int MODE, int S>
+__global__ __launch_bounds__(WNT) void split_gemm_wide_kernel(const ST *__restrict__ As, const ST *__restrict__ Bs,
+                                                               const int *__restrict__ eA, const int *__restrict__ eB,
+                                                               Tout *__restrict__ C, const int64_t *__restrict__ offCm,
+                                                               const int64_t *__restrict__ offCn, int64_t M, int64_t N,
+                                                               int64_t Mp, int64_t Np, int64_t Kp, double alpha,
+                                                               double beta, int tilesM, int tilesN) {
+  typedef Pairs<MODE, S> PP;
+  static_assert(MODE == 0 && PP::NACC == 3 && PP::FOLD == 4, "the wide tile is for the aligned split");
+  static_assert(wide_tile_fits(S), "two stages must fit in LDS");
+  typedef typename Vec8<ST>::type v8;
+  constexpr int WM = WBM / WWM, WN = WBN / WWN;      // 64 x 48
+  constexpr int FM = WM / 16, FN = WN / 16;          // 4 x 3
+  constexpr int STAGE = S * (WBM + WBN) * GBK;       // elements per LDS buffer
+  __shared__ __attribute__((aligned(16))) ST smem0_[STAGE];
+  __shared__ __attribute__((aligned(16))) ST smem1_[STAGE];
+  lds_t<ST> *const buf0 = to_lds(smem0_);
+  lds_t<ST> *const buf1 = to_lds(smem1_);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int tm, tn;
+  {
+    const int total = tilesM * tilesN, X = 8, bid = blockIdx.x;
+    const int xcd = bid % X, local = bid / X, q = total / X, rem = total % X;
+    const int id = xcd * q + (xcd < rem ? xcd : rem) + local;
+    const int G = 8, per = G * tilesN, group = id / per, first = group * G;
+    const int gsize = tilesM - first < G ? tilesM - first : G;
+    const int in = id - group * per;
+    tm = first + in % gsize;
+    tn = in / gsize;
+  }
+  const int64_t m0 = int64_t(tm) * WBM, n0 = int64_t(tn) * WBN;
+  const int wm0 = (wave / WWN) * WM, wn0 = (wave % WWN) * WN;
+
+  f4_t acc[3][FM][FN];
+  d4_t acc64[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      acc64[i][j] = d4_t{0, 0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) acc[a][i][j] = f4_t{0, 0, 0, 0};
+    }
+
+  auto a_at = [&](const lds_t<ST> *buf, int p, int row, int c) { return buf + (p * WBM) * GBK + sw(row, c); };
+  auto b_at = [&](const lds_t<ST> *buf, int p, int row, int c) {
+    return buf + S * WBM * GBK + (p * WBN) * GBK + sw(row, c);
+  };
+  const int64_t nst = Kp / GBK;   // even: Kp is a multiple of 64
+  // (the launch checks that a summation block of the slices spans less
+  // than 4 GB)
+  const char *const base = reinterpret_cast<const char *>(As);
+  StageDMA32<WBM, WBN, S, WNT / 64> sd;
+  sd.init(reinterpret_cast<const char *>(Bs) - base, Mp, Np, m0, n0, wave, lane);
+  const int64_t RT = slice_rows(S, Mp, Np);
+  // every wave issues the same number of loads per stage, so a wait for all
+  // but the newer stage's loads is one constant
+  constexpr int NU = StageDMA32<WBM, WBN, S, WNT / 64>::NU;
+  static_assert(NU < 64, "loads in flight per wave fit the counter");
+  auto dma = [&](lds_t<ST> *buf, int64_t st) {
+    sd.issue(base, reinterpret_cast<lds_t<char> *>(buf), (st < nst ? st : nst - 1) * RT * 64);
+  };
+  // fold the exact diagonal accumulators / the third one into FP64
+  auto fold01_rows = [&](int i0, int i1) {
+#pragma unroll
+    for (int i = i0; i < i1; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[0][i][j][r]) + double(acc[1][i][j][r]);
+        acc[0][i][j] = f4_t{0, 0, 0, 0};
+        acc[1][i][j] = f4_t{0, 0, 0, 0};
+      }
+  };
+  auto fold01 = [&]() { fold01_rows(0, FM); };
+  auto fold2 = [&]() {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[2][i][j][r]);
+        acc[2][i][j] = f4_t{0, 0, 0, 0};
+      }
+  };
+  // one stage from buf: the loads of the next stage into the other buffer
+  // first (it was last read before the barrier that ended the stage before),
+  // then the products -- the B fragments of every slice held, the A
+  // fragments of one slice at a time -- then a wait for this wave's loads
+  // and the barrier.  f2 / f01: fold the third accumulator (at the start,
+  // before its first product) / the exact two (after their last products,
+  // slice 1's pair with B slice 0).
+  // The A fragments of slice p + 1 are requested before the products of
+  // slice p (scheduling barriers keep them there): with one wave per SIMD
+  // nothing else would cover the LDS latency.
+  auto read_a = [&](v8 *aF, const lds_t<ST> *buf, int p) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      aF[i] = *reinterpret_cast<const lds_t<v8> *>(a_at(buf, p, wm0 + i * 16 + (lane & 15), lane >> 4));
+  };
+  auto stage = [&](const lds_t<ST> *buf, lds_t<ST> *nxt, int64_t st, auto f2, auto f01) {
+    dma(nxt, st + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    v8 aF[2][FM], bF[S][FN];
+    read_a(aF[0], buf, 0);
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        bF[q][j] = *reinterpret_cast<const lds_t<v8> *>(b_at(buf, q, wn0 + j * 16 + (lane & 15), lane >> 4));
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      if (p + 1 < S) read_a(aF[(p + 1) & 1], buf, p + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (decltype(f2)::value)
+        if (p == 0) fold2();
+#pragma unroll
+      for (int q = 0; q < S - p; ++q) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[PP::acc(p, q)][i][j] = mfma_slice(aF[p & 1][i], bF[q][j], acc[PP::acc(p, q)][i][j]);
+        // the exact accumulators are final after slice 1's product with B
+        // slice 0; their rows are folded over the products of slices 1 to 3
+        // (which add to the third accumulator only)
+        if constexpr (decltype(f01)::value) {
+          if (p == 1 && q == 0) fold01_rows(0, FM / 2);
+          if (p == 2 && q == 0) fold01_rows(FM / 2, 3 * FM / 4);
+          if (p == 3 && q == 0) fold01_rows(3 * FM / 4, FM);
+        }
+      }
+      // spread the folds' VALU work among the products: one product, then a
+      // few conversions and additions, as long as both last
+      if constexpr (decltype(f2)::value)
+        if (p == 0)
+          for (int k = 0; k < 36; ++k) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+          }
+      if constexpr (decltype(f01)::value)
+        if (p >= 1 && p <= 3)
+          for (int k = 0; k < 36; ++k) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+          }
+    }
+    stage_landed();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  dma(buf0, 0);
+  stage_landed();
+  int64_t st = 0;
+  for (; st + 4 <= nst; st += 4) {
+    // groups of FOLD = 4 stages: the third accumulator of the group before
+    // is folded in the first stage, the exact two in the last
+    stage(buf0, buf1, st, std::true_type{}, std::false_type{});
+    stage(buf1, buf0, st + 1, std::false_type{}, std::false_type{});
+    stage(buf0, buf1, st + 2, std::false_type{}, std::false_type{});
+    stage(buf1, buf0, st + 3, std::false_type{}, std::true_type{});
+  }
+  if (st < nst) {   // two stages left (nst is even)
+    stage(buf0, buf1, st, std::true_type{}, std::false_type{});
+    stage(buf1, buf0, st + 1, std::false_type{}, std::false_type{});
+  }
+  fold2();
+  fold01();
+
+  // (the last stage's barrier passed: both buffers are free, the clamped
+  // loads past the end landed)
+  static_assert((WBM + WBN) * 12 <= STAGE * int(sizeof(ST)), "epilogue tables fit in LDS");
+  split_store<Tout, WBM, WBN, FM, FN, WNT>(C, offCm, offCn, eA, eB, M, N, alpha, beta, m0, n0, wm0, wn0, smem0_,
+                                          [&](int i, int j, int r) { return acc64[i][j][r]; });
 }
 
 // ------------------------------------------------------ INT8 slice-pair GEMM --
@@ -885,18 +1152,19 @@ __global__ __launch_bounds__(GNT) void split_gemm_i8_kernel(const signed char *_
   };
   i4_t pre[NV];
   const int64_t nst = k_len / IBK;
+  const int64_t RT = slice_rows(S, Mp, Np);
   auto gload = [&](int64_t st) {
-    const int64_t k0 = k_begin + (st < nst ? st : nst - 1) * IBK;
+    const int64_t kr = (k_begin / IBK + (st < nst ? st : nst - 1)) * RT;   // the stage's summation block, in rows
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
       const int v = tid + u * GNT;
       if (v < NVA) {
         const int p = v / (GBM * 4), rem = v % (GBM * 4), row = rem / 4, kc = (rem % 4) * 16;
-        pre[u] = *reinterpret_cast<const i4_t *>(As + (int64_t(p) * Mp + m0 + row) * Kp + k0 + kc);
+        pre[u] = *reinterpret_cast<const i4_t *>(As + (kr + int64_t(p) * Mp + m0 + row) * IBK + kc);
       } else if (v < NVA + NVB) {
         const int w = v - NVA;
         const int p = w / (GBN * 4), rem = w % (GBN * 4), row = rem / 4, kc = (rem % 4) * 16;
-        pre[u] = *reinterpret_cast<const i4_t *>(Bs + (int64_t(p) * Np + n0 + row) * Kp + k0 + kc);
+        pre[u] = *reinterpret_cast<const i4_t *>(Bs + (kr + int64_t(p) * Np + n0 + row) * IBK + kc);
       }
     }
   };
@@ -942,9 +1210,9 @@ __global__ __launch_bounds__(GNT) void split_gemm_i8_kernel(const signed char *_
 
   if constexpr (NBUF == 2) {
     StageDMA<GBM, GBN, S, GNT / 64> sd;
-    sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, Kp, m0, n0, wave, lane);
+    sd.init(reinterpret_cast<const char *>(As), reinterpret_cast<const char *>(Bs), Mp, Np, m0, n0, wave, lane);
     auto dma = [&](signed char *buf, int64_t st) {
-      sd.issue(reinterpret_cast<lds_t<char> *>(to_lds(buf)), k_begin + (st < nst ? st : nst - 1) * IBK);
+      sd.issue(reinterpret_cast<lds_t<char> *>(to_lds(buf)), (k_begin / IBK + (st < nst ? st : nst - 1)) * RT * 64);
     };
     dma(smem0_, 0);
     stage_landed();
@@ -1008,6 +1276,7 @@ hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &
                          reinterpret_cast<int *>(w + sp.offPB), eB, Bs, sp.Np};
   a.K = an.k;
   a.Kp = sp.Kp;
+  a.RT = slice_rows(S, sp.Mp, sp.Np);
   a.ky = sp.ky;
   hipLaunchKernelGGL((split_exp_kernel<Tin>), dim3(unsigned(a.op[0].tilesR + a.op[1].tilesR), unsigned(sp.ky)),
                      dim3(PT), 0, s, a);
@@ -1025,6 +1294,14 @@ hipError_t run_split(const Analysis &an, const SplitPlan &sp, const GettTables &
       hipLaunchKernelGGL((split_gemm_i8_kernel<Tin, S>), dim3(tilesM * tilesN), dim3(GNT), 0, s, As, Bs, eA, eB,
                          static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp, sp.Np, sp.Kp, k0, len, alpha,
                          k0 == 0 ? beta : 1.0, tilesM, tilesN);
+    }
+  } else if (sp.tile == 2) {
+    if constexpr (MODE == 0 && wide_tile_fits(S)) {
+      hipLaunchKernelGGL((split_gemm_wide_kernel<ST, Tin, MODE, S>), dim3(int(sp.Mp / WBM) * int(sp.Np / WBN)),
+                         dim3(WNT), 0, s, As, Bs, eA, eB, static_cast<Tin *>(C), t.offCm, t.offCn, an.m, an.n, sp.Mp,
+                         sp.Np, sp.Kp, alpha, beta, int(sp.Mp / WBM), int(sp.Np / WBN));
+    } else {
+      return hipErrorInvalidValue;
     }
   } else if (sp.tile == 1) {
     if constexpr (Pairs<MODE, S>::FOLD == 0) {
@@ -1084,17 +1361,27 @@ Status split_prepare(const Analysis &an, SplitPlan &sp, int force_tile) {
   // the large tile for the classic splits on large products, when padding
   // to 192 wastes little (COMET_SPLIT_TILE=0/1 overrides)
   sp.tile = 0;
+  const char *env = std::getenv("COMET_SPLIT_TILE");
   if (sp.mode == 1 || sp.mode == 2) {
     const double waste = double(round_up(an.m, XBM)) * double(round_up(an.n, XBN)) / (double(an.m) * double(an.n));
     sp.tile = (an.m >= 1536 && an.n >= 1536 && waste <= 1.1) ? 1 : 0;
-    const char *env = std::getenv("COMET_SPLIT_TILE");
     if (env && *env) sp.tile = std::atoi(env) == 1 ? 1 : 0;
     if (force_tile >= 0) sp.tile = force_tile == 1 ? 1 : 0;
+  } else if (sp.mode == 0 && wide_tile_fits(sp.S)) {
+    // the wide tile pads N to a multiple of 192 (its 96 and the slicer's 64)
+    const double waste = double(round_up(an.m, WBM)) * double(round_up(an.n, 192)) / (double(an.m) * double(an.n));
+    sp.tile = (an.m >= 1024 && an.n >= 1024 && waste <= 1.1) ? 2 : 0;
+    if (env && *env) sp.tile = std::atoi(env) == 2 ? 2 : 0;
+    if (force_tile >= 0) sp.tile = force_tile == 2 ? 2 : 0;
+    // its loads address a summation block of the slices with 32-bit offsets
+    if (64.0 * sp.S * (double(round_up(an.m, WBM)) + double(round_up(an.n, 192))) >= 4294967296.0) sp.tile = 0;
   }
-  sp.Mp = round_up(an.m, sp.tile == 1 ? XBM : GBM);
-  sp.Np = round_up(an.n, sp.tile == 1 ? XBN : GBN);
+  sp.Mp = round_up(an.m, sp.tile == 1 ? XBM : sp.tile == 2 ? WBM : GBM);
+  sp.Np = round_up(an.n, sp.tile == 1 ? XBN : sp.tile == 2 ? 192 : GBN);
   sp.Kp = round_up(an.k, PK);   // whole slicer tiles (a multiple of GBK and IBK)
-  const int64_t tiles = sp.tile == 1 ? (sp.Mp / XBM) * (sp.Np / XBN) : (sp.Mp / GBM) * (sp.Np / GBN);
+  const int64_t tiles = sp.tile == 1   ? (sp.Mp / XBM) * (sp.Np / XBN)
+                        : sp.tile == 2 ? (sp.Mp / WBM) * (sp.Np / WBN)
+                                       : (sp.Mp / GBM) * (sp.Np / GBN);
   // one pack launch covers both operands' tiles; its grid must stay below
   // 2^32 work-items
   if (tiles > INT_MAX || ((sp.Mp + sp.Np) / PR) * (sp.Kp / PK) > int64_t(INT_MAX) / PT)
@@ -1107,10 +1394,11 @@ Status split_prepare(const Analysis &an, SplitPlan &sp, int force_tile) {
   }
   const size_t es = sp.mode == 3 ? 1 : 2;
   size_t off = 0;
+  // both operands' slices in the blocked layout: B's first row follows A's
+  // S Mp rows of the first summation block
   sp.offA = off;
-  off = align256(off + size_t(sp.S) * sp.Mp * sp.Kp * es);
-  sp.offB = off;
-  off = align256(off + size_t(sp.S) * sp.Np * sp.Kp * es);
+  sp.offB = off + size_t(sp.S) * sp.Mp * 64;
+  off = align256(off + size_t(slice_rows(sp.S, sp.Mp, sp.Np)) * sp.Kp * es);
   sp.offEA = off;
   off = align256(off + size_t(sp.Mp) * 4);
   sp.offEB = off;

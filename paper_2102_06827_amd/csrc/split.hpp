@@ -17,11 +17,13 @@ struct SplitPlan {
   size_t offPA = 0, offPB = 0;                        // partial row exponents, ky per row
   int ky = 1;                                         // summation ranges of the exponent pass
   size_t ws_bytes = 0;
-  int tile = 0;             // slice-pair product: 0 the 128 x 64 tile, 1 the 192 x 192 tile (modes 1, 2)
+  int tile = 0;             // slice-pair product: 0 the 128 x 64 tile, 1 the 192 x 192 tile (modes 1, 2),
+                            // 2 the 128 x 96 tile (mode 0, S <= 5)
 };
 
-// force_tile >= 0 sets the slice-pair tile of modes 1 and 2 (the autotuner's
-// choice); otherwise a size rule, which COMET_SPLIT_TILE overrides.
+// force_tile >= 0 sets the slice-pair tile (the autotuner's choice: 0 or 1
+// for modes 1 and 2, 0 or 2 for mode 0); otherwise a size rule, which
+// COMET_SPLIT_TILE overrides.
 Status split_prepare(const Analysis &an, SplitPlan &sp, int force_tile = -1);
 // vecA / vecB: the offset tables allow vector loads of the operand along its
 // unit-stride dimension (the gather path's condition); the slicers use them

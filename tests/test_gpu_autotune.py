@@ -114,6 +114,26 @@ def test_autotune_split_product_tile(cache, dtype, choices):
         assert d["split_tile"] == entry["tile"]
 
 
+def test_autotune_aligned_split_tile(cache):
+    """The aligned BF16 split: the 128 x 64 and 128 x 96 slice-pair tiles are
+    timed, the winner is recorded and used, and the tuned plan is exact on
+    integer inputs."""
+    spec = "abij=acik*bkcj"
+    ext = dict(a=40, b=36, c=24, i=12, j=16, k=20)
+    A = synth.integers(13, shape_of("acik", ext))
+    B = synth.integers(14, shape_of("bkcj", ext))
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    print_case("autotune aligned split")
+    comet.autotune(str(cache), 2)
+    plan = comet.Plan(spec, Ad, Bd, compute="split_bf16")
+    C = plan(Ad, Bd)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), oracle.contract(spec, A, B))
+    (key, entry), = json.loads(cache.read_text())["entries"].items()
+    assert entry["tile"] in (0, 2) and entry["us"] > 0
+    assert plan.describe()["split_tile"] == entry["tile"]
+
+
 def test_autotune_batch_classes(cache):
     """The batch's tile classes come from timings per problem class: every
     problem is counted as tuned, the cache holds batch entries with valid

@@ -207,6 +207,61 @@ def test_split_large_tile_is_chosen_for_large_products():
     assert d.get("split_tile") == 1
 
 
+WIDE_CASES = [
+    # ragged M and N (not multiples of 128 and 192), K = 300: ten 32-index
+    # stages, two groups of four and a tail of two
+    ("ij=ik*kj", dict(i=200, j=250, k=300)),
+    ("abij=acik*bkcj", dict(a=40, b=40, c=40, i=12, j=12, k=12)),
+    ("abcd=aebf*dfce", dict(a=13, b=11, c=12, d=9, e=10, f=7)),
+]
+
+
+@pytest.mark.parametrize("S", [3, 4, 5, 6])
+@pytest.mark.parametrize("spec,ext", WIDE_CASES)
+def test_split_wide_tile_forced(spec, ext, S, monkeypatch):
+    """The 128 x 96 aligned slice-pair kernel (COMET_SPLIT_TILE=2) on ragged
+    problems: FP64 storage as close to the oracle as the 128 x 64 tile (the
+    same slice pairs, accumulators and fold length) and within the aligned
+    bar at S >= 5, FP32 storage within 1e-5, integer inputs bit for bit, and
+    all-zero rows exact.  Six slices do not fit its LDS: the plan falls back
+    to the 128 x 64 tile."""
+    A, B, C0 = inputs(spec, ext, 870, kind="normal", beta=True)
+    A[(0,) * A.ndim] = 0.0
+    A[(1,) + (slice(None),) * (A.ndim - 1)] = 0.0   # a zero slab: zero rows of the matrix view
+    ref = oracle.contract(spec, A, B, C0, alpha=1.25, beta=-0.5)
+    try:
+        comet.set_split_slices(S)
+        monkeypatch.setenv("COMET_SPLIT_TILE", "0")
+        err0 = oracle.relerr(run(spec, A, B, C0, 1.25, -0.5, torch.float64, "split_bf16"), ref)
+        monkeypatch.setenv("COMET_SPLIT_TILE", "2")
+        d = comet.Plan(spec, torch_dev(A, torch.float64), torch_dev(B, torch.float64),
+                       compute="split_bf16").describe()
+        assert d["split_tile"] == (2 if S <= 5 else 0), d
+        print_case("split wide tile", spec, S)
+        got = run(spec, A, B, C0, 1.25, -0.5, torch.float64, "split_bf16")
+        assert np.all(got[oracle.contract(spec, A, B) == 0.0] == (-0.5 * C0)[oracle.contract(spec, A, B) == 0.0])
+        err = oracle.relerr(got, ref)
+        assert err <= 2.0 * err0 + 1e-15, "relerr %.3e against %.3e on the 128 x 64 tile" % (err, err0)
+        assert S < 5 or err <= 1e-9, "relerr %.3e" % err
+        A32, B32 = A.astype(np.float32), B.astype(np.float32)
+        g32 = run(spec, A32, B32, None, 1.0, 0.0, torch.float32, "split_bf16")
+        assert oracle.relerr(g32, oracle.contract(spec, A32, B32)) <= 1e-5
+        Ai, Bi, Ci = inputs(spec, ext, 871, kind="integer", beta=True)
+        gi = run(spec, Ai, Bi, Ci, 1.0, 1.0, torch.float64, "split_bf16")
+        assert np.array_equal(gi, oracle.contract(spec, Ai, Bi, Ci, alpha=1.0, beta=1.0))
+    finally:
+        comet.set_split_slices(5)
+
+
+def test_split_wide_tile_is_chosen_for_large_aligned_products():
+    V, O = 96, 32
+    A = torch.zeros((V, V, O, O), dtype=torch.float64, device="cuda")
+    B = torch.zeros((V, O, V, O), dtype=torch.float64, device="cuda")
+    assert comet.Plan("abij=acik*bkcj", A, B, compute="split_bf16").describe().get("split_tile") == 2
+    small = torch.zeros((300, 300), dtype=torch.float64, device="cuda")
+    assert comet.Plan("ij=ik*kj", small, small, compute="split_bf16").describe().get("split_tile") == 0
+
+
 @pytest.mark.parametrize("fused", ["1", "0"])
 @pytest.mark.parametrize("spec,ext", CASES)
 def test_fp32_bf16x3_fused_and_sliced_paths(spec, ext, fused, monkeypatch):
