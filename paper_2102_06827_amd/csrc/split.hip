@@ -900,18 +900,20 @@ __global__ __launch_bounds__(XNT) void split_gemm_big_kernel(const ST *__restric
 //
 // The aligned BF16 split (three FP32 accumulators per output block plus the
 // FP64 sum they are folded into) on large products: a 128 x 96 workgroup
-// tile of 4 waves, each owning 64 x 48 outputs (4 x 3 blocks of the
+// tile of 8 waves, each owning 32 x 48 outputs (2 x 3 blocks of the
 // 16x16x32 MFMA), one workgroup per CU (two stages of S <= 5 slices fill 140
 // KB of LDS) -- a 3072^2 output is 768 tiles, three full rounds.  Against
-// the 128 x 64 tile of 8 waves every fragment read feeds twice as many
-// products.
+// the 128 x 64 tile every B fragment read feeds three products instead of
+// two; two waves share each SIMD, so one's LDS waits and folds run under
+// the other's products (the same tile with 4 waves of 64 x 48, one per
+// SIMD, measured 15% slower on the CCSD-like contraction).
 //
 // The folds of the accumulators into FP64 sit among the products so that
 // they overlap them: the exact diagonal accumulators right after their last
 // products of the stage that ends a group of FOLD stages, the third one at
 // the start of the stage after (before its first product there).
 constexpr int WBM = 128, WBN = 96;             // block tile
-constexpr int WWM = 2, WWN = 2;                // wave grid
+constexpr int WWM = 4, WWN = 2;                // wave grid
 constexpr int WNT = 64 * WWM * WWN;
 
 // stages of S slices (64-byte rows of 16-bit values) of a WBM x WBN tile fit
@@ -929,8 +931,8 @@ __global__ __launch_bounds__(WNT) void split_gemm_wide_kernel(const ST *__restri
   static_assert(MODE == 0 && PP::NACC == 3 && PP::FOLD == 4, "the wide tile is for the aligned split");
   static_assert(wide_tile_fits(S), "two stages must fit in LDS");
   typedef typename Vec8<ST>::type v8;
-  constexpr int WM = WBM / WWM, WN = WBN / WWN;      // 64 x 48
-  constexpr int FM = WM / 16, FN = WN / 16;          // 4 x 3
+  constexpr int WM = WBM / WWM, WN = WBN / WWN;      // 32 x 48
+  constexpr int FM = WM / 16, FN = WN / 16;          // 2 x 3
   constexpr int STAGE = S * (WBM + WBN) * GBK;       // elements per LDS buffer
   __shared__ __attribute__((aligned(16))) ST smem0_[STAGE];
   __shared__ __attribute__((aligned(16))) ST smem1_[STAGE];
@@ -1012,8 +1014,8 @@ __global__ __launch_bounds__(WNT) void split_gemm_wide_kernel(const ST *__restri
   // before its first product) / the exact two (after their last products,
   // slice 1's pair with B slice 0).
   // The A fragments of slice p + 1 are requested before the products of
-  // slice p (scheduling barriers keep them there): with one wave per SIMD
-  // nothing else would cover the LDS latency.
+  // slice p (scheduling barriers keep them there), so that their LDS latency
+  // runs under those products.
   auto read_a = [&](v8 *aF, const lds_t<ST> *buf, int p) {
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -1055,13 +1057,13 @@ __global__ __launch_bounds__(WNT) void split_gemm_wide_kernel(const ST *__restri
       // few conversions and additions, as long as both last
       if constexpr (decltype(f2)::value)
         if (p == 0)
-          for (int k = 0; k < 36; ++k) {
+          for (int k = 0; k < S * FM * FN; ++k) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
           }
       if constexpr (decltype(f01)::value)
         if (p >= 1 && p <= 3)
-          for (int k = 0; k < 36; ++k) {
+          for (int k = 0; k < (S - p) * FM * FN; ++k) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
           }
