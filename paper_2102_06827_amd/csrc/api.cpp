@@ -500,7 +500,12 @@ void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
   Schedule sc = pick_schedule(an, cus, p->vecA_tables, p->vecB_tables, forced_tile);
   const bool native = an.compute == COMET_COMPUTE_F64 || an.compute == COMET_COMPUTE_F32;
   if (!native || an.empty_out || an.empty_sum || !an.X.empty()) sc.sk_tiles = sc.sk_blocks = sc.persist = 0;
-  an.shortk = sc.persist > 0 ? 0 : shortk_choice(an, cus, p->vecA_tables, p->vecB_tables, forced_tile);
+  int forced = forced_tile;   // the caller's tile, else COMET_GETT_TILE's
+  if (const char *env = std::getenv("COMET_GETT_TILE"); forced < 0 && env && *env) {
+    const int t = std::atoi(env);
+    if (t >= 0 && t < gett_tile_count()) forced = t;
+  }
+  an.shortk = sc.persist > 0 ? 0 : shortk_choice(an, cus, p->vecA_tables, p->vecB_tables, forced);
   if (an.shortk > 0) {
     sc.tile = 3;
     sc.sk_tiles = sc.sk_blocks = 0;

@@ -1,8 +1,9 @@
 """The short-summation kernel (K <= 32; a persistent walk over 128 x 128
 tiles whose stores overlap the next tile's products) against the oracle:
 ragged M and N, every summation length up to 32, both storage types, both
-operand layouts, beta 0 and beta != 0, fewer tiles than workgroups, and the
-planner taking it for the triples contraction."""
+operand layouts, beta 0 and beta != 0, fewer tiles than workgroups and
+several per workgroup, a forced tile other than its own turning it off, and
+the planner taking it for the triples contraction."""
 import numpy as np
 import pytest
 
@@ -61,3 +62,44 @@ def test_shortk_chosen_for_triples_and_uniform_inputs():
     pts = np.concatenate([pts, np.zeros((1, 6), np.int64), np.array([shp]) - 1])
     ref = oracle.contract_points(spec, A, B, pts)
     assert oracle.relerr(to_np(C)[tuple(pts.T)], ref) <= 1e-12
+
+
+@pytest.mark.parametrize("spec,ext", [
+    ("mn=km*kn", dict(m=4096, n=4096, k=32)),                           # 1024 whole tiles, row-contiguous operands
+    ("abcijk=daij*bcdk", dict(a=16, b=16, c=16, d=32, i=16, j=16, k=16)),   # the triples pattern, 1024 whole tiles
+    ("mn=km*kn", dict(m=4000, n=4100, k=32)),                           # ragged edges
+])
+def test_shortk_several_tiles_per_workgroup(spec, ext, monkeypatch):
+    """Enough tiles that every workgroup walks several (beta = 0, whole tiles
+    where the extents allow): integer inputs bit for bit."""
+    c, a, b = oracle.split_spec(spec)
+    A = synth.integers(7421, shape_of(a, ext))
+    B = synth.integers(7422, shape_of(b, ext))
+    monkeypatch.setenv("COMET_GETT_SHORTK", "1")
+    print_case("shortk many tiles", spec)
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    plan = comet.Plan(spec, Ad, Bd, path="gett")
+    d = plan.describe()
+    assert d["shortk"] > 0 and d["tile"] == 3
+    C = plan(Ad, Bd)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), oracle.contract(spec, A, B))
+
+
+def test_forced_tile_turns_shortk_off(monkeypatch):
+    """A forced tile other than the short-summation kernel's own (tile 3)
+    keeps the plain schedule, which is still exact."""
+    spec, ext = "mn=km*kn", dict(m=1024, n=1024, k=32)
+    c, a, b = oracle.split_spec(spec)
+    A = synth.integers(7431, shape_of(a, ext))
+    B = synth.integers(7432, shape_of(b, ext))
+    monkeypatch.setenv("COMET_GETT_SHORTK", "1")
+    monkeypatch.setenv("COMET_GETT_TILE", "0")
+    print_case("shortk forced tile 0")
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    plan = comet.Plan(spec, Ad, Bd, path="gett")
+    d = plan.describe()
+    assert d["shortk"] == 0 and d["tile"] == 0
+    C = plan(Ad, Bd)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), oracle.contract(spec, A, B))
