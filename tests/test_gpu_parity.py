@@ -329,6 +329,33 @@ def test_fill(dtype):
     assert torch.equal(odd, torch.full_like(odd, 4.0))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_contiguous_fill_and_copy(dtype):
+    """One contiguous run on both sides (the plain vector walk): a fill of
+    40M elements (several grid passes), a scaled copy with beta != 0, and the
+    same run one element off 16-byte alignment (the table-driven kernel)."""
+    t = tdt(dtype)
+    x = torch.zeros(40_000_004, dtype=t, device="cuda")
+    print_case("contiguous fill", dtype)
+    comet.fill(x, 3.25)
+    torch.cuda.synchronize()
+    assert torch.equal(x, torch.full_like(x, 3.25))
+    del x
+    a = synth.uniform(620, (1000, 1004))
+    o0 = synth.uniform(621, (1000, 1004))
+    ad, od = torch_dev(a, t), torch_dev(o0, t)
+    comet.permute("ab=ab", ad, od, alpha=2.0, beta=-1.0)
+    torch.cuda.synchronize()
+    cast = np.float32 if dtype == "f32" else np.float64
+    exp = (2.0 * a.astype(cast).astype(np.float64) - o0.astype(cast).astype(np.float64)).astype(cast)
+    assert np.array_equal(to_np(od).astype(cast), exp)
+    buf = torch.zeros(1002, dtype=t, device="cuda")
+    v = buf[1:1001]
+    comet.fill(v, -1.5)
+    torch.cuda.synchronize()
+    assert buf[0].item() == 0.0 and buf[1001].item() == 0.0 and torch.equal(v, torch.full_like(v, -1.5))
+
+
 @pytest.mark.parametrize("spec", ["ji=ij", "jik=ijk"])
 def test_permute_64bit_indexing(spec):
     """More than 2^30 elements: the 64-bit index path of both kernels."""
