@@ -175,7 +175,9 @@ comet_status_t upload_tables(comet_plan_s *p) {
 // reads back.  The autotuner replaces this model with timings.
 constexpr double kThroughputF64[] = {28.7, 33.5, 30.9, 41.4, 39.5, 34.2, 33.4, 34.2, 35.0, 34.8};
 constexpr double kThroughputF32[] = {76.0, 70.6, 74.2, 77.0, 80.3, 69.2, 69.5};
-constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times
+constexpr int kTuneTTGT = 32;           // TTGT flattenings the autotuner times against the gather tiles
+constexpr int kTuneTTGTAll = 512;       // the same when TTGT is asked for: every one, up to this many,
+constexpr int kTuneTTGTRetime = 8;      // and the fastest this many timed twice more
 // A contraction whose operands only tile 1's element-load kernel can gather
 // goes through TTGT when the time the vector-load GEMM saves exceeds what the
 // permutes cost.  Rates on MI355X ("cmia=cdmn*inad" at 3072^3: element-load
@@ -529,6 +531,8 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
                           const TTGTChoice *forced_ttgt = nullptr);
 comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
                              const int64_t *sA, const int64_t *sB, const int64_t *sC);
+comet_status_t autotune_ttgt(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
+                             const int64_t *sA, const int64_t *sB, const int64_t *sC);
 hipError_t fill_value(void *p, int64_t n, int dt, double value, hipStream_t s);
 comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
                         hipStream_t s, void *ws);
@@ -704,6 +708,12 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
   }
   if (tune && path == COMET_PATH_AUTO) {
     comet_status_t rc2 = autotune_plan(p, spec, extents, sA, sB, sC);
+    if (rc2 != COMET_OK) return rc2;
+  }
+  // TTGT asked for, tuning on, no flattening forced: time the flattenings
+  if (tune && path == COMET_PATH_TTGT && an.path == COMET_PATH_TTGT && tuning && native && !forced_ttgt &&
+      !std::getenv("COMET_TTGT_ORDER") && !an.empty_out && !an.empty_sum && an.X.empty()) {
+    comet_status_t rc2 = autotune_ttgt(p, spec, extents, sA, sB, sC);
     if (rc2 != COMET_OK) return rc2;
   }
   out = std::move(p);
@@ -980,6 +990,101 @@ comet_status_t autotune_split(comet_plan_s *p, TuneCache &tc) {
   }
   tc.store(key, best);
   return apply(best.tile);
+}
+
+// A plan that asks for TTGT, with the autotuner on: time every flattening
+// with beta = 0 and with beta = 1 (up to kTuneTTGTAll; the fastest few
+// twice more), record the fastest per
+// problem class (the tuning key with "/ttgt") and rebuild the plan with it.
+// On MI355X the Section 6
+// cost model does not order the flattenings of the CCSD-like contractions
+// (its pick is among the slowest), so the flattening is measured, as the
+// gather tiles are.  Keeps the model's flattening when timing is not
+// possible.
+comet_status_t autotune_ttgt(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,
+                             const int64_t *sA, const int64_t *sB, const int64_t *sC) {
+  Analysis &an = p->an;
+  TuneCache &tc = tune_cache();
+  std::lock_guard<std::mutex> lk(tc.mutex());
+  const std::string key = tune_key(an, arch_id(p->device)) + "/ttgt";
+  std::vector<TTGTChoice> cands = ttgt_candidates(an);
+  TuneEntry best;
+  if (!(tc.mode() == 1 && tc.lookup(key, &best) && best.path == COMET_PATH_TTGT)) {
+    if (cands.size() > size_t(kTuneTTGTAll)) cands.resize(kTuneTTGTAll);
+    const size_t es = elem_size(an.dtype);
+    void *bufA = nullptr, *bufB = nullptr, *bufC = nullptr, *ws = nullptr;
+    size_t wsb = 0;
+    hipStream_t s = nullptr;
+    bool ok = hipStreamCreate(&s) == hipSuccess && hipMalloc(&bufA, std::max<int64_t>(an.sizeA, 1) * es) == hipSuccess &&
+              hipMalloc(&bufB, std::max<int64_t>(an.sizeB, 1) * es) == hipSuccess &&
+              hipMalloc(&bufC, std::max<int64_t>(an.sizeC, 1) * es) == hipSuccess;
+    best = TuneEntry{-1, COMET_PATH_TTGT, 1e30};
+    if (ok) {
+      const int dt = an.dtype == COMET_F64 ? 0 : 1;
+      (void)fill_value(bufA, std::max<int64_t>(an.sizeA, 1), dt, 0.5, s);
+      (void)fill_value(bufB, std::max<int64_t>(an.sizeB, 1), dt, -0.25, s);
+      (void)fill_value(bufC, std::max<int64_t>(an.sizeC, 1), dt, 0.125, s);
+      // every flattening once, then the fastest few again (their times lie
+      // within a few percent of each other)
+      std::vector<std::pair<double, size_t>> timed;
+      auto time_choice = [&](size_t i, bool *good) -> double {
+        std::unique_ptr<comet_plan_s> cp;
+        *good = false;
+        if (build_plan(cp, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false, &cands[i]) !=
+            COMET_OK)
+          return 0.0;
+        if (cp->ws_bytes > wsb) {
+          if (ws) (void)hipFree(ws);
+          ws = nullptr;
+          wsb = 0;
+          if (hipMalloc(&ws, cp->ws_bytes) != hipSuccess) return 0.0;
+          wsb = cp->ws_bytes;
+        }
+        // a plan serves any beta, and whether C is read changes which
+        // flattening is fastest: the score is the sum over beta = 0 and 1
+        const comet_plan_s *pt = cp.get();
+        bool g1;
+        const double t0 = time_us([&]() { return execute(pt, 1.0, bufA, bufB, 0.0, bufC, ws, wsb, s); }, s, good);
+        const double t1 = time_us([&]() { return execute(pt, 1.0, bufA, bufB, 1.0, bufC, ws, wsb, s); }, s, &g1);
+        *good = *good && g1;
+        return t0 + t1;
+      };
+      for (size_t i = 0; i < cands.size(); ++i) {
+        bool good;
+        const double us = time_choice(i, &good);
+        if (good) timed.emplace_back(us, i);
+      }
+      std::sort(timed.begin(), timed.end());
+      if (timed.size() > size_t(kTuneTTGTRetime)) timed.resize(kTuneTTGTRetime);
+      for (auto &tm : timed) {
+        for (int r = 0; r < 2; ++r) {
+          bool good;
+          const double us = time_choice(tm.second, &good);
+          if (good) tm.first = std::min(tm.first, us);
+        }
+        const TTGTChoice &ch = cands[tm.second];
+        if (tm.first < best.us)
+          best = TuneEntry{0, COMET_PATH_TTGT, tm.first, ch.a_order + "|" + ch.b_order + "|" + ch.c_order};
+      }
+      (void)hipStreamSynchronize(s);
+    }
+    if (bufA) (void)hipFree(bufA);
+    if (bufB) (void)hipFree(bufB);
+    if (bufC) (void)hipFree(bufC);
+    if (ws) (void)hipFree(ws);
+    if (s) (void)hipStreamDestroy(s);
+    if (!ok || best.us >= 1e30) return COMET_OK;
+    tc.store(key, best);
+    cands = ttgt_candidates(an);
+  }
+  for (const TTGTChoice &ch : cands) {
+    if (ch.a_order + "|" + ch.b_order + "|" + ch.c_order != best.ttgt) continue;
+    std::unique_ptr<comet_plan_s> tt;
+    if (build_plan(tt, spec, extents, sA, sB, sC, an.dtype, an.compute, COMET_PATH_TTGT, false, &ch) == COMET_OK)
+      p = std::move(tt);
+    break;
+  }
+  return COMET_OK;
 }
 
 comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec, const int64_t *extents,

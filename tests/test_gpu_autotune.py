@@ -134,6 +134,35 @@ def test_autotune_aligned_split_tile(cache):
     assert plan.describe()["split_tile"] == entry["tile"]
 
 
+def test_autotune_ttgt_flattening(cache):
+    """A plan that asks for TTGT with the autotuner on: every flattening is
+    timed, the fastest is recorded under its own key and used (also from the
+    cache), and the result is exact on integer inputs."""
+    spec = "abij=acik*bkcj"
+    ext = dict(a=16, b=12, c=8, i=8, j=12, k=8)
+    A = synth.integers(15, shape_of("acik", ext))
+    B = synth.integers(16, shape_of("bkcj", ext))
+    Ad, Bd = torch_dev(A, torch.float64), torch_dev(B, torch.float64)
+    ref = oracle.contract(spec, A, B)
+    print_case("autotune ttgt flattening")
+    comet.autotune(str(cache), 2)
+    plan = comet.Plan(spec, Ad, Bd, path="ttgt")
+    C = plan(Ad, Bd)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(C), ref)
+    (key, entry), = json.loads(cache.read_text())["entries"].items()
+    assert key.endswith("/ttgt") and entry["path"] == 2 and entry["us"] > 0
+    t = plan.describe()["ttgt"]
+    assert entry["ttgt"] == "%s|%s|%s" % (t["A"], t["B"], t["C"])
+    # from the cache: the same flattening, no new entry
+    comet.autotune(str(cache), 1)
+    plan2 = comet.Plan(spec, Ad, Bd, path="ttgt")
+    t2 = plan2.describe()["ttgt"]
+    assert (t2["A"], t2["B"], t2["C"]) == (t["A"], t["B"], t["C"])
+    assert np.array_equal(to_np(plan2(Ad, Bd)), ref)
+    assert len(json.loads(cache.read_text())["entries"]) == 1
+
+
 def test_autotune_batch_classes(cache):
     """The batch's tile classes come from timings per problem class: every
     problem is counted as tuned, the cache holds batch entries with valid
