@@ -54,15 +54,15 @@ FLOPS = 2.0 * V ** 3 * O ** 3            # 2 * M * N * K, M = N = K = 3072
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "f16": 2516.6, "i8": 5033.2}
 HBM_PEAK_GBS = 8000.0
 # The headline contraction runs as one launch group of the gather kernel:
-# whole output tiles (gett_kernel), the summation pieces of the tiles left
-# after the last full round (gett_piece_kernel, or gett_sk_kernel when
-# stream-K is planned) and the sum of those pieces (gett_piece_fixup_kernel
-# or gett_fixup_kernel).  HBM bytes of one group from FETCH_SIZE / WRITE_SIZE
+# the whole output tiles and the summation pieces of the tiles left after
+# the last full round in one launch (gett_whole_piece_kernel; gett_kernel
+# and gett_sk_kernel when stream-K is planned instead), then the sum of
+# those pieces (gett_piece_fixup_kernel or gett_fixup_kernel).  HBM bytes of one group from FETCH_SIZE / WRITE_SIZE
 # counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
 # valid only for the schedule and kernel version recorded, null otherwise.
 HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512, "even": 1}, "kernel_version": "k10",
                     "bytes": 959172639}
-KERNEL_VERSION = "k10"
+KERNEL_VERSION = "k11"
 
 
 def headline_kernels(d):
@@ -70,11 +70,11 @@ def headline_kernels(d):
     # 3 runs its unmasked variant (last template argument true)
     t = d["tile"]
     full = ", true" if t == 3 else ""
-    ks = ["gett_kernel<double, double, %d, 0, 1, true, true%s>" % (t, full)]
     if d.get("sk_tiles") and d.get("even"):
-        ks += ["gett_piece_kernel<double, double, %d, 0, 1, true, true%s>" % (t, full),
-               "gett_piece_fixup_kernel<double, double, %d>" % t]
-    elif d.get("sk_tiles"):
+        return ["gett_whole_piece_kernel<double, double, %d, 0, 1, true, true%s>" % (t, full),
+                "gett_piece_fixup_kernel<double, double, %d>" % t]
+    ks = ["gett_kernel<double, double, %d, 0, 1, true, true%s>" % (t, full)]
+    if d.get("sk_tiles"):
         ks += ["gett_sk_kernel<double, double, %d, 0, 1, true, true>" % t, "gett_fixup_kernel<double, double, %d>" % t]
     return ks
 MODES = {

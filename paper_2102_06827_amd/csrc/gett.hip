@@ -23,6 +23,7 @@
 // planner orders A and B so that C's unit-stride label lies along N, which
 // the MFMA output spreads over consecutive lanes.
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "gather.hpp"
@@ -340,16 +341,17 @@ __device__ __forceinline__ int64_t scalar64(int64_t x) {
   return int64_t((uint64_t(hi) << 32) | lo);
 }
 
-template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB, bool FULL = false>
-__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_piece_kernel(
-    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
-    int64_t K, double alpha, double beta, int tilesM, int tilesN, StreamK sk) {
+// Piece b of the balanced schedule's leftover tiles: its share of the
+// summation of its tile, stored as a partial tile in workspace slot b.
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB, bool FULL>
+__device__ __forceinline__ void gett_piece(const Tin *__restrict__ A, const Tin *__restrict__ B, const GettTables &t,
+                                           int64_t M, int64_t N, int64_t K, int tilesM, int tilesN, const StreamK &sk,
+                                           int b, Tc *smem) {
   constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
   constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
   constexpr int NT = 64 * WGM * WGN;
   typedef WaveTile<Tc, BM, BN, WGM, WGN> WT;
-  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB, FULL>()];
-  const int S = sk.blocks, R = sk.tiles, b = blockIdx.x;
+  const int S = sk.blocks, R = sk.tiles;
   // leftover tile r: the largest r with first(r) <= b
   const int r = int((int64_t(b + 1) * R - 1) / S);
   const int f0 = even_first(S, R, r), P = even_first(S, R, r + 1) - f0, j = b - f0;
@@ -369,6 +371,30 @@ __global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TI
                                                                        int64_t(tn) * BN, 0, (Kp + BK - 1) / BK, smem);
   constexpr int64_t kSlot = int64_t(WT::FM) * WT::FN * NT;   // 4-vectors per slot
   gett_store_partial<Tc, BM, BN, WGM, WGN>(w, static_cast<typename WT::acc_t *>(sk.ws) + b * kSlot);
+}
+
+// The whole tiles and the pieces of the balanced schedule in one launch:
+// workgroups 0 .. whole - 1 compute the whole tiles (in the XCD-aware order
+// over them), the rest the pieces, which start as whole tiles finish instead
+// of after the last one (3.5% less time on the CCSD-like contraction than
+// two launches).
+template <typename Tin, typename Tc, int TILE, int LA, int LB, bool VA, bool VB, bool FULL = false>
+__global__ __launch_bounds__(64 * kTiles[TILE].wgm * kTiles[TILE].wgn, kTiles[TILE].wpe) void gett_whole_piece_kernel(
+    const Tin *__restrict__ A, const Tin *__restrict__ B, Tin *__restrict__ C, GettTables t, int64_t M, int64_t N,
+    int64_t K, double alpha, double beta, int tilesM, int tilesN, StreamK sk) {
+  constexpr int BM = kTiles[TILE].bm, BN = kTiles[TILE].bn, BK = kTiles[TILE].bk;
+  constexpr int WGM = kTiles[TILE].wgm, WGN = kTiles[TILE].wgn;
+  constexpr int NT = 64 * WGM * WGN;
+  __shared__ __attribute__((aligned(16))) Tc smem[gett_lds_elems<Tin, Tc, BM, BN, BK, NT, LA, LB, VA, VB, FULL>()];
+  const int b = blockIdx.x;
+  if (b < sk.whole) {
+    int tm, tn;
+    group_coords(xcd_remap(b, sk.whole), tilesM, tilesN, &tm, &tn);
+    gett_tile<Tin, Tc, BM, BN, BK, WGM, WGN, LA, LB, VA, VB, FULL>(A, B, C, t, M, N, K, alpha, beta,
+                                                                   int64_t(tm) * BM, int64_t(tn) * BN, smem);
+    return;
+  }
+  gett_piece<Tin, Tc, TILE, LA, LB, VA, VB, FULL>(A, B, t, M, N, K, tilesM, tilesN, sk, b - sk.whole, smem);
 }
 
 // Sum the pieces of each leftover tile of the balanced schedule in piece
@@ -635,8 +661,8 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
         }
       }
       if (g.query_sk == 2)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy,
-                                                            gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            g.occupancy, gett_whole_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
       if (g.query_sk)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(g.occupancy,
                                                             gett_sk_kernel<Tin, Tc, TILE, LA, LB, VA, VB>, NT, 0);
@@ -715,22 +741,15 @@ hipError_t launch_v(const GettLaunch &g, hipStream_t s) {
       if (!ev.ws || ev.blocks <= 0 || ev.whole < 0 || ev.tiles < 1 || 2 * int64_t(ev.tiles) > ev.blocks ||
           int64_t(ev.whole) + ev.tiles != int64_t(tilesM) * tilesN)
         return hipErrorInvalidValue;
-      if (ev.whole > 0) {
-        if (full)
-          hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB, full_tile(TILE)>), dim3(ev.whole), dim3(NT), 0,
-                             s, A, B, C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
-        else
-          hipLaunchKernelGGL((gett_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.whole), dim3(NT), 0, s, A, B, C,
-                             g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-      }
+      // whole tiles and pieces in one launch (the pieces start as whole
+      // tiles finish), then the sum of each leftover tile's pieces
       if (full)
-        hipLaunchKernelGGL((gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB, full_tile(TILE)>), dim3(ev.blocks),
-                           dim3(NT), 0, s, A, B, C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, ev);
+        hipLaunchKernelGGL((gett_whole_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB, full_tile(TILE)>),
+                           dim3(ev.whole + ev.blocks), dim3(NT), 0, s, A, B, C, g.t, g.M, g.N, g.K, g.alpha, g.beta,
+                           tilesM, tilesN, ev);
       else
-        hipLaunchKernelGGL((gett_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.blocks), dim3(NT), 0, s, A, B,
-                           C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, ev);
+        hipLaunchKernelGGL((gett_whole_piece_kernel<Tin, Tc, TILE, LA, LB, VA, VB>), dim3(ev.whole + ev.blocks),
+                           dim3(NT), 0, s, A, B, C, g.t, g.M, g.N, g.K, g.alpha, g.beta, tilesM, tilesN, ev);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       constexpr int FRAGS = (BM / kTiles[TILE].wgm / 16) * (BN / kTiles[TILE].wgn / 16);

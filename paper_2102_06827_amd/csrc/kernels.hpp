@@ -21,9 +21,10 @@ struct StreamK {
   int tiles = 0;
   int blocks = 0;
   void *ws = nullptr;
-  // nonzero: the balanced schedule instead: the first `whole` tiles whole
-  // (gett_kernel), then one round of `blocks` workgroups (gett_piece_kernel)
-  // that split the `tiles` leftover tiles along the summation, tile r into
+  // nonzero: the balanced schedule instead: the first `whole` tiles whole,
+  // then one round of `blocks` workgroups that split the `tiles` leftover
+  // tiles along the summation (both in one launch, gett_whole_piece_kernel),
+  // tile r into
   // the pieces floor(blocks * r / tiles) .. floor(blocks * (r + 1) / tiles) - 1
   // (at least two), which gett_piece_fixup_kernel sums; ws holds one slot
   // per piece

@@ -17,7 +17,7 @@ namespace comet {
 
 namespace {
 const char *kFormat = "comet-tune-2";
-const char *kKernelVersion = "k10";   // bump when kernels change in a way that invalidates timings
+const char *kKernelVersion = "k11";   // bump when kernels change in a way that invalidates timings
 
 int bucket(int64_t x) {
   int b = 0;

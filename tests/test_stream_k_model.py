@@ -9,7 +9,7 @@ This mirror re-derives every piece and checks that the steps of every tile
 are covered exactly once, that every slot index lies inside the 2*blocks
 slots the plan allocates, that no slot is written twice, and that the fixup
 reads exactly the slots written for its tile.  The same for the balanced
-schedule's pieces (gett_piece_kernel, gett_piece_fixup_kernel).  The mirror
+schedule's pieces (gett_whole_piece_kernel, gett_piece_fixup_kernel).  The mirror
 must be kept in step with the device code.
 """
 import pytest
@@ -105,7 +105,7 @@ def test_owner_matches_shares():
             assert sk_begin(I, blocks, s) <= x < sk_begin(I, blocks, s + 1)
 
 
-# ---- the balanced schedule (gett_piece_kernel, gett_piece_fixup_kernel) ----
+# ---- the balanced schedule (gett_whole_piece_kernel, gett_piece_fixup_kernel) ----
 # S workgroups share R leftover tiles: tile r takes workgroups
 # first(r) = floor(S r / R) .. first(r + 1) - 1, workgroup b finds its tile as
 # r = floor(((b + 1) R - 1) / S) and its piece j = b - first(r) of P = first(r
