@@ -60,8 +60,8 @@ HBM_PEAK_GBS = 8000.0
 # those pieces (gett_piece_fixup_kernel or gett_fixup_kernel).  HBM bytes of one group from FETCH_SIZE / WRITE_SIZE
 # counters scaled by a plain 1 GiB copy (profiles/gett_f64_ccsd_v96_o32_hbm_counters.md);
 # valid only for the schedule and kernel version recorded, null otherwise.
-HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512, "even": 1}, "kernel_version": "k10",
-                    "bytes": 959172639}
+HEADLINE_TRAFFIC = {"schedule": {"tile": 3, "sk_tiles": 64, "sk_blocks": 512, "even": 1}, "kernel_version": "k11",
+                    "bytes": 971436304}
 KERNEL_VERSION = "k11"
 
 
