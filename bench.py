@@ -502,10 +502,12 @@ def bench_permute(comet, reps):
 
 
 def bench_ttgt_study(comet, reps=10):
-    """TTGT permutation choice on MI355X (Section 6's cost model): time every
-    valid flattening -- each order of the M, N and K label groups, each operand
-    stored K-major or not -- and compare the planner's pick with the fastest
-    and with GETT.  Config 2 (FP64) and config 3 (FP64, beta = 0)."""
+    """TTGT permutation choice on MI355X (Section 6): time every valid
+    flattening -- each order of the M, N and K label groups, each operand
+    stored K-major or not -- and rank the planner's pick (the MI355X time
+    model), the published position weights' pick and the autotuner's pick
+    among them, against GETT too.  Config 2 (FP64) and config 3 (FP64,
+    beta = 0)."""
     import itertools
     import torch
     dev = torch.device("cuda:0")
@@ -533,6 +535,13 @@ def bench_ttgt_study(comet, reps=10):
         K = [l for l in a if l not in c]
         pick = comet.analyze(spec, [ext[l] for l in spec_labels(spec)], path="ttgt")["ttgt"]
         pick_key = (pick["A"], pick["B"], pick["C"])
+        # the published position weights' pick, for comparison
+        os.environ["COMET_TTGT_MODEL"] = "weights"
+        try:
+            wpick = comet.analyze(spec, [ext[l] for l in spec_labels(spec)], path="ttgt")["ttgt"]
+        finally:
+            os.environ.pop("COMET_TTGT_MODEL", None)
+        wpick_key = (wpick["A"], wpick["B"], wpick["C"])
         rows = []
         for mo in itertools.permutations(M):
             for no in itertools.permutations(N):
@@ -580,7 +589,10 @@ def bench_ttgt_study(comet, reps=10):
                      "best_ttgt": {"orders": "|".join(best), "ms": round(times[best], 4)},
                      "planner_pick": {"orders": "|".join(pick_key), "ms": round(times.get(pick_key, float("nan")), 4),
                                       "rank": ranked.index(pick_key) + 1 if pick_key in times else None,
-                                      "cost": pick["cost"]},
+                                      "model_us": round(pick["model_us"], 1)},
+                     "weights_pick": {"orders": "|".join(wpick_key), "ms": round(times.get(wpick_key, float("nan")), 4),
+                                      "rank": ranked.index(wpick_key) + 1 if wpick_key in times else None,
+                                      "cost": wpick["cost"]},
                      "tuned_pick": {"orders": "|".join(tuned_key), "ms": round(times.get(tuned_key, float("nan")), 4),
                                     "rank": ranked.index(tuned_key) + 1 if tuned_key in times else None},
                      "worst_ttgt": {"orders": "|".join(ranked[-1]), "ms": round(times[ranked[-1]], 4)},

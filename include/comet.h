@@ -128,16 +128,20 @@ typedef enum {
 /* Which lowering a plan uses.
  *   AUTO  the planner's choice: the fused gather path, except TTGT where
  *         the autotune cache recorded it as faster for this problem class,
- *         and for native FP64 / FP32 products of 2^28 multiply-adds and more
- *         (no batch labels) whose operands only the gather path's element
- *         loads can read (their unit strides lie on different summation
- *         labels) while the TTGT matrices can be read in vectors.
+ *         and for native FP64 / FP32 products (no batch labels) whose
+ *         operands only the gather path's element loads can read (their
+ *         unit strides lie on different summation labels) where an estimate
+ *         of the permutes' traffic and launches against the GEMM time they
+ *         save says TTGT is faster (from about 768^3 on MI355X).
  *   GETT  operands are gathered through per-label offset tables straight into
  *         on-chip tiles; no transposed copies are made.
  *   TTGT  transpose-transpose-GEMM-transpose (Section 2; Section 6 "TTGT"):
  *         A and B are permuted into matrices, multiplied, and the product is
- *         permuted into C, with the permutation picked by the cost model of
- *         Section 6 ("Optimal permutation for TTGT"). */
+ *         permuted into C.  The flattening (Section 6 "Optimal permutation
+ *         for TTGT") is the fastest under a time model of the permute
+ *         kernels and the product on MI355X; environment variable
+ *         COMET_TTGT_MODEL=weights takes the cost model Section 6 publishes
+ *         instead. */
 typedef enum { COMET_PATH_AUTO = 0, COMET_PATH_GETT = 1, COMET_PATH_TTGT = 2 } comet_path_t;
 
 typedef struct comet_plan_s *comet_plan_t;

@@ -187,9 +187,14 @@ constexpr int kTuneTTGTRetime = 8;      // and the fastest this many timed twice
 // and its ramp).  Measured crossover:
 // 512^3 0.031 (gather) vs 0.034 ms (TTGT) in FP64, 768^3 0.063 vs 0.047;
 // FP32 0.025 vs 0.027 and 0.054 vs 0.039.
+// When an extent keeps even the TTGT matrices from vector reads (an odd
+// summation length, say), their GEMM still reads dense rows: 49 TFLOP/s in
+// FP64 and 50 in FP32 at 3025^3 (extents of 55), where the element-load
+// gather ran at 13 and 16.
 constexpr double kElemLoadFlops = 22.0e12;        // FLOP/s, FP64 and FP32
 constexpr double kVecGemmFlopsF64 = 58.0e12;
 constexpr double kVecGemmFlopsF32 = 100.0e12;
+constexpr double kDenseElemGemmFlops = 45.0e12;
 constexpr double kPermuteBytesPerS = 4.5e12;
 constexpr double kPermuteLaunchS = 5.0e-6;
 constexpr size_t kTTGTMaxWorkspace = size_t(4) << 30;   // no automatic TTGT needing more
@@ -204,7 +209,9 @@ constexpr double kSkLaunchUs = 4.0;      // the two extra launches
 // minus the permutes' traffic and launches.
 double ttgt_saving_s(const Analysis &an, const comet_plan_s &tt) {
   const double flops = 2.0 * double(an.m) * double(an.n) * double(an.k);
-  const double vec = an.compute == COMET_COMPUTE_F64 ? kVecGemmFlopsF64 : kVecGemmFlopsF32;
+  const bool vec_reads = tt.gemm && tt.gemm->vecA_tables && tt.gemm->vecB_tables;
+  const double vec = !vec_reads ? kDenseElemGemmFlops
+                     : an.compute == COMET_COMPUTE_F64 ? kVecGemmFlopsF64 : kVecGemmFlopsF32;
   const TTGTChoice &c = tt.an.ttgt;
   const double es = double(elem_size(an.dtype));
   auto count = [&](const std::string &labels) {
@@ -673,8 +680,7 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
       an.X.empty() && !an.empty_out && !an.empty_sum && !(p->vecA_tables && p->vecB_tables)) {
     std::unique_ptr<comet_plan_s> tt;
     if (build_plan(tt, spec, extents, sA, sB, sC, dtype, compute, COMET_PATH_TTGT, false) == COMET_OK && tt->gemm &&
-        tt->gemm->vecA_tables && tt->gemm->vecB_tables && tt->ws_bytes <= kTTGTMaxWorkspace &&
-        ttgt_saving_s(an, *tt) > 0.0) {
+        tt->ws_bytes <= kTTGTMaxWorkspace && ttgt_saving_s(an, *tt) > 0.0) {
       out = std::move(tt);
       return COMET_OK;
     }

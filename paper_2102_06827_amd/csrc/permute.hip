@@ -27,11 +27,12 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "permute_shape.hpp"
 
 namespace comet {
 namespace {
 
-constexpr int TP = 32;   // transpose tile edge
+constexpr int TP = kPermTile;   // transpose tile edge
 constexpr int TR = 8;    // thread rows of the transpose block
 constexpr int SB = 256;  // stream block
 constexpr int SU = 4;    // vectors per stream thread per pass
@@ -268,34 +269,7 @@ __global__ __launch_bounds__(TP *TR) void permute_tiled(const T *__restrict__ in
   }
 }
 
-struct Dim {
-  int64_t ext, si, so;
-};
-
-// Drop extent-1 dimensions and fuse pairs that are contiguous in both
-// tensors (the faster one continues into the slower one on both sides).
-std::vector<Dim> normalise(const PermuteLaunch &p) {
-  std::vector<Dim> d;
-  for (int k = 0; k < p.ndim; ++k)
-    if (p.ext[k] != 1) d.push_back({p.ext[k], p.s_in[k], p.s_out[k]});
-  bool merged = true;
-  while (merged) {
-    merged = false;
-    for (size_t f = 0; f < d.size() && !merged; ++f)
-      for (size_t g = 0; g < d.size() && !merged; ++g) {
-        if (f == g) continue;
-        // g continues f in both tensors
-        if (d[g].si == d[f].si * d[f].ext && d[g].so == d[f].so * d[f].ext) {
-          d[f].ext *= d[g].ext;
-          d.erase(d.begin() + g);
-          merged = true;
-        }
-      }
-  }
-  return d;
-}
-
-void fill(DimSet &s, const std::vector<Dim> &d, const std::vector<int> &idx) {
+void fill(DimSet &s, const std::vector<PermDim> &d, const std::vector<int> &idx) {
   s.n = (int)idx.size();
   for (int k = 0; k < s.n; ++k) {
     s.ext[k] = d[idx[k]].ext;
@@ -306,24 +280,16 @@ void fill(DimSet &s, const std::vector<Dim> &d, const std::vector<int> &idx) {
 
 template <typename T>
 hipError_t launch_perm_t(const PermuteLaunch &p, hipStream_t s) {
-  int64_t total = 1;
-  for (int k = 0; k < p.ndim; ++k) total *= p.ext[k];
-  if (total == 0) return hipSuccess;
-  std::vector<Dim> d = normalise(p);
+  const PermShape sh = permute_shape(p.ndim, p.ext, p.s_in, p.s_out, p.alpha != 0.0);
+  if (sh.kind == PERM_EMPTY) return hipSuccess;
+  const std::vector<PermDim> &d = sh.d;
+  const int64_t total = sh.total;
   const T *in = static_cast<const T *>(p.in);
   T *out = static_cast<T *>(p.out);
   const int n = (int)d.size();
-  // unit dimensions: the smallest stride on each side (without reads, only
-  // the output side matters)
-  int ui = -1, uo = -1;
-  for (int k = 0; k < n; ++k) {
-    if (uo < 0 || d[k].so < d[uo].so) uo = k;
-    if (ui < 0 || d[k].si < d[ui].si) ui = k;
-  }
-  if (p.alpha == 0.0) ui = uo;
   constexpr int WF = Vec16<T>::W;
-  if (n == 1 && d[0].so == 1 && (p.alpha == 0.0 || d[0].si == 1) && d[0].ext % WF == 0 &&
-      reinterpret_cast<uintptr_t>(out) % 16 == 0 && (p.alpha == 0.0 || reinterpret_cast<uintptr_t>(in) % 16 == 0)) {
+  if (sh.kind == PERM_FLAT && d[0].ext % WF == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0 &&
+      (p.alpha == 0.0 || reinterpret_cast<uintptr_t>(in) % 16 == 0)) {
     const int64_t nv = d[0].ext / WF;
     const int64_t want = (nv + int64_t(SB) * FL - 1) / (int64_t(SB) * FL);
     const unsigned grid = unsigned(std::max<int64_t>(1, std::min<int64_t>(want, 16384)));
@@ -331,7 +297,8 @@ hipError_t launch_perm_t(const PermuteLaunch &p, hipStream_t s) {
                        p.beta, p.fill);
     return hipGetLastError();
   }
-  if (n == 0 || ui == uo) {
+  if (sh.kind == PERM_FLAT || sh.kind == PERM_STREAM) {
+    const int uo = sh.uo;
     StreamArgs a{};
     std::vector<int> rows;
     for (int k = 0; k < n; ++k)
@@ -367,46 +334,18 @@ hipError_t launch_perm_t(const PermuteLaunch &p, hipStream_t s) {
       hipLaunchKernelGGL((permute_stream<T, 1, uint64_t>), dim3(grid), dim3(SB), 0, s, in, out, a, p.alpha, p.beta);
     return hipGetLastError();
   }
-  // transpose: grow Gi from ui along input contiguity and Go from uo along
-  // output contiguity, until each holds TP elements
-  std::vector<int> gi{ui}, go{uo};
-  std::vector<bool> used(n, false);
-  used[ui] = used[uo] = true;
-  int64_t EI = d[ui].ext, EO = d[uo].ext;
-  auto grow = [&](std::vector<int> &g, int64_t &E, bool input) {
-    while (E < TP) {
-      const Dim &last = d[g.back()];
-      int next = -1;
-      for (int k = 0; k < n; ++k) {
-        if (used[k]) continue;
-        if (input ? d[k].si == last.si * last.ext : d[k].so == last.so * last.ext) {
-          next = k;
-          break;
-        }
-      }
-      if (next < 0) break;
-      used[next] = true;
-      g.push_back(next);
-      E *= d[next].ext;
-    }
-  };
-  grow(gi, EI, true);
-  grow(go, EO, false);
-  std::vector<int> rest;
-  for (int k = 0; k < n; ++k)
-    if (!used[k]) rest.push_back(k);
-  std::sort(rest.begin(), rest.end(), [&](int x, int y) { return d[x].so < d[y].so; });
+  // transpose over the groups Gi and Go
   TileArgs a{};
-  fill(a.gi, d, gi);
-  fill(a.go, d, go);
-  fill(a.batch, d, rest);
-  a.EI = EI;
-  a.EO = EO;
-  a.gi_sin = d[ui].si;
-  a.go_sout = d[uo].so;
-  a.tiles_i = (EI + TP - 1) / TP;
-  a.tiles_o = (EO + TP - 1) / TP;
-  const int64_t blocks = a.tiles_i * a.tiles_o * (total / (EI * EO));
+  fill(a.gi, d, sh.gi);
+  fill(a.go, d, sh.go);
+  fill(a.batch, d, sh.rest);
+  a.EI = sh.EI;
+  a.EO = sh.EO;
+  a.gi_sin = d[sh.ui].si;
+  a.go_sout = d[sh.uo].so;
+  a.tiles_i = (sh.EI + TP - 1) / TP;
+  a.tiles_o = (sh.EO + TP - 1) / TP;
+  const int64_t blocks = a.tiles_i * a.tiles_o * (total / (sh.EI * sh.EO));
   if (total < (int64_t(1) << 30))
     hipLaunchKernelGGL((permute_tiled<T, uint32_t>), dim3(unsigned(blocks)), dim3(TP, TR), 0, s, in, out, a, p.alpha,
                        p.beta);

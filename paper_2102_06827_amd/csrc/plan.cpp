@@ -10,12 +10,14 @@
 // tensor holding it.  The TTGT permutation is picked by the cost model of
 // Section 6 ("Optimal permutation for TTGT").
 #include "plan.hpp"
+#include "permute_shape.hpp"
 
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <set>
 #include <sstream>
 
 namespace comet {
@@ -216,7 +218,7 @@ static bool dense_rowmajor(const std::vector<int64_t> &ext, const std::vector<in
   return true;
 }
 
-TTGTChoice choose_ttgt(const Analysis &an) {
+static TTGTChoice choose_ttgt_weights(const Analysis &an) {
   const std::string &c = an.spec_c, &a = an.spec_a, &b = an.spec_b;
   std::string Mset, Nset, Kset;
   for (char ch : a) (c.find(ch) != std::string::npos ? Mset : Kset) += ch;
@@ -285,6 +287,82 @@ TTGTChoice choose_ttgt(const Analysis &an) {
   return best;
 }
 
+double ttgt_model_us(const Analysis &an, const TTGTChoice &ch) {
+  auto ext_of = [&](char ch_) {
+    return an.extents[std::find(an.labels.begin(), an.labels.end(), ch_) - an.labels.begin()];
+  };
+  // dense row-major stride of `label` in `order`
+  auto dense = [&](const std::string &order, char label) {
+    int64_t st = 1;
+    for (size_t p = order.size(); p-- > 0;) {
+      if (order[p] == label) return st;
+      st *= ext_of(order[p]);
+    }
+    return int64_t(0);
+  };
+  const int es = (int)elem_size(an.dtype);
+  double t = 0.0;
+  // one permute from `src` (strides given, or dense when null) to `dst` (the same)
+  auto perm = [&](const std::string &src, const std::vector<int64_t> *ssrc, const std::string &dst,
+                  const std::vector<int64_t> *sdst, bool reads_out) {
+    std::vector<int64_t> e, si, so;
+    for (size_t p = 0; p < src.size(); ++p) {
+      e.push_back(ext_of(src[p]));
+      si.push_back(ssrc ? (*ssrc)[p] : dense(src, src[p]));
+      const size_t q = dst.find(src[p]);
+      so.push_back(sdst ? (*sdst)[q] : dense(dst, src[p]));
+    }
+    t += permute_time_us(permute_shape((int)e.size(), e.data(), si.data(), so.data(), true), es, reads_out);
+  };
+  if (ch.a_copy) perm(an.spec_a, &an.strA, ch.a_order, nullptr, false);
+  if (ch.b_copy) perm(an.spec_b, &an.strB, ch.b_order, nullptr, false);
+  // a plan serves any beta: the output permute is costed with its read of C
+  if (ch.c_copy) perm(ch.c_order, nullptr, an.spec_c, &an.strC, true);
+  // the product: FLOP at 65 (FP64) or 120 (FP32) TFLOP/s, or its output at
+  // 5 TB/s written (and read), whichever is longer
+  double M = 1, N = 1, K = 1;
+  for (char l : an.spec_a) (an.spec_c.find(l) != std::string::npos ? M : K) *= double(ext_of(l));
+  for (char l : an.spec_b)
+    if (an.spec_c.find(l) != std::string::npos) N *= double(ext_of(l));
+  const double rate = an.dtype == COMET_F64 ? 65e12 : 120e12;
+  double g = std::max(2.0 * M * N * K / rate, 2.0 * es * M * N / 5e12) * 1e6;
+  // the gather kernel's left operand holds the product's row labels and its
+  // right operand its column labels; measured on the CCSD-like product:
+  // +2% when the left operand's unit stride is not along the summation,
+  // +1.7% when the right operand's unit stride is along it
+  if (!ch.c_order.empty()) {
+    const bool a_left = an.spec_a.find(ch.c_order[0]) != std::string::npos;
+    const std::string &left = a_left ? ch.a_order : ch.b_order;
+    const std::string &right = a_left ? ch.b_order : ch.a_order;
+    auto in_k = [&](char l) { return an.spec_c.find(l) == std::string::npos; };
+    if (!left.empty() && !in_k(left.back())) g *= 1.02;
+    if (!right.empty() && in_k(right.back())) g *= 1.017;
+  }
+  return t + g;
+}
+
+static int64_t orders_of(size_t n) {
+  int64_t f = 1;
+  for (size_t k = 2; k <= n; ++k) f *= int64_t(k);
+  return f;
+}
+
+TTGTChoice choose_ttgt(const Analysis &an) {
+  const std::string &c = an.spec_c, &a = an.spec_a, &b = an.spec_b;
+  size_t nm = 0, nn = 0, nk = 0;
+  for (char ch : a) (c.find(ch) != std::string::npos ? nm : nk) += 1;
+  for (char ch : b)
+    if (c.find(ch) != std::string::npos) nn += 1;
+  const char *env = std::getenv("COMET_TTGT_MODEL");
+  const bool weights = env && std::strcmp(env, "weights") == 0;
+  if (weights || nm > 8 || nn > 8 || nk > 8 || orders_of(nm) * orders_of(nn) * orders_of(nk) > kTTGTModelMax) {
+    TTGTChoice ch = choose_ttgt_weights(an);
+    ch.model_us = ttgt_model_us(an, ch);
+    return ch;
+  }
+  return ttgt_candidates(an).front();
+}
+
 std::vector<TTGTChoice> ttgt_candidates(const Analysis &an) {
   const std::string &c = an.spec_c, &a = an.spec_a, &b = an.spec_b;
   std::string Mset, Nset, Kset;
@@ -309,7 +387,7 @@ std::vector<TTGTChoice> ttgt_candidates(const Analysis &an) {
   const bool denseA = dense_rowmajor(exts(a), an.strA), denseB = dense_rowmajor(exts(b), an.strB),
              denseC = dense_rowmajor(exts(c), an.strC);
   std::vector<TTGTChoice> out;
-  std::vector<std::string> seen;
+  std::set<std::string> seen;
   for (const auto &mo : perms(Mset))
     for (const auto &no : perms(Nset))
       for (const auto &ko : perms(Kset))
@@ -325,17 +403,20 @@ std::vector<TTGTChoice> ttgt_candidates(const Analysis &an) {
               ch.b_order = swap ? left : right;
               ch.c_order = rows + cols;
               const std::string key = ch.a_order + "|" + ch.b_order + "|" + ch.c_order;
-              if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
-              seen.push_back(key);
+              if (!seen.insert(key).second) continue;
               ch.a_copy = !(ch.a_order == a && denseA);
               ch.b_copy = !(ch.b_order == b && denseB);
               ch.c_copy = !(ch.c_order == c && denseC);
               ch.cost = (ch.a_copy ? ttgt_cost(a, ch.a_order == a ? std::string(a.size(), '#') : ch.a_order, 1) : 0) +
                         (ch.b_copy ? ttgt_cost(b, ch.b_order == b ? std::string(b.size(), '#') : ch.b_order, 1) : 0) +
                         (ch.c_copy ? ttgt_cost(c, ch.c_order == c ? std::string(c.size(), '#') : ch.c_order, 2) : 0);
+              ch.model_us = ttgt_model_us(an, ch);
               out.push_back(ch);
             }
-  std::stable_sort(out.begin(), out.end(), [](const TTGTChoice &x, const TTGTChoice &y) { return x.cost < y.cost; });
+  std::stable_sort(out.begin(), out.end(), [](const TTGTChoice &x, const TTGTChoice &y) {
+    if (x.model_us != y.model_us) return x.model_us < y.model_us;
+    return x.cost < y.cost;
+  });
   return out;
 }
 
@@ -588,7 +669,7 @@ std::string describe_json(const Analysis &an) {
     o << ",\"ttgt\":{\"swap\":" << (t.swap ? "true" : "false") << ",\"A\":\"" << t.a_order << "\",\"B\":\""
       << t.b_order << "\",\"C\":\"" << t.c_order << "\",\"copyA\":" << (t.a_copy ? "true" : "false")
       << ",\"copyB\":" << (t.b_copy ? "true" : "false") << ",\"copyC\":" << (t.c_copy ? "true" : "false")
-      << ",\"cost\":" << t.cost << "}";
+      << ",\"cost\":" << t.cost << ",\"model_us\":" << t.model_us << "}";
   }
   o << "}";
   return o.str();

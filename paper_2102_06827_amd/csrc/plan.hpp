@@ -54,7 +54,8 @@ struct TTGTChoice {
   std::string b_order;            // label order of the permuted B (B_p)
   std::string c_order;            // label order of the product C_p
   bool a_copy = true, b_copy = true, c_copy = true;   // permute needed at all
-  int64_t cost = 0;
+  int64_t cost = 0;               // the Section 6 position weights of this flattening
+  double model_us = 0.0;          // the MI355X time model of its permutes and product
 };
 
 struct Analysis {
@@ -116,14 +117,26 @@ Status analyze(const char *spec, const int64_t *extents, const int64_t *strides_
                comet_compute_t compute, comet_path_t path, int split_slices, Analysis &an,
                int int8_slices = 6);
 
-// TTGT permutation choice by the cost model (Section 6): every valid
-// flattening of A, B and C, with and without exchanging A and B, costed by
-// the positions of the dimensions it moves; the cheapest wins.
+// TTGT permutation choice (Section 6, "Optimal permutation for TTGT").  By
+// default every valid flattening is ranked by the MI355X time model
+// (ttgt_model_us) and the fastest wins; with COMET_TTGT_MODEL=weights, or
+// when the label groups have more than kTTGTModelMax orders together, the
+// published cost model decides instead: the flattenings that keep each label
+// group in the order of a tensor holding it, costed by the positions of the
+// dimensions they move.
 TTGTChoice choose_ttgt(const Analysis &an);
+constexpr int64_t kTTGTModelMax = 512;
 // Every valid TTGT flattening (each order of the M, N and K label groups, each
 // operand stored K-major or not, with and without exchanging A and B), with
-// its cost-model value, cheapest first.  The autotuner times them.
+// its Section 6 cost and its modelled time, fastest by the model first.  The
+// autotuner times them.
 std::vector<TTGTChoice> ttgt_candidates(const Analysis &an);
+// Modelled time of one flattening on MI355X, in microseconds: each permute
+// launch it needs at its kernel class's measured rate (C's read with beta !=
+// 0 included), plus the product at a rate from its FLOP and output bytes,
+// raised by the measured penalty of the operand layouts it gives the gather
+// kernel.
+double ttgt_model_us(const Analysis &an, const TTGTChoice &ch);
 int64_t ttgt_cost(const std::string &orig, const std::string &perm, int64_t weight);
 
 // Describe the permutation `in_labels` (with strides) -> `out_labels` (with

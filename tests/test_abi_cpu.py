@@ -264,11 +264,13 @@ def test_offset_decomposition_matches_direct_addressing(spec):
         assert len(seen[name]) == int(np.prod([ext[ch] for ch in labs])), name
 
 
-def test_ttgt_cost_model_on_the_worked_example():
+def test_ttgt_cost_model_on_the_worked_example(monkeypatch):
     """The paper's TTGT grouping of its worked example is one of the
-    candidates; the cost model picks one that moves no more (Section 6)."""
+    candidates; the published cost model picks one that moves no more
+    (Section 6)."""
     spec = "abcd=aebf*dfce"
     ext = dict(a=4, b=5, c=6, d=3, e=4, f=5)
+    monkeypatch.setenv("COMET_TTGT_MODEL", "weights")
     d = comet.analyze(spec, ext_list(spec, ext), path="ttgt")
     t = d["ttgt"]
     # cost of the paper's choice under the same weights: A aebf->abef, B dfce->efdc, C abcd->abdc
@@ -278,6 +280,61 @@ def test_ttgt_cost_model_on_the_worked_example():
     assert t["cost"] <= paper
     # every candidate keeps each group contiguous
     assert set(t["A"]) == set("aebf") and set(t["B"]) == set("dfce") and set(t["C"]) == set("abcd")
+
+
+TTGT_SHAPES = [
+    ("abcd=aebf*dfce", dict(a=4, b=5, c=6, d=3, e=4, f=5)),
+    ("abij=acik*bkcj", dict(a=96, b=96, c=96, i=32, j=32, k=32)),
+    ("abcijk=daij*bcdk", dict(a=32, b=32, c=32, d=32, i=16, j=16, k=16)),
+    ("abij=ciak*bkjc", dict(a=24, b=40, c=16, i=8, j=12, k=20)),
+    ("cmia=cdmn*inad", dict(a=64, c=48, d=32, i=40, m=24, n=16)),
+]
+
+
+@pytest.mark.parametrize("spec,ext", TTGT_SHAPES)
+def test_ttgt_time_model_pick(spec, ext, monkeypatch):
+    """The default TTGT choice minimises the MI355X time model over every
+    flattening, a superset of the published model's candidates: its modelled
+    time is never above that of the published pick, and it is a valid
+    flattening (each operand a relabeling of its tensor, the M, N and K
+    groups contiguous, the product rows then columns)."""
+    labs = []
+    for ch in spec.replace("=", "").replace("*", ""):
+        if ch not in labs:
+            labs.append(ch)
+    c, ab = spec.split("=")
+    a, b = ab.split("*")
+    t = comet.analyze(spec, [ext[ch] for ch in labs], path="ttgt")["ttgt"]
+    monkeypatch.setenv("COMET_TTGT_MODEL", "weights")
+    w = comet.analyze(spec, [ext[ch] for ch in labs], path="ttgt")["ttgt"]
+    assert t["model_us"] > 0 and t["model_us"] <= w["model_us"] * (1 + 1e-12)
+    assert sorted(t["A"]) == sorted(a) and sorted(t["B"]) == sorted(b) and sorted(t["C"]) == sorted(c)
+    M = {ch for ch in a if ch in c}
+    N = {ch for ch in b if ch in c}
+    K = {ch for ch in a if ch not in c}
+
+    def contiguous(order, group):
+        pos = [order.index(ch) for ch in group]
+        return max(pos) - min(pos) == len(group) - 1
+
+    for order, groups in ((t["A"], (M, K)), (t["B"], (N, K)), (t["C"], (M, N))):
+        for g in groups:
+            assert contiguous(order, g), (order, g)
+    rows = t["C"][:len(N if t["swap"] else M)]
+    assert set(rows) == (N if t["swap"] else M)
+
+
+def test_ttgt_time_model_keeps_unit_strides_on_the_ccsd_contraction():
+    """abij=acik*bkcj: every tensor can keep its unit-stride label (k in A,
+    j in B and C) with the summation innermost in A and the columns
+    innermost in B, so each permute is a row copy with rows of 32 elements
+    and the gather kernel gets its fastest operand layouts: the model takes
+    that flattening."""
+    spec = "abij=acik*bkcj"
+    ext = dict(a=96, b=96, c=96, i=32, j=32, k=32)
+    t = comet.analyze(spec, [ext[ch] for ch in "abijck"], path="ttgt")["ttgt"]
+    assert t["A"][-1] == "k" and t["B"][-1] == "j" and t["C"][-1] == "j"
+    assert (t["A"], t["B"], t["C"]) == ("aick", "ckbj", "aibj")
 
 
 def test_ttgt_identity_for_plain_gemm():

@@ -30,6 +30,10 @@ def _ext(cm, ia, dn):
     # 4096^2 x 16, C in the product's own order: TTGT only permutes the two
     # small operands
     (torch.float64, ((64, 64), (64, 64), (4, 4)), "ttgt"),
+    # odd extents: not even the TTGT matrices can be read in vectors, but
+    # their GEMM still reads dense rows (3025^3: 1.2 against 4.2 ms gathered)
+    (torch.float64, ((45, 45), (45, 45), (45, 45)), "ttgt"),
+    (torch.float32, ((45, 45), (45, 45), (45, 45)), "ttgt"),
 ])
 def test_auto_ttgt_switch_follows_the_estimate(dtype, sizes, path):
     _check_switch(SPEC, dtype, sizes, path)

@@ -61,7 +61,7 @@ def _labels(spec):
 def test_planner_under_asan_ubsan(tmp_path):
     exe = _build(tmp_path, "planner", ["g++", "-std=c++17", *SAN, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                                        os.path.join(HERE, "planner_driver.cpp"), os.path.join(CSRC, "plan.cpp"),
-                                       os.path.join(CSRC, "chain.cpp")])
+                                       os.path.join(CSRC, "permute_shape.cpp"), os.path.join(CSRC, "chain.cpp")])
     rng = random.Random(2024)
     lines = []
     fixed = ["abij=acik*cbkj", "abij=acik*bkcj", "abcijk=daij*bcdk", "abij=abcd*cdij", "abij=ijcd*cdab",
