@@ -181,8 +181,9 @@ constexpr int kTuneTTGTRetime = 8;      // and the fastest this many timed twice
 // A contraction whose operands only tile 1's element-load kernel can gather
 // goes through TTGT when the time the vector-load GEMM saves exceeds what the
 // permutes cost.  Rates on MI355X ("cmia=cdmn*inad" at 3072^3: element-load
-// gather 2.64 ms in FP64 and 2.62 ms in FP32, the TTGT GEMM alone 1.00 and
-// 0.58 ms); permutes move their bytes at about 4.5 TB/s, and each of the up to
+// gather 2.64 ms in FP64 and 2.62 ms in FP32 when first measured, 3.3 and
+// 4.0 ms on later boxes with the same kernel; the TTGT GEMM alone about 0.9
+// and 0.55 ms; the element-load rate below is the fastest of those); permutes move their bytes at about 4.5 TB/s, and each of the up to
 // three extra launches costs about 5 us on small problems (its launch gap
 // and its ramp).  Measured crossover:
 // 512^3 0.031 (gather) vs 0.034 ms (TTGT) in FP64, 768^3 0.063 vs 0.047;
