@@ -134,7 +134,11 @@ typedef enum {
  *         of the permutes' traffic and launches against the GEMM time they
  *         save says TTGT is faster (from about 768^3 on MI355X).
  *   GETT  operands are gathered through per-label offset tables straight into
- *         on-chip tiles; no transposed copies are made.
+ *         on-chip tiles; no transposed copies are made.  A native product
+ *         with one output row (the vector operand has no free label) streams
+ *         the matrix through a matrix-vector kernel instead, its summation
+ *         cut into slabs whose partial sums are added in a fixed order
+ *         (environment variable COMET_GEMV=0 keeps the tiles).
  *   TTGT  transpose-transpose-GEMM-transpose (Section 2; Section 6 "TTGT"):
  *         A and B are permuted into matrices, multiplied, and the product is
  *         permuted into C.  The flattening (Section 6 "Optimal permutation

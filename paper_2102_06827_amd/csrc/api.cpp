@@ -199,6 +199,7 @@ constexpr double kDenseElemGemmFlops = 45.0e12;
 constexpr double kPermuteBytesPerS = 4.5e12;
 constexpr double kPermuteLaunchS = 5.0e-6;
 constexpr size_t kTTGTMaxWorkspace = size_t(4) << 30;   // no automatic TTGT needing more
+constexpr size_t kGemvMaxWorkspace = size_t(256) << 20;   // partial sums of the matrix-vector kernel
 constexpr double kFused3MaxMNK = 0x1p31;  // above: FP32 BF16x3 through the slicer and slice-pair product
 constexpr int kSkMinSteps = 8;          // fewest BK steps a stream-K share should hold
 constexpr int kSkSmallSteps = 4;        // the same for latency-bound problems (tile 1)
@@ -531,6 +532,42 @@ void apply_schedule(comet_plan_s *p, int cus, int forced_tile = -1) {
   const size_t slot = gett_sk_slot_bytes(sc.tile, an.compute == COMET_COMPUTE_F64 ? 0 : 1);
   // stream-K: two slots per workgroup (its first and last tile); balanced: one
   p->sk_bytes = sc.sk_tiles > 0 ? align256(size_t(sc.even ? 1 : 2) * size_t(sc.sk_blocks) * slot) : 0;
+  // a matrix times a vector: the streaming kernel instead of the tiles,
+  // unless a gather schedule is forced or COMET_GEMV=0
+  an.gemv = an.gemv_split = 0;
+  an.gemv_slab = 0;
+  const char *genv = std::getenv("COMET_GEMV");
+  const bool gather_forced = forced >= 0 || std::getenv("COMET_GETT_SK") || std::getenv("COMET_GETT_PERSIST") ||
+                             std::getenv("COMET_GETT_EVEN");
+  // (the vector has no free label, so C's unit stride lies in the matrix and
+  // the planner's exchange makes the vector the kernel's A operand: M == 1)
+  if (native && !an.empty_out && !an.empty_sum && an.X.empty() && an.m == 1 && !gather_forced &&
+      !(genv && std::strcmp(genv, "0") == 0)) {
+    const int64_t J = an.n;
+    // read the matrix along whichever index group holds its smaller first
+    // step (the fastest dimension of each group leads its table)
+    auto step = [](const std::vector<int64_t> &t) {
+      return t.size() > 1 ? std::llabs(t[1] - t[0]) : INT64_MAX;
+    };
+    const bool kfast = step(an.offBk) < step(an.offBn);
+    int sp = 0;
+    int64_t sl = 0;
+    gemv_shape(J, an.k, kfast, cus, &sp, &sl);
+    // COMET_GEMV_SPLIT=n: about n slabs (at least the summation over kGemvSlab)
+    if (const char *fs = std::getenv("COMET_GEMV_SPLIT"); fs && std::atoi(fs) > 0) {
+      const int64_t want = std::max<int64_t>({int64_t(std::atoi(fs)), (an.k + kGemvSlab - 1) / kGemvSlab, 1});
+      sl = (an.k + std::min<int64_t>(want, an.k) - 1) / std::min<int64_t>(want, an.k);
+      sp = int((an.k + sl - 1) / sl);
+    }
+    const size_t ws = sp > 1 ? align256(size_t(sp) * size_t(J) * sizeof(double)) : 0;
+    if (sp <= 65535 && ws <= kGemvMaxWorkspace) {
+      an.gemv = kfast ? 2 : 1;
+      an.gemv_split = sp;
+      an.gemv_slab = sl;
+      an.shortk = an.sk_tiles = an.sk_blocks = an.even = an.even_whole = an.persist = 0;
+      p->sk_bytes = ws;
+    }
+  }
 }
 
 comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, const int64_t *extents,
@@ -731,6 +768,30 @@ comet_status_t build_plan(std::unique_ptr<comet_plan_s> &out, const char *spec, 
 comet_status_t run_gett(const comet_plan_s *p, double alpha, const void *A, const void *B, double beta, void *C,
                         hipStream_t s, void *ws) {
   const Analysis &an = p->an;
+  if (an.gemv > 0) {
+    // the kernel's A operand (B when exchanged) is the vector: M == 1
+    GemvLaunch v{};
+    v.X = an.swapped ? B : A;
+    v.Y = an.swapped ? A : B;
+    v.C = C;
+    v.offXk = p->t.offAk;
+    v.offX0 = p->t.offAm;
+    v.offYk = p->t.offBk;
+    v.offYj = p->t.offBn;
+    v.offC0 = p->t.offCm;
+    v.offCj = p->t.offCn;
+    v.J = an.n;
+    v.K = an.k;
+    v.split = an.gemv_split;
+    v.slab = an.gemv_slab;
+    v.kfast = an.gemv == 2;
+    v.dtype = an.dtype == COMET_F64 ? 0 : 1;
+    v.alpha = alpha;
+    v.beta = beta;
+    v.ws = ws;
+    HIP_TRY(launch_gemv(v, s), "matrix-vector launch");
+    return COMET_OK;
+  }
   GettLaunch g{};
   g.A = an.swapped ? B : A;
   g.B = an.swapped ? A : B;
@@ -1108,6 +1169,8 @@ comet_status_t autotune_plan(std::unique_ptr<comet_plan_s> &p, const char *spec,
       !std::getenv("COMET_FUSED3"))
     return autotune_split(p.get(), tc);
   if (tc.mode() == 0 || !native || an.empty_out || an.empty_sum) return COMET_OK;
+  // a matrix times a vector streams the matrix once: nothing to time
+  if (an.gemv > 0) return COMET_OK;
   if (std::getenv("COMET_GETT_TILE") || std::getenv("COMET_FORCE_PATH") || std::getenv("COMET_GETT_SK") ||
       std::getenv("COMET_GETT_PERSIST") || std::getenv("COMET_GETT_EVEN"))
     return COMET_OK;

@@ -121,6 +121,30 @@ int batch_blocks_per_cu(int dtype, int mode);
 // C[offCb[b] + offCm[m] + offCn[n]] = beta * C over NB batch entries
 // (offCb == nullptr: NB must be 1 and offCb[0] reads as 0); beta == 0 writes
 // zeros without reading.
+// Matrix-vector product (one free index group empty):
+//   C[offC0[0] + offCj[j]] = alpha * sum_k X[offX0[0] + offXk[k]] * Y[offYj[j] + offYk[k]]
+//                            + beta * C[...]   (C not read when beta == 0),
+// j < J, k < K; all tables on the device.  kfast: Y is contiguous along k
+// (else along j).  The summation is cut into `split` slabs of `slab` indices
+// (split * slab >= K, slab <= kGemvSlab); with split > 1, ws holds split * J
+// doubles of partial sums.  dtype 0: FP64 storage, 1: FP32.
+constexpr int kGemvSlab = 1024;
+struct GemvLaunch {
+  const void *X, *Y;
+  void *C;
+  const int64_t *offXk, *offX0, *offYk, *offYj, *offC0, *offCj;
+  int64_t J, K;
+  int64_t slab;
+  int split;
+  int kfast;
+  int dtype;
+  double alpha, beta;
+  void *ws;
+};
+hipError_t launch_gemv(const GemvLaunch &a, hipStream_t s);
+// The slabs for J outputs over a summation of K on `cus` compute units.
+void gemv_shape(int64_t J, int64_t K, bool kfast, int cus, int *split, int64_t *slab);
+
 hipError_t launch_scale(void *C, int dtype, const int64_t *offCm, const int64_t *offCn, int64_t M, int64_t N,
                         double beta, hipStream_t s, const int64_t *offCb = nullptr, int64_t NB = 1);
 

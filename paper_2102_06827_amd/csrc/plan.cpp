@@ -661,7 +661,7 @@ std::string describe_json(const Analysis &an) {
   o << ",\"layoutB\":\"" << (an.layoutB == LAYOUT_K_CONTIG ? "k" : "n") << "\"";
   o << ",\"tables32\":" << (an.tables32 ? "true" : "false");
   o << ",\"tile\":" << an.tile << ",\"sk_tiles\":" << an.sk_tiles << ",\"sk_blocks\":" << an.sk_blocks << ",\"even\":" << an.even << ",\"even_whole\":" << an.even_whole << ",\"persist\":" << an.persist
-    << ",\"shortk\":" << an.shortk;
+    << ",\"shortk\":" << an.shortk << ",\"gemv\":" << an.gemv << ",\"gemv_split\":" << an.gemv_split;
   o << ",\"split_slices\":" << an.split_slices;
   o << ",\"empty_out\":" << (an.empty_out ? "true" : "false") << ",\"empty_sum\":" << (an.empty_sum ? "true" : "false");
   if (an.path == COMET_PATH_TTGT) {

@@ -102,6 +102,12 @@ struct Analysis {
   // > 0: the short-summation kernel (stores overlapped with the next tile's
   // products) with this many workgroups
   int shortk = 0;
+  // matrix-vector products (M == 1): 1 the matrix is read along its free
+  // index, 2 along the summation; the summation cut into gemv_split
+  // slabs of gemv_slab indices
+  int gemv = 0;
+  int gemv_split = 0;
+  int64_t gemv_slab = 0;
   int split_slices = 5;
 
   TTGTChoice ttgt;

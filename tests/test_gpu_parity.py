@@ -729,13 +729,17 @@ def test_stream_k_element_load_variants(spec, ext, dtype, sk, monkeypatch):
     check(spec, ext, dtype, seed=961, alpha=-0.5, beta=0.25)
 
 
-def test_gemv_like_contraction_is_split():
-    """A contraction with one output row and a long summation whose operands
-    cannot both read vectors is spread over the CUs by stream-K."""
+def test_gemv_like_contraction_is_split(monkeypatch):
+    """A contraction with one output row and a long summation: the
+    matrix-vector kernel by default; with it switched off (COMET_GEMV=0) the
+    gather path spreads the summation over the CUs by stream-K."""
     A = torch.zeros((96, 32), dtype=torch.float64, device="cuda")
     B = torch.zeros((32, 32, 96, 96), dtype=torch.float64, device="cuda")
     d = comet.Plan("ia=dn*inad", A, B).describe()
-    assert d["tile"] == 1 and d["sk_tiles"] > 0 and d["sk_blocks"] > d["sk_tiles"]
+    assert d["gemv"] == 2 and d["gemv_split"] > 1
+    monkeypatch.setenv("COMET_GEMV", "0")
+    d = comet.Plan("ia=dn*inad", A, B).describe()
+    assert d["gemv"] == 0 and d["tile"] == 1 and d["sk_tiles"] > 0 and d["sk_blocks"] > d["sk_tiles"]
 
 
 def test_large_element_load_problem_goes_through_ttgt():
