@@ -9,9 +9,9 @@
 //   j-fast:  Y is contiguous along j.  A wave's 64 lanes take 64 consecutive
 //            outputs and walk the slab's summation indices together; the
 //            block's four waves take every fourth index.
-//   k-fast:  Y is contiguous along k.  A wave's lanes walk one output's
-//            summation indices, 64 apart, and add up with a fixed butterfly;
-//            the four waves take four outputs.
+//   k-fast:  Y is contiguous along k.  A wave's lanes walk the summation
+//            indices, 64 apart, of four outputs at once and add up each with
+//            a fixed butterfly; the four waves take sixteen outputs.
 //
 // The summation is cut into `split` slabs of at most kGemvSlab indices, whose
 // x values and Y offsets a block stages in LDS.  With one slab the block
@@ -28,10 +28,27 @@ namespace {
 
 constexpr int kGemvThreads = 256;
 
+constexpr int kJW = 4;   // outputs per wave when reading along the summation
+
+// one output's sum over a slab: C itself with a single slab, else the slab's
+// partial sum
+template <typename T>
+__device__ __forceinline__ void emit(const GemvLaunch &a, int64_t j, double sum) {
+  if (a.split == 1) {
+    T *__restrict__ C = static_cast<T *>(a.C);
+    const int64_t c = a.offC0[0] + a.offCj[j];
+    double v = a.alpha * sum;
+    if (a.beta != 0.0) v += a.beta * double(C[c]);
+    C[c] = T(v);
+  } else {
+    static_cast<double *>(a.ws)[int64_t(blockIdx.y) * a.J + j] = sum;
+  }
+}
+
 template <typename T, bool KFAST>
 __global__ __launch_bounds__(kGemvThreads) void gemv_kernel(GemvLaunch a) {
-  constexpr int BJ = KFAST ? 4 : 64;    // outputs per block
-  constexpr int BK = KFAST ? 64 : 4;    // threads sharing an output
+  constexpr int BJ = KFAST ? 4 * kJW : 64;   // outputs per block
+  constexpr int BK = KFAST ? 64 : 4;         // threads sharing an output
   __shared__ double xs[kGemvSlab];
   __shared__ int64_t yk[kGemvSlab];
   __shared__ double red[kGemvThreads];
@@ -46,12 +63,53 @@ __global__ __launch_bounds__(kGemvThreads) void gemv_kernel(GemvLaunch a) {
     yk[i] = a.offYk[k0 + i];
   }
   __syncthreads();
-  const int tj = KFAST ? wave : lane, tk = KFAST ? lane : wave;
-  const int64_t j = int64_t(blockIdx.x) * BJ + tj;
+  if constexpr (KFAST) {
+    // each wave: kJW outputs, their loads interleaved, then one butterfly each
+    const int64_t j0 = int64_t(blockIdx.x) * BJ + wave * kJW;
+    const T *__restrict__ Yj[kJW];
+    double acc[kJW];
+#pragma unroll
+    for (int u = 0; u < kJW; ++u) {
+      acc[u] = 0.0;
+      Yj[u] = Y + a.offYj[j0 + u < a.J ? j0 + u : a.J - 1];   // a past-the-end output re-reads the last one
+    }
+    int i = lane;
+    for (; i + BK < n; i += 2 * BK) {
+      double y[2][kJW];
+#pragma unroll
+      for (int u = 0; u < kJW; ++u) {
+        y[0][u] = double(Yj[u][yk[i]]);
+        y[1][u] = double(Yj[u][yk[i + BK]]);
+      }
+#pragma unroll
+      for (int u = 0; u < kJW; ++u) {
+        acc[u] += xs[i] * y[0][u];
+        acc[u] += xs[i + BK] * y[1][u];
+      }
+    }
+    if (i < n) {
+#pragma unroll
+      for (int u = 0; u < kJW; ++u) acc[u] += xs[i] * double(Yj[u][yk[i]]);
+    }
+    // butterfly over the wave's 64 lanes: every lane ends with the same sums
+#pragma unroll
+    for (int u = 0; u < kJW; ++u)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, 64);
+    if (lane < kJW && j0 + lane < a.J) {
+      double sum = acc[0];
+#pragma unroll
+      for (int u = 1; u < kJW; ++u)
+        if (lane == u) sum = acc[u];
+      emit<T>(a, j0 + lane, sum);
+    }
+    return;
+  }
+  const int64_t j = int64_t(blockIdx.x) * BJ + lane;
   double acc = 0.0;
   if (j < a.J) {
     const T *__restrict__ Yj = Y + a.offYj[j];
-    int i = tk;
+    int i = wave;
     // four independent loads in flight per thread
     for (; i + 3 * BK < n; i += 4 * BK) {
       const double y0 = double(Yj[yk[i]]), y1 = double(Yj[yk[i + BK]]);
@@ -63,34 +121,13 @@ __global__ __launch_bounds__(kGemvThreads) void gemv_kernel(GemvLaunch a) {
     }
     for (; i < n; i += BK) acc += xs[i] * double(Yj[yk[i]]);
   }
-  double sum;
-  bool owner;
-  if constexpr (KFAST) {
-    // butterfly over the wave's 64 lanes: every lane ends with the same sum
+  red[tid] = acc;
+  __syncthreads();
+  if (wave != 0 || j >= a.J) return;
+  double sum = 0.0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    sum = acc;
-    owner = lane == 0;
-  } else {
-    red[tid] = acc;
-    __syncthreads();
-    sum = 0.0;
-    if (wave == 0) {
-#pragma unroll
-      for (int w = 0; w < 4; ++w) sum += red[w * 64 + lane];
-    }
-    owner = wave == 0;
-  }
-  if (!owner || j >= a.J) return;
-  if (a.split == 1) {
-    T *__restrict__ C = static_cast<T *>(a.C);
-    const int64_t c = a.offC0[0] + a.offCj[j];
-    double v = a.alpha * sum;
-    if (a.beta != 0.0) v += a.beta * double(C[c]);
-    C[c] = T(v);
-  } else {
-    static_cast<double *>(a.ws)[int64_t(blockIdx.y) * a.J + j] = sum;
-  }
+  for (int w = 0; w < 4; ++w) sum += red[w * 64 + lane];
+  emit<T>(a, j, sum);
 }
 
 constexpr int kFixThreads = 64;
@@ -121,7 +158,7 @@ __global__ __launch_bounds__(kFixThreads) void gemv_fixup_kernel(GemvLaunch a) {
 
 template <typename T>
 hipError_t launch_gemv_t(const GemvLaunch &a, hipStream_t s) {
-  const int bj = a.kfast ? 4 : 64;
+  const int bj = a.kfast ? 4 * kJW : 64;
   const int64_t gx = (a.J + bj - 1) / bj;
   if (gx > INT32_MAX || a.split < 1 || a.split > 65535 || a.slab < 1 || a.slab > kGemvSlab ||
       int64_t(a.split) * a.slab < a.K || (a.split > 1 && !a.ws))
@@ -142,7 +179,7 @@ hipError_t launch_gemv_t(const GemvLaunch &a, hipStream_t s) {
 }  // namespace
 
 void gemv_shape(int64_t J, int64_t K, bool kfast, int cus, int *split, int64_t *slab) {
-  const int64_t bj = kfast ? 4 : 64;
+  const int64_t bj = kfast ? 4 * kJW : 64;
   const int64_t gx = std::max<int64_t>(1, (J + bj - 1) / bj);
   // about sixteen blocks per CU, but slabs of at least 256 indices (the
   // fix-up reads every slab's partial sums), and at most kGemvSlab.
