@@ -138,7 +138,8 @@ typedef enum {
  *         with one output row (the vector operand has no free label) streams
  *         the matrix through a matrix-vector kernel instead, its summation
  *         cut into slabs whose partial sums are added in a fixed order
- *         (environment variable COMET_GEMV=0 keeps the tiles).
+ *         (environment variable COMET_GEMV=0 keeps the tiles;
+ *         COMET_GEMV_SPLIT=n asks for about n slabs).
  *   TTGT  transpose-transpose-GEMM-transpose (Section 2; Section 6 "TTGT"):
  *         A and B are permuted into matrices, multiplied, and the product is
  *         permuted into C.  The flattening (Section 6 "Optimal permutation
@@ -241,9 +242,13 @@ comet_status_t comet_plan_execute_noalloc(comet_plan_t plan, double alpha, const
  * operand layouts and contiguous runs, tile shape, stream-K split
  * (sk_tiles, sk_blocks; with even = 1 the balanced schedule: the first
  * even_whole tiles whole, then the sk_tiles leftover tiles cut into sk_blocks
- * pieces), persistent workgroups, resident workgroups per CU,
- * the split tile and whether FP32 BF16x3 runs fused, TTGT permutations and
- * cost.  COMET_ERR_WORKSPACE if buf is too small (the text is truncated). */
+ * pieces), persistent workgroups, resident workgroups per CU, the
+ * short-summation kernel's workgroups (shortk), the matrix-vector kernel
+ * (gemv: 1 reads the matrix along the output, 2 along the summation; 0 not
+ * used) and its summation slabs (gemv_split), the split tile and whether
+ * FP32 BF16x3 runs fused, TTGT permutations with their Section 6 cost and
+ * modelled time (model_us).  COMET_ERR_WORKSPACE if buf is too small (the
+ * text is truncated). */
 comet_status_t comet_plan_describe(comet_plan_t plan, char *buf, size_t len);
 
 /*
